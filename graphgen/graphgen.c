@@ -1,0 +1,413 @@
+/*
+ * graphgen.c -- seeded synthetic graph generators (GNM, RMAT, 2D grid, 2D RGG).
+ *
+ * This module produces input edge lists only.  It holds none of the minimum
+ * spanning forest arithmetic: both the GPU library and the CPU oracle consume
+ * the arrays it writes, so a parity check never depends on how an input was
+ * drawn.  Every random number comes from one counter-based generator:
+ *
+ *   mix(z)        the SplitMix64 output function (Steele, Lea & Flood,
+ *                 "Fast splittable pseudorandom number generators", OOPSLA 2014)
+ *   base(s, tag)  = mix(mix(s) ^ tag)           one independent stream per use
+ *   draw(b, k)    = mix(b + (k + 1) * GAMMA)    the k-th value of stream b
+ *
+ * so any value can be recomputed from (seed, tag, k) alone, in any order and
+ * on any number of threads.  graphgen/ref.py restates the same definitions in
+ * numpy; the tests require both to agree bit for bit.
+ *
+ * Families follow the paper's experimental section (Instances and
+ * Methodology): GNM (Erdos-Renyi with a fixed edge count), RMAT with the
+ * Graph500 default probabilities, 2D grids and 2D random geometric graphs.
+ * Output format: undirected edges, each listed once, as SoA arrays
+ * int32 u[m], int32 v[m], uint32 w[m]; the edge id is the array index.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#define GAMMA 0x9E3779B97F4A7C15ULL
+
+enum { TAG_GNM = 1, TAG_RMAT = 2, TAG_PERM = 3, TAG_RMAT_W = 4, TAG_GRID_KEEP = 5,
+       TAG_GRID_W = 6, TAG_RGG = 7 };
+
+static inline uint64_t mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+static inline uint64_t base(uint64_t seed, uint64_t tag) { return mix(mix(seed) ^ tag); }
+static inline uint64_t draw(uint64_t b, uint64_t k) { return mix(b + (k + 1) * GAMMA); }
+
+/* floor(r * n / 2^64) for n < 2^32, via two 32x32 products (exactly what ref.py does). */
+static inline uint64_t below(uint64_t r, uint64_t n) {
+    uint64_t hi = r >> 32, lo = r & 0xffffffffULL;
+    return (hi * n + ((lo * n) >> 32)) >> 32;
+}
+
+/* ------------------------------------------------------------------ threads */
+
+typedef void (*range_fn)(void* ctx, int64_t lo, int64_t hi);
+typedef struct { range_fn fn; void* ctx; int64_t lo, hi; } job_t;
+
+static void* run_job(void* p) {
+    job_t* j = (job_t*)p;
+    if (j->lo < j->hi) j->fn(j->ctx, j->lo, j->hi);
+    return NULL;
+}
+
+int gg_threads(void) {
+    const char* s = getenv("GRAPHGEN_THREADS");
+    int t = s ? atoi(s) : (int)sysconf(_SC_NPROCESSORS_ONLN);
+    if (t < 1) t = 1;
+    if (t > 64) t = 64;
+    return t;
+}
+
+static void parallel_for(int64_t n, range_fn fn, void* ctx) {
+    int t = gg_threads();
+    if (n < 65536 || t == 1) { if (n > 0) fn(ctx, 0, n); return; }
+    pthread_t th[64];
+    job_t jobs[64];
+    int64_t chunk = (n + t - 1) / t;
+    for (int i = 0; i < t; ++i) {
+        jobs[i].fn = fn; jobs[i].ctx = ctx;
+        jobs[i].lo = i * chunk < n ? i * chunk : n;
+        jobs[i].hi = (i + 1) * chunk < n ? (i + 1) * chunk : n;
+        pthread_create(&th[i], NULL, run_job, &jobs[i]);
+    }
+    for (int i = 0; i < t; ++i) pthread_join(th[i], NULL);
+}
+
+/* --------------------------------------------------------------------- GNM */
+/* Edge i: u uniform on [0,n); v uniform on [0,n) minus {u}, as
+ * v = (u + 1 + U[0,n-1)) mod n; w uniform on [wlo, whi].  Draws 3i, 3i+1, 3i+2. */
+
+typedef struct { int64_t n; uint32_t wlo, whi; uint64_t b; int32_t *u, *v; uint32_t* w; } gnm_ctx;
+
+static void gnm_range(void* p, int64_t lo, int64_t hi) {
+    gnm_ctx* c = (gnm_ctx*)p;
+    uint64_t span = (uint64_t)c->whi - c->wlo + 1;
+    for (int64_t i = lo; i < hi; ++i) {
+        uint64_t a = below(draw(c->b, 3 * (uint64_t)i), (uint64_t)c->n);
+        uint64_t d = below(draw(c->b, 3 * (uint64_t)i + 1), (uint64_t)c->n - 1);
+        c->u[i] = (int32_t)a;
+        c->v[i] = (int32_t)((a + 1 + d) % (uint64_t)c->n);
+        c->w[i] = c->wlo + (uint32_t)below(draw(c->b, 3 * (uint64_t)i + 2), span);
+    }
+}
+
+int gg_gnm(int64_t n, int64_t m, uint32_t wlo, uint32_t whi, uint64_t seed,
+           int32_t* u, int32_t* v, uint32_t* w) {
+    if (n < 2 || n > 0x7fffffffLL || m < 0 || wlo > whi) return -1;
+    gnm_ctx c = { n, wlo, whi, base(seed, TAG_GNM), u, v, w };
+    parallel_for(m, gnm_range, &c);
+    return 0;
+}
+
+/* -------------------------------------------------------------------- RMAT */
+/* Per level l (most significant bit first) one 32-bit draw x picks the
+ * quadrant: x < ta -> (0,0), x < tab -> (0,1), x < tabc -> (1,0), else (1,1),
+ * with ta = floor(a 2^32), tab = floor((a+b) 2^32), tabc = floor((a+b+c) 2^32).
+ * Level l uses the high (l even) or low (l odd) half of 64-bit draw l/2 of edge
+ * i, i.e. draw index i*ceil(scale/2) + l/2.  The weight is draw i of its own
+ * stream.  Vertex ids are then mapped through a seeded 4-round balanced
+ * Feistel bijection on [0, 2^scale) (cycle walking when scale is odd). */
+
+typedef struct {
+    int scale, h, permute;
+    uint32_t ta, tab, tabc, wlo, whi;
+    uint64_t b, bw, keys[4];
+    int32_t *u, *v; uint32_t* w;
+} rmat_ctx;
+
+static inline uint64_t feistel(const rmat_ctx* c, uint64_t x) {
+    uint64_t mask = (1ULL << c->h) - 1, lim = 1ULL << c->scale;
+    do {
+        uint64_t L = x >> c->h, R = x & mask;
+        for (int k = 0; k < 4; ++k) {
+            uint64_t F = mix(R ^ c->keys[k]) & mask;
+            uint64_t nL = R, nR = L ^ F;
+            L = nL; R = nR;
+        }
+        x = (L << c->h) | R;
+    } while (x >= lim);
+    return x;
+}
+
+static void rmat_range(void* p, int64_t lo, int64_t hi) {
+    rmat_ctx* c = (rmat_ctx*)p;
+    uint64_t per = (uint64_t)(c->scale + 1) / 2;
+    uint64_t span = (uint64_t)c->whi - c->wlo + 1;
+    for (int64_t i = lo; i < hi; ++i) {
+        uint64_t a = 0, b = 0, r = 0;
+        for (int l = 0; l < c->scale; ++l) {
+            if ((l & 1) == 0) r = draw(c->b, (uint64_t)i * per + (uint64_t)(l >> 1));
+            uint32_t x = (l & 1) ? (uint32_t)(r & 0xffffffffULL) : (uint32_t)(r >> 32);
+            uint64_t ub, vb;
+            if (x < c->ta) { ub = 0; vb = 0; }
+            else if (x < c->tab) { ub = 0; vb = 1; }
+            else if (x < c->tabc) { ub = 1; vb = 0; }
+            else { ub = 1; vb = 1; }
+            a = (a << 1) | ub;
+            b = (b << 1) | vb;
+        }
+        if (c->permute) { a = feistel(c, a); b = feistel(c, b); }
+        c->u[i] = (int32_t)a;
+        c->v[i] = (int32_t)b;
+        c->w[i] = c->wlo + (uint32_t)below(draw(c->bw, (uint64_t)i), span);
+    }
+}
+
+int gg_rmat(int scale, int64_t m, double a, double b, double c, uint32_t wlo, uint32_t whi,
+            int permute, uint64_t seed, int32_t* u, int32_t* v, uint32_t* w) {
+    if (scale < 1 || scale > 31 || m < 0 || wlo > whi) return -1;
+    if (a < 0 || b < 0 || c < 0 || a + b + c > 1.0) return -1;
+    rmat_ctx x;
+    memset(&x, 0, sizeof x);
+    x.scale = scale;
+    x.h = (scale + 1) / 2;
+    x.permute = permute;
+    x.ta = (uint32_t)floor(a * 4294967296.0);
+    x.tab = (uint32_t)floor((a + b) * 4294967296.0);
+    x.tabc = (uint32_t)fmin(floor((a + b + c) * 4294967296.0), 4294967295.0);
+    x.wlo = wlo; x.whi = whi;
+    x.b = base(seed, TAG_RMAT);
+    x.bw = base(seed, TAG_RMAT_W);
+    uint64_t bp = base(seed, TAG_PERM);
+    for (int k = 0; k < 4; ++k) x.keys[k] = draw(bp, (uint64_t)k);
+    x.u = u; x.v = v; x.w = w;
+    parallel_for(m, rmat_range, &x);
+    return 0;
+}
+
+/* Exposed so that tests can check the bijection directly. */
+int gg_rmat_permute(int scale, uint64_t seed, const int64_t* in, int64_t k, int64_t* out) {
+    rmat_ctx x;
+    memset(&x, 0, sizeof x);
+    x.scale = scale; x.h = (scale + 1) / 2;
+    uint64_t bp = base(seed, TAG_PERM);
+    for (int j = 0; j < 4; ++j) x.keys[j] = draw(bp, (uint64_t)j);
+    for (int64_t i = 0; i < k; ++i) out[i] = (int64_t)feistel(&x, (uint64_t)in[i]);
+    return 0;
+}
+
+/* -------------------------------------------------------------------- grid */
+/* rows x cols lattice, vertex id = i*cols + j.  Candidates are enumerated per
+ * vertex in id order, right neighbour first, then the one below; candidate c
+ * is kept iff the high half of draw c is below floor(keep 2^32).  The edge id
+ * is the rank among kept candidates.  wmode 0: w = wlo for every edge;
+ * wmode 1: w uniform on [wlo, whi] from draw c of the weight stream. */
+
+typedef struct { int32_t *u, *v; uint32_t* w; int64_t m; } edge_buf;
+
+typedef struct {
+    int64_t rows, cols; uint32_t thr; int wmode; uint32_t wlo, whi;
+    uint64_t bk, bw; int64_t* row_count; int64_t* row_start; edge_buf* out;
+} grid_ctx;
+
+static inline int64_t grid_cand0(const grid_ctx* g, int64_t i) { return i * (2 * g->cols - 1); }
+
+static void grid_count_range(void* p, int64_t lo, int64_t hi) {
+    grid_ctx* g = (grid_ctx*)p;
+    for (int64_t i = lo; i < hi; ++i) {
+        int64_t c = grid_cand0(g, i), cnt = 0;
+        for (int64_t j = 0; j < g->cols; ++j) {
+            if (j + 1 < g->cols) { cnt += (draw(g->bk, (uint64_t)c) >> 32) < g->thr; ++c; }
+            if (i + 1 < g->rows) { cnt += (draw(g->bk, (uint64_t)c) >> 32) < g->thr; ++c; }
+        }
+        g->row_count[i] = cnt;
+    }
+}
+
+static void grid_fill_range(void* p, int64_t lo, int64_t hi) {
+    grid_ctx* g = (grid_ctx*)p;
+    uint64_t span = (uint64_t)g->whi - g->wlo + 1;
+    for (int64_t i = lo; i < hi; ++i) {
+        int64_t c = grid_cand0(g, i), e = g->row_start[i];
+        for (int64_t j = 0; j < g->cols; ++j) {
+            int64_t x = i * g->cols + j;
+            for (int dir = 0; dir < 2; ++dir) {
+                int ok = dir == 0 ? (j + 1 < g->cols) : (i + 1 < g->rows);
+                if (!ok) continue;
+                if ((draw(g->bk, (uint64_t)c) >> 32) < g->thr) {
+                    g->out->u[e] = (int32_t)x;
+                    g->out->v[e] = (int32_t)(dir == 0 ? x + 1 : x + g->cols);
+                    g->out->w[e] = g->wmode == 0 ? g->wlo
+                                 : g->wlo + (uint32_t)below(draw(g->bw, (uint64_t)c), span);
+                    ++e;
+                }
+                ++c;
+            }
+        }
+    }
+}
+
+static void* grid_build(int64_t rows, int64_t cols, double keep, int wmode, uint32_t wlo,
+                        uint32_t whi, uint64_t seed, int64_t* m_out) {
+    if (rows < 1 || cols < 1 || rows * cols > 0x7fffffffLL || keep < 0 || keep > 1 || wlo > whi)
+        return NULL;
+    grid_ctx g;
+    memset(&g, 0, sizeof g);
+    g.rows = rows; g.cols = cols;
+    g.thr = keep >= 1.0 ? 0xffffffffU : (uint32_t)floor(keep * 4294967296.0);
+    g.wmode = wmode; g.wlo = wlo; g.whi = whi;
+    g.bk = base(seed, TAG_GRID_KEEP);
+    g.bw = base(seed, TAG_GRID_W);
+    g.row_count = (int64_t*)calloc((size_t)rows, sizeof(int64_t));
+    g.row_start = (int64_t*)calloc((size_t)rows + 1, sizeof(int64_t));
+    parallel_for(rows, grid_count_range, &g);
+    for (int64_t i = 0; i < rows; ++i) g.row_start[i + 1] = g.row_start[i] + g.row_count[i];
+    int64_t m = g.row_start[rows];
+    edge_buf* out = (edge_buf*)calloc(1, sizeof(edge_buf));
+    out->m = m;
+    out->u = (int32_t*)malloc((size_t)(m ? m : 1) * 4);
+    out->v = (int32_t*)malloc((size_t)(m ? m : 1) * 4);
+    out->w = (uint32_t*)malloc((size_t)(m ? m : 1) * 4);
+    g.out = out;
+    parallel_for(rows, grid_fill_range, &g);
+    free(g.row_count);
+    free(g.row_start);
+    *m_out = m;
+    return out;
+}
+
+/* --------------------------------------------------------------------- RGG */
+/* n points uniform in [0,1)^2 (x from draw 2t, y from draw 2t+1, 53-bit
+ * mantissa), bucketed into a G x G cell grid, G = floor(1/r) so a cell side is
+ * at least r.  Vertex ids follow cell-major order (cell index cy*G + cx, then
+ * draw order).  Edge {i,j} iff squared distance < r^2; edges are listed in
+ * lexicographic (i, j) order with i < j, w = llround(wscale * distance). */
+
+typedef struct {
+    int64_t n, G; double r, r2, wscale;
+    double *x, *y; int64_t* cell_start; int64_t* cnt; int64_t* start; edge_buf* out;
+} rgg_ctx;
+
+static inline int64_t rgg_cell_of(const rgg_ctx* g, double x, double y) {
+    int64_t cx = (int64_t)(x * (double)g->G), cy = (int64_t)(y * (double)g->G);
+    if (cx >= g->G) cx = g->G - 1;
+    if (cy >= g->G) cy = g->G - 1;
+    return cy * g->G + cx;
+}
+
+static void rgg_scan_vertex(rgg_ctx* g, int64_t i, int fill) {
+    double xi = g->x[i], yi = g->y[i];
+    int64_t ci = rgg_cell_of(g, xi, yi), cx = ci % g->G, cy = ci / g->G, k = 0;
+    int64_t e = fill ? g->start[i] : 0;
+    for (int64_t dy = -1; dy <= 1; ++dy) {
+        int64_t yy = cy + dy;
+        if (yy < 0 || yy >= g->G) continue;
+        for (int64_t dx = -1; dx <= 1; ++dx) {
+            int64_t xx = cx + dx;
+            if (xx < 0 || xx >= g->G) continue;
+            int64_t c = yy * g->G + xx;
+            for (int64_t j = g->cell_start[c]; j < g->cell_start[c + 1]; ++j) {
+                if (j <= i) continue;
+                double ddx = g->x[j] - xi, ddy = g->y[j] - yi, d2 = ddx * ddx + ddy * ddy;
+                if (d2 < g->r2) {
+                    if (fill) {
+                        g->out->u[e] = (int32_t)i;
+                        g->out->v[e] = (int32_t)j;
+                        g->out->w[e] = (uint32_t)llround(g->wscale * sqrt(d2));
+                        ++e;
+                    } else {
+                        ++k;
+                    }
+                }
+            }
+        }
+    }
+    if (!fill) g->cnt[i] = k;
+}
+
+static void rgg_count_range(void* p, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) rgg_scan_vertex((rgg_ctx*)p, i, 0);
+}
+static void rgg_fill_range(void* p, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) rgg_scan_vertex((rgg_ctx*)p, i, 1);
+}
+
+typedef struct { uint64_t b; double *x, *y; } pts_ctx;
+static void pts_range(void* p, int64_t lo, int64_t hi) {
+    pts_ctx* c = (pts_ctx*)p;
+    for (int64_t t = lo; t < hi; ++t) {
+        c->x[t] = (double)(draw(c->b, 2 * (uint64_t)t) >> 11) * 0x1.0p-53;
+        c->y[t] = (double)(draw(c->b, 2 * (uint64_t)t + 1) >> 11) * 0x1.0p-53;
+    }
+}
+
+static void* rgg_build(int64_t n, double r, double wscale, uint64_t seed, int64_t* m_out) {
+    if (n < 1 || n > 0x7fffffffLL || !(r > 0) || r > 1) return NULL;
+    rgg_ctx g;
+    memset(&g, 0, sizeof g);
+    g.n = n; g.r = r; g.r2 = r * r; g.wscale = wscale;
+    g.G = (int64_t)floor(1.0 / r);
+    if (g.G < 1) g.G = 1;
+    if (g.G > 1 << 20) g.G = 1 << 20;
+    double* px = (double*)malloc((size_t)n * 8);
+    double* py = (double*)malloc((size_t)n * 8);
+    pts_ctx pc = { base(seed, TAG_RGG), px, py };
+    parallel_for(n, pts_range, &pc);
+    int64_t ncell = g.G * g.G;
+    g.cell_start = (int64_t*)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t* cellof = (int64_t*)malloc((size_t)n * 8);
+    for (int64_t t = 0; t < n; ++t) {
+        cellof[t] = rgg_cell_of(&g, px[t], py[t]);
+        g.cell_start[cellof[t] + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) g.cell_start[c + 1] += g.cell_start[c];
+    int64_t* fillp = (int64_t*)malloc((size_t)ncell * 8);
+    memcpy(fillp, g.cell_start, (size_t)ncell * 8);
+    g.x = (double*)malloc((size_t)n * 8);
+    g.y = (double*)malloc((size_t)n * 8);
+    for (int64_t t = 0; t < n; ++t) {          /* stable counting sort by cell */
+        int64_t id = fillp[cellof[t]]++;
+        g.x[id] = px[t];
+        g.y[id] = py[t];
+    }
+    free(fillp); free(cellof); free(px); free(py);
+    g.cnt = (int64_t*)malloc((size_t)n * 8);
+    g.start = (int64_t*)malloc((size_t)(n + 1) * 8);
+    parallel_for(n, rgg_count_range, &g);
+    g.start[0] = 0;
+    for (int64_t i = 0; i < n; ++i) g.start[i + 1] = g.start[i] + g.cnt[i];
+    int64_t m = g.start[n];
+    edge_buf* out = (edge_buf*)calloc(1, sizeof(edge_buf));
+    out->m = m;
+    out->u = (int32_t*)malloc((size_t)(m ? m : 1) * 4);
+    out->v = (int32_t*)malloc((size_t)(m ? m : 1) * 4);
+    out->w = (uint32_t*)malloc((size_t)(m ? m : 1) * 4);
+    g.out = out;
+    parallel_for(n, rgg_fill_range, &g);
+    free(g.x); free(g.y); free(g.cnt); free(g.start); free(g.cell_start);
+    *m_out = m;
+    return out;
+}
+
+/* ----------------------------------------------- variable-size result handles */
+
+void* gg_grid_build(int64_t rows, int64_t cols, double keep, int wmode, uint32_t wlo,
+                    uint32_t whi, uint64_t seed, int64_t* m_out) {
+    return grid_build(rows, cols, keep, wmode, wlo, whi, seed, m_out);
+}
+
+void* gg_rgg2d_build(int64_t n, double r, double wscale, uint64_t seed, int64_t* m_out) {
+    return rgg_build(n, r, wscale, seed, m_out);
+}
+
+/* Copies a built edge list into caller arrays of length m and releases it. */
+int gg_take(void* h, int32_t* u, int32_t* v, uint32_t* w) {
+    edge_buf* b = (edge_buf*)h;
+    if (!b) return -1;
+    memcpy(u, b->u, (size_t)b->m * 4);
+    memcpy(v, b->v, (size_t)b->m * 4);
+    memcpy(w, b->w, (size_t)b->m * 4);
+    free(b->u); free(b->v); free(b->w); free(b);
+    return 0;
+}
+
+/* Raw stream access for the bit-exactness tests of ref.py. */
+uint64_t gg_draw(uint64_t seed, uint64_t tag, uint64_t k) { return draw(base(seed, tag), k); }
