@@ -1,0 +1,146 @@
+/*
+ * msf.h -- C ABI of the MI355X (gfx950) minimum spanning forest library.
+ *
+ * Computes the minimum spanning forest (MSF) of an undirected weighted
+ * multigraph: a minimum spanning tree of every connected component (paper
+ * Sec. II-B).  Ties between equal weights are broken by edge id, i.e. edge e
+ * precedes edge f iff (w_e, e) < (w_f, f); under this strict order the MSF is
+ * unique (Sec. II-C), so results are exact and reproducible bit for bit.
+ *
+ * Two algorithms are provided:
+ *   MSF_ALGO_BORUVKA  Borůvka rounds (Sec. II-C, Alg. 1's round body):
+ *                     lightest incident edge per vertex, 2-cycle tie break,
+ *                     pointer jumping to stars, contraction to dense labels,
+ *                     relabelling with self-loop removal.
+ *   MSF_ALGO_FILTER   Filter-Borůvka (Sec. V, Alg. 2): sampled pivot, split
+ *                     into light and heavy edges, recursion on the light ones,
+ *                     removal of heavy edges inside a light component using the
+ *                     representative array P, recursion on the survivors.
+ *
+ * Conventions shared by every entry point
+ *   - Vertex ids are 0-based in [0, n) (the paper numbers them 1..|V|).
+ *   - Edge e is (u[e], v[e], w[e]), undirected, listed once; its id is e.
+ *     Self-loops and parallel edges are legal input.  A graph that lists both
+ *     directions of an edge simply has two parallel edges; the lower id wins.
+ *   - Limits: 0 <= n <= 2^31-1, 0 <= m <= 2^32-1, n == 0 requires m == 0.
+ *   - Array arguments are DEVICE pointers (hipMalloc / torch tensors on ROCm)
+ *     unless marked HOST.  Inputs are never modified.  The caller owns every
+ *     buffer; the library writes only the outputs and the workspace.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).
+ *   - Functions return an msf_status; nothing aborts or throws across the ABI.
+ *     Argument errors are reported before any GPU work is launched.
+ */
+#ifndef MSF_H
+#define MSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSF_OK = 0,
+    MSF_EINVAL = -1,      /* bad argument (null pointer, n/m out of limits, bad options) */
+    MSF_ERANGE = -2,      /* some u[e] or v[e] outside [0, n); outputs unspecified */
+    MSF_ENOMEM = -3,      /* device allocation of an internal workspace failed */
+    MSF_EDEVICE = -4,     /* a HIP call failed; msf_last_error() has the text */
+    MSF_EWORKSPACE = -5,  /* caller workspace smaller than msf_workspace_bytes() */
+    MSF_EINTERNAL = -6    /* an internal consistency check failed (a library bug) */
+} msf_status;
+
+typedef enum { MSF_ALGO_BORUVKA = 0, MSF_ALGO_FILTER = 1 } msf_algo;
+
+typedef enum {
+    MSF_PIVOT_MEDIAN = 0,    /* lower median of the sample (the paper's choice, Sec. V) */
+    MSF_PIVOT_QUANTILE = 1,  /* sample quantile `quantile` in [0, 1] */
+    MSF_PIVOT_MLP = 2        /* quantile predicted by the loaded pivot network;
+                                falls back to the median when none is loaded */
+} msf_pivot;
+
+/* Options; a NULL pointer means {MSF_ALGO_BORUVKA, MSF_PIVOT_MEDIAN, 0.5, seed 1,
+ * defaults}.  Every field only changes running time, never the result. */
+typedef struct msf_options {
+    int32_t algo;            /* msf_algo */
+    int32_t pivot;           /* msf_pivot (filter only) */
+    float quantile;          /* MSF_PIVOT_QUANTILE: sample quantile in [0, 1] */
+    int32_t sample_size;     /* filter pivot sample size; 0 = 4096 */
+    uint64_t seed;           /* seed of the pivot sampler's counter-based generator */
+    int32_t sparse_degree;   /* filter isSparse: stop splitting when 2m'/n' <= this; 0 = 4 */
+    int32_t min_split_edges; /* filter isSparse: stop splitting below this many edges; 0 = 65536 */
+    int32_t reserved[8];     /* must be zero */
+} msf_options;
+
+#define MSF_MAX_TRACE 64
+
+/* Per-call statistics (HOST struct, optional). */
+typedef struct msf_stats {
+    uint64_t total_weight;      /* same as *total_weight_out */
+    uint64_t msf_edges;         /* number of MSF edges = n - #components */
+    uint32_t rounds;            /* Borůvka rounds executed (all base cases summed) */
+    uint32_t levels;            /* filter recursion calls that split (0 for Borůvka) */
+    uint32_t base_cases;        /* Borůvka base-case calls (1 for plain Borůvka) */
+    float pivot_q_used;         /* quantile used at the first split (filter), else 0 */
+    /* First MSF_MAX_TRACE rounds, in execution order: */
+    uint64_t round_live[MSF_MAX_TRACE];   /* vertices with an incident live edge */
+    uint64_t round_edges[MSF_MAX_TRACE];  /* edges scanned by the round */
+    uint64_t round_found[MSF_MAX_TRACE];  /* MSF edges found by the round */
+    uint64_t filtered_in;       /* heavy edges entering filtering (filter only) */
+    uint64_t filtered_out;      /* heavy edges surviving filtering (filter only) */
+} msf_stats;
+
+/* Bytes of device workspace msf_compute needs for (m, n, opt); opt may be NULL. */
+size_t msf_workspace_bytes(int64_t m, int64_t n, const msf_options* opt);
+
+/*
+ * msf_compute -- MSF of one graph.
+ *   u, v, w       device arrays of length m (int32, int32, uint32), read only
+ *   mask_out      device uint8[m]; on MSF_OK mask_out[e] = 1 iff edge e is in
+ *                 the MSF, else 0
+ *   total_weight_out  HOST; sum of w over MSF edges (cannot overflow 64 bits)
+ *   workspace     device buffer of >= msf_workspace_bytes(m, n, opt) bytes, or
+ *                 NULL: the library then allocates it on `stream` and frees it
+ *                 before returning (MSF_ENOMEM if that fails)
+ *   stats         optional HOST struct, filled on MSF_OK
+ * Blocking: returns once the mask and total are final.  Out-of-range ids are
+ * detected on the device and reported as MSF_ERANGE after the first pass.
+ */
+int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,
+                uint8_t* mask_out, uint64_t* total_weight_out, void* workspace,
+                size_t workspace_bytes, void* stream, const msf_options* opt,
+                msf_stats* stats);
+
+/* Static description of a status code. */
+const char* msf_status_string(int status);
+
+/* Text of the last MSF_EDEVICE / MSF_EINTERNAL error on the calling thread. */
+const char* msf_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int msf_version(void);
+
+/*
+ * Kernel timing for benchmarks.  While enabled, every kernel launch of
+ * msf_compute is bracketed by HIP events recorded on the call's stream; the
+ * elapsed times are accumulated per kernel together with the algorithmic
+ * bytes of each launch (bytes the step must read or write at minimum, e.g.
+ * 12 B per input edge for the first lightest-edge pass).  Process-wide state,
+ * guarded by a lock; costs one event pair per launch.
+ */
+typedef struct msf_kernel_profile {
+    char name[32];           /* kernel family */
+    uint64_t launches;       /* launches timed */
+    double total_ms;         /* summed event-timed duration */
+    double bytes;            /* summed algorithmic bytes */
+} msf_kernel_profile;
+
+int msf_profile_enable(int on);                            /* returns MSF_OK */
+int msf_profile_reset(void);                               /* returns MSF_OK */
+/* Copies up to `capacity` entries (HOST array); returns the number copied. */
+int msf_profile_read(msf_kernel_profile* out, int capacity);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSF_H */

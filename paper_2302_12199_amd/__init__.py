@@ -1,0 +1,185 @@
+"""Python binding of libmsf.so, the MI355X minimum spanning forest library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/msf.h``.  PyTorch provides
+device memory and the current stream.  There is no CPU fallback: if the
+library is not built, importing the binding's entry points raises.
+
+    import paper_2302_12199_amd as msf
+    mask, total, stats = msf.compute(u, v, w, n)      # u, v, w: int32 CUDA tensors
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first so libmsf.so binds to the HIP runtime torch uses
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsf.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EWORKSPACE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+ALGOS = {"boruvka": 0, "filter": 1}
+PIVOTS = {"median": 0, "quantile": 1, "mlp": 2}
+MAX_TRACE = 64
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("pivot", ctypes.c_int32),
+                ("quantile", ctypes.c_float), ("sample_size", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("sparse_degree", ctypes.c_int32),
+                ("min_split_edges", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("total_weight", ctypes.c_uint64), ("msf_edges", ctypes.c_uint64),
+                ("rounds", ctypes.c_uint32), ("levels", ctypes.c_uint32),
+                ("base_cases", ctypes.c_uint32), ("pivot_q_used", ctypes.c_float),
+                ("round_live", ctypes.c_uint64 * MAX_TRACE),
+                ("round_edges", ctypes.c_uint64 * MAX_TRACE),
+                ("round_found", ctypes.c_uint64 * MAX_TRACE),
+                ("filtered_in", ctypes.c_uint64), ("filtered_out", ctypes.c_uint64)]
+
+    def to_dict(self):
+        r = min(self.rounds, MAX_TRACE)
+        return {"total_weight": int(self.total_weight), "msf_edges": int(self.msf_edges),
+                "rounds": int(self.rounds), "levels": int(self.levels),
+                "base_cases": int(self.base_cases), "pivot_q_used": float(self.pivot_q_used),
+                "round_live": [int(x) for x in self.round_live[:r]],
+                "round_edges": [int(x) for x in self.round_edges[:r]],
+                "round_found": [int(x) for x in self.round_found[:r]],
+                "filtered_in": int(self.filtered_in), "filtered_out": int(self.filtered_out)}
+
+
+class MSFError(RuntimeError):
+    def __init__(self, status, detail=""):
+        self.status = status
+        text = _lib().msf_status_string(status).decode() if _LIB else str(status)
+        super().__init__(f"msf status {status} ({text}){': ' + detail if detail else ''}")
+
+
+_LIB = None
+
+# Exported C symbols (each declared in include/msf.h).
+SYMBOLS = ("msf_workspace_bytes", "msf_compute", "msf_status_string", "msf_last_error",
+           "msf_version", "msf_profile_enable", "msf_profile_reset", "msf_profile_read")
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+        lib.msf_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Options)]
+        lib.msf_workspace_bytes.restype = sz
+        lib.msf_compute.argtypes = [vp, vp, vp, i64, i64, vp, ctypes.POINTER(ctypes.c_uint64),
+                                    vp, sz, vp, ctypes.POINTER(Options), ctypes.POINTER(Stats)]
+        lib.msf_compute.restype = ctypes.c_int
+        lib.msf_status_string.argtypes = [ctypes.c_int]
+        lib.msf_status_string.restype = ctypes.c_char_p
+        lib.msf_last_error.restype = ctypes.c_char_p
+        lib.msf_version.restype = ctypes.c_int
+        lib.msf_profile_enable.argtypes = [ctypes.c_int]
+        lib.msf_profile_read.argtypes = [ctypes.POINTER(KernelProfile), ctypes.c_int]
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library (raises if libmsf.so is not built)."""
+    return _lib()
+
+
+def make_options(algo="boruvka", pivot="median", quantile=0.5, seed=1, sample_size=0,
+                 sparse_degree=0, min_split_edges=0):
+    o = Options()
+    o.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    o.pivot = PIVOTS[pivot] if isinstance(pivot, str) else int(pivot)
+    o.quantile = float(quantile)
+    o.seed = int(seed)
+    o.sample_size = int(sample_size)
+    o.sparse_degree = int(sparse_degree)
+    o.min_split_edges = int(min_split_edges)
+    return o
+
+
+def workspace_bytes(m, n, **opts):
+    o = make_options(**opts)
+    return int(_lib().msf_workspace_bytes(int(m), int(n), ctypes.byref(o)))
+
+
+def _dev_i32(t, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype == torch.uint32:
+        t = t.view(torch.int32)
+    if t.dtype != torch.int32:
+        raise TypeError(f"{name} must be int32 (or uint32 for w)")
+    return t.contiguous()
+
+
+def compute(u, v, w, n, *, workspace=None, mask_out=None, stream=None, **opts):
+    """MSF of the graph (u[e], v[e], w[e]) on vertices [0, n).
+
+    Returns (mask, total, stats): mask is a uint8 CUDA tensor (1 = MSF edge),
+    total the 64-bit MSF weight (Python int) and stats a dict (msf.h msf_stats).
+    ``workspace`` may be a uint8 CUDA tensor of at least workspace_bytes(m, n)
+    bytes; otherwise torch allocates one for the call.
+    """
+    lib = _lib()
+    u, v, w = _dev_i32(u, "u"), _dev_i32(v, "v"), _dev_i32(w, "w")
+    m = u.numel()
+    if v.numel() != m or w.numel() != m:
+        raise ValueError("u, v, w must have the same length")
+    o = make_options(**opts)
+    dev = u.device
+    if mask_out is None:
+        mask_out = torch.empty(max(m, 1), dtype=torch.uint8, device=dev)[:m]
+    need = int(lib.msf_workspace_bytes(m, int(n), ctypes.byref(o)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    total = ctypes.c_uint64(0)
+    st = Stats()
+    rc = lib.msf_compute(u.data_ptr(), v.data_ptr(), w.data_ptr(), m, int(n),
+                         mask_out.data_ptr(), ctypes.byref(total), workspace.data_ptr(),
+                         workspace.numel(), ctypes.c_void_p(s.cuda_stream), ctypes.byref(o),
+                         ctypes.byref(st))
+    if rc != OK:
+        raise MSFError(rc, lib.msf_last_error().decode(errors="replace"))
+    return mask_out, int(total.value), st.to_dict()
+
+
+def profile_enable(on=True):
+    _lib().msf_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    _lib().msf_profile_reset()
+
+
+def profile_read():
+    """{kernel family: {"launches", "ms", "bytes"}} accumulated since the last reset."""
+    buf = (KernelProfile * 64)()
+    k = _lib().msf_profile_read(buf, 64)
+    return {buf[i].name.decode(): {"launches": int(buf[i].launches), "ms": float(buf[i].total_ms),
+                                   "bytes": float(buf[i].bytes)} for i in range(k)}
+
+
+def compute_raw(u_ptr, v_ptr, w_ptr, m, n, mask_ptr, workspace_ptr=0, workspace_bytes=0,
+                stream=0, options=None, stats=None):
+    """Direct C-ABI call on raw device pointers; returns (status, total)."""
+    total = ctypes.c_uint64(0)
+    rc = _lib().msf_compute(u_ptr, v_ptr, w_ptr, int(m), int(n), mask_ptr, ctypes.byref(total),
+                            workspace_ptr or None, int(workspace_bytes), stream or None,
+                            ctypes.byref(options) if options is not None else None,
+                            ctypes.byref(stats) if stats is not None else None)
+    return rc, int(total.value)

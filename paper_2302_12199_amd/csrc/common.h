@@ -1,0 +1,52 @@
+// Shared device/host definitions of the MSF library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msf {
+
+constexpr int kBlock = 256;                 // threads per workgroup (4 waves)
+constexpr int kWave = 64;                   // CDNA wavefront width
+constexpr int kItems = 16;                  // items per thread in scan tiles
+constexpr int kTile = kBlock * kItems;      // items per decoupled-lookback tile
+constexpr int kRelabelItems = 8;            // edges per thread in the relabel pass
+constexpr int kRelabelTile = kBlock * kRelabelItems;
+constexpr uint64_t kKeyMax = ~0ull;         // "no edge" in best[]
+
+// Error bits accumulated on the device.
+constexpr uint32_t kErrRange = 1u;          // an endpoint id outside [0, n)
+constexpr uint32_t kErrLookback = 2u;       // a lookback wait hit its spin bound
+constexpr uint32_t kErrInternal = 4u;       // a min edge not incident to its vertex
+
+// Device control block (lives in the workspace; zeroed per call).
+struct Ctrl {
+    uint32_t tile_counter;   // dynamic tile ids of the running lookback scan
+    uint32_t err;            // kErr* bits
+    uint32_t jump_more;      // pointer jumping has not reached a fixed point yet
+    uint32_t pad0;
+    uint64_t n_next;         // vertices of the next round (root scan result)
+    uint64_t m_next;         // edges of the next round (edge compaction result)
+    uint64_t total;          // MSF weight so far
+    uint64_t msf_edges;      // MSF edges so far
+    uint64_t live;           // vertices with an incident edge, this round
+    uint64_t found;          // MSF edges marked this round
+    uint64_t aux[8];         // scratch counters for the filter driver
+};
+
+// Lookback status word: 2 flag bits over a 62-bit inclusive/aggregate value.
+constexpr uint64_t kStatAgg = 1ull << 62;
+constexpr uint64_t kStatInc = 2ull << 62;
+constexpr uint64_t kStatMask = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+// Edge arrays of a round: structure of arrays, 16 B per edge.  Position order
+// equals edge-id order (every compaction is stable), so inside a round the key
+// (w << 32 | position) orders edges exactly like (w, id).
+struct EdgeSoA {
+    int32_t* u;
+    int32_t* v;
+    uint32_t* w;
+    uint32_t* id;
+};
+
+}  // namespace msf

@@ -1,0 +1,90 @@
+// Wave and workgroup primitives for gfx950 (wave64): ballot-based stream
+// compaction ranks, wave reductions and a decoupled-lookback tile prefix.
+#pragma once
+#include "common.h"
+
+namespace msf {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` in lanes below the calling lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// min-update of a 64-bit packed key: read first, issue the atomic only when it
+// can still lower the value.  Stale reads are harmless: best[] only decreases.
+__device__ __forceinline__ void atomic_min_key(uint64_t* p, uint64_t key) {
+    if (key < *p) atomicMin((unsigned long long*)p, (unsigned long long)key);
+}
+
+// Dynamic tile id: tiles are numbered in the order workgroups start, so a tile
+// only ever waits on tiles that are already running (no deadlock).
+__device__ __forceinline__ uint32_t take_tile(Ctrl* ctrl, uint32_t* s_tile) {
+    if (threadIdx.x == 0) *s_tile = atomicAdd(&ctrl->tile_counter, 1u);
+    __syncthreads();
+    return *s_tile;
+}
+
+// Exclusive prefix of this tile's aggregate over all earlier tiles
+// (single-pass scan with decoupled lookback).  Must be called by the whole
+// workgroup; wave 0 does the lookback, 64 predecessors per step.  Every wait
+// is bounded: past kSpinLimit polls the error bit is raised and the missing
+// value is taken as zero, so the kernel always terminates.
+__device__ __forceinline__ uint64_t tile_prefix(uint64_t* status, uint32_t tile, uint64_t agg,
+                                                Ctrl* ctrl, uint64_t* s_prefix) {
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        uint64_t excl = 0;
+        if (tile == 0) {
+            if (lane == 0) st_relaxed(&status[0], kStatInc | agg);
+        } else {
+            if (lane == 0) st_relaxed(&status[tile], kStatAgg | agg);
+            int64_t base = (int64_t)tile - 1;
+            while (true) {
+                const int64_t idx = base - lane;
+                uint64_t s = kStatInc;  // before tile 0: inclusive zero
+                uint32_t spins = 0;
+                while (true) {
+                    if (idx >= 0) s = ld_relaxed(&status[idx]);
+                    const uint64_t pending = __ballot((s >> 62) == 0);
+                    if (pending == 0) break;
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicOr(&ctrl->err, kErrLookback);
+                        if ((s >> 62) == 0) s = kStatInc;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                const uint64_t inc = __ballot((s >> 62) == 2);
+                if (inc) {
+                    const int first = __builtin_ctzll(inc);  // closest inclusive predecessor
+                    excl += wave_sum_u64(lane <= first ? (s & kStatMask) : 0);
+                    break;
+                }
+                excl += wave_sum_u64(s & kStatMask);
+                base -= kWave;
+            }
+            if (lane == 0) st_relaxed(&status[tile], kStatInc | (excl + agg));
+        }
+        if (lane == 0) *s_prefix = excl;
+    }
+    __syncthreads();
+    return *s_prefix;
+}
+
+}  // namespace msf

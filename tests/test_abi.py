@@ -1,0 +1,104 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol the header
+declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def msf():
+    import paper_2302_12199_amd as msf
+    if not os.path.exists(msf.LIB_PATH):
+        pytest.fail("libmsf.so not built: run __graft_entry__.build()")
+    return msf
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "msf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\**\s+\**(msf_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(msf):
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    assert sorted(msf.SYMBOLS) == names
+    lib = msf.library()
+    for name in names:
+        assert getattr(lib, name) is not None
+
+
+def test_status_strings(msf):
+    lib = msf.library()
+    assert lib.msf_status_string(0) == b"ok"
+    assert lib.msf_status_string(msf.ERANGE) == b"vertex id out of range"
+    assert lib.msf_version() >= 100
+
+
+def test_workspace_size_monotone(msf):
+    a = msf.workspace_bytes(1000, 100)
+    b = msf.workspace_bytes(2000, 100)
+    c = msf.workspace_bytes(2000, 200)
+    assert 0 < a < b < c
+    assert msf.workspace_bytes(2**28, 2**24) > 32 * 2**28
+
+
+FAKE = 0x1000  # never dereferenced: argument checks run before any device work
+
+
+@pytest.mark.parametrize("m,n", [(-1, 5), (5, -1), (2**32, 5), (5, 2**31), (3, 0)])
+def test_rejects_bad_sizes(msf, m, n):
+    rc, _ = msf.compute_raw(FAKE, FAKE, FAKE, m, n, FAKE)
+    assert rc == msf.EINVAL
+
+
+def test_rejects_null_pointers(msf):
+    for args in [(0, FAKE, FAKE, FAKE), (FAKE, 0, FAKE, FAKE), (FAKE, FAKE, 0, FAKE),
+                 (FAKE, FAKE, FAKE, 0)]:
+        rc, _ = msf.compute_raw(args[0], args[1], args[2], 10, 5, args[3])
+        assert rc == msf.EINVAL
+    total = ctypes.c_uint64()
+    rc = msf.library().msf_compute(FAKE, FAKE, FAKE, 10, 5, FAKE, None, None, 0, None, None, None)
+    assert rc == msf.EINVAL
+
+
+def test_rejects_bad_options(msf):
+    for kw in [dict(algo=7), dict(pivot=9), dict(quantile=1.5), dict(quantile=float("nan")),
+               dict(sample_size=-1)]:
+        rc, _ = msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE, options=msf.make_options(**kw))
+        assert rc == msf.EINVAL, kw
+    o = msf.make_options()
+    o.reserved[3] = 1
+    assert msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE, options=o)[0] == msf.EINVAL
+
+
+def test_workspace_too_small(msf):
+    need = msf.workspace_bytes(10, 5)
+    rc, _ = msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE, workspace_ptr=FAKE,
+                            workspace_bytes=need - 1)
+    assert rc == msf.EWORKSPACE
+
+
+def test_forced_allocation_failure(msf, monkeypatch):
+    monkeypatch.setenv("MSF_TEST_FAIL_ALLOC", "1")
+    rc, _ = msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE)
+    assert rc == msf.ENOMEM
+
+
+def test_empty_graph_needs_no_device(msf):
+    st = msf.Stats()
+    rc, total = msf.compute_raw(0, 0, 0, 0, 7, 0, stats=st)
+    assert rc == msf.OK and total == 0 and st.msf_edges == 0
+
+
+def test_no_cpu_fallback(msf, monkeypatch, tmp_path):
+    import importlib
+    import sys
+    monkeypatch.setattr(msf, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(msf, "_LIB", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        msf.library()
