@@ -65,10 +65,10 @@ typedef struct msf_options {
     int32_t algo;            /* msf_algo */
     int32_t pivot;           /* msf_pivot (filter only) */
     float quantile;          /* MSF_PIVOT_QUANTILE: sample quantile in [0, 1] */
-    int32_t sample_size;     /* filter pivot sample size; 0 = 4096 */
+    int32_t sample_size;     /* filter pivot sample size in [1, 8192]; 0 = 4096 */
     uint64_t seed;           /* seed of the pivot sampler's counter-based generator */
     int32_t sparse_degree;   /* filter isSparse: stop splitting when 2m'/n' <= this; 0 = 4 */
-    int32_t min_split_edges; /* filter isSparse: stop splitting below this many edges; 0 = 65536 */
+    int32_t min_split_edges; /* filter isSparse: stop splitting below this many edges; 0 = 2^20 */
     int32_t reserved[8];     /* must be zero */
 } msf_options;
 
@@ -88,6 +88,12 @@ typedef struct msf_stats {
     uint64_t round_found[MSF_MAX_TRACE];  /* MSF edges found by the round */
     uint64_t filtered_in;       /* heavy edges entering filtering (filter only) */
     uint64_t filtered_out;      /* heavy edges surviving filtering (filter only) */
+    /* Filter-Borůvka splits in depth-first order (first MSF_MAX_TRACE): */
+    uint64_t split_edges[MSF_MAX_TRACE];  /* edges of the graph being split */
+    uint64_t split_pivot[MSF_MAX_TRACE];  /* pivot key w << 32 | edge id */
+    uint64_t split_light[MSF_MAX_TRACE];  /* edges with key <= pivot */
+    uint64_t split_kept[MSF_MAX_TRACE];   /* heavy edges surviving the filter */
+    float split_q[MSF_MAX_TRACE];         /* sample quantile used by the split */
 } msf_stats;
 
 /* Bytes of device workspace msf_compute needs for (m, n, opt); opt may be NULL. */

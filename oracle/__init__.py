@@ -111,6 +111,12 @@ def components(u, v, n):
     return int(_load().oracle_components(_p(u), _p(v), len(u), n))
 
 
+def filter_boruvka(*args, **kwargs):
+    """Filter-Borůvka step by step (see oracle/filter_ref.py)."""
+    from .filter_ref import filter_boruvka as fb
+    return fb(*args, **kwargs)
+
+
 def sort_u64(a):
     a = np.ascontiguousarray(a, dtype=np.uint64).copy()
     st = _load().oracle_sort_u64(_p(a), len(a))

@@ -38,7 +38,12 @@ class Stats(ctypes.Structure):
                 ("round_live", ctypes.c_uint64 * MAX_TRACE),
                 ("round_edges", ctypes.c_uint64 * MAX_TRACE),
                 ("round_found", ctypes.c_uint64 * MAX_TRACE),
-                ("filtered_in", ctypes.c_uint64), ("filtered_out", ctypes.c_uint64)]
+                ("filtered_in", ctypes.c_uint64), ("filtered_out", ctypes.c_uint64),
+                ("split_edges", ctypes.c_uint64 * MAX_TRACE),
+                ("split_pivot", ctypes.c_uint64 * MAX_TRACE),
+                ("split_light", ctypes.c_uint64 * MAX_TRACE),
+                ("split_kept", ctypes.c_uint64 * MAX_TRACE),
+                ("split_q", ctypes.c_float * MAX_TRACE)]
 
     def to_dict(self):
         r = min(self.rounds, MAX_TRACE)
@@ -48,7 +53,11 @@ class Stats(ctypes.Structure):
                 "round_live": [int(x) for x in self.round_live[:r]],
                 "round_edges": [int(x) for x in self.round_edges[:r]],
                 "round_found": [int(x) for x in self.round_found[:r]],
-                "filtered_in": int(self.filtered_in), "filtered_out": int(self.filtered_out)}
+                "filtered_in": int(self.filtered_in), "filtered_out": int(self.filtered_out),
+                "splits": [{"edges": int(self.split_edges[i]), "pivot": int(self.split_pivot[i]),
+                            "light": int(self.split_light[i]), "kept": int(self.split_kept[i]),
+                            "q": float(self.split_q[i])}
+                           for i in range(min(self.levels, MAX_TRACE))]}
 
 
 class MSFError(RuntimeError):

@@ -1,17 +1,22 @@
-// Borůvka round kernels (paper Sec. II-C; Alg. 1 round body of Sec. IV).
+// Borůvka round kernels (paper Sec. II-C; the round body of Alg. 1, Sec. IV).
 //
-// One round on the edge list of the current graph:
-//   minedge      best[x] = min key over live edges incident to x   (minEdges)
+// One round on the current graph:
+//   minedge      best[x] = min key over live edges incident to x   (minEdges;
+//                packed (w << 32 | position) keys, 64-bit atomicMin)
 //   hook         parent[x] = other endpoint of best[x]; the smaller vertex of
 //                each 2-cycle becomes the root; every non-root marks its edge
 //                as an MSF edge                                     (contractComponents)
 //   jump         parent[x] <- parent[parent[x]] until stars         (pointer doubling)
-//   scan_roots   dense new ids for roots that still have edges      (base-case style relabel)
+//   scan_roots   dense new ids for roots that still have edges      (dense relabel of the base case)
 //   label        label[x] = new id of x's root
-//   relabel      (label[u], label[v]), drop self-loops, stable compaction, fused
-//                with the next round's minedge                       (relabel)
-// Keys are (w << 32 | position) with positions in edge-id order, so every
-// comparison is the paper's consistent tie break by (weight, edge id).
+//   pass         every edge is relabelled through the label map, self-loops
+//                are dropped, and the survivors immediately take part in the
+//                next round's minedge (relabel fused with minEdges)
+// The pass either keeps the edge positions (rewriting endpoint labels, or
+// only composing the label map when nothing needs rewriting) or compacts the
+// live edges stably with a decoupled-lookback scan.
+#include <stdlib.h>
+
 #include "prim.h"
 
 namespace msf {
@@ -32,8 +37,8 @@ __global__ void k_zero_bytes(uint8_t* __restrict__ p, int64_t n) {
     if (t < (n & 15)) p[(nv << 4) + t] = 0;
 }
 
-// Clears a lookback status array and the tile counter before a scan launch,
-// and the per-round counters when `round_begin` is set.
+// Clears a lookback status array and the tile counter before a scan launch.
+// round_begin also clears the per-round counters.
 __global__ void k_scan_prep(uint64_t* __restrict__ status, int64_t ntiles, Ctrl* ctrl,
                             int round_begin) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ntiles;
@@ -45,37 +50,88 @@ __global__ void k_scan_prep(uint64_t* __restrict__ status, int64_t ntiles, Ctrl*
             ctrl->live = 0;
             ctrl->found = 0;
             ctrl->jump_more = 0;
+            ctrl->m_next = 0;
         }
     }
 }
 
-// Round 0 lightest incident edge, reading the caller's arrays directly.
-// Validates ids (bit kErrRange) and skips self-loops.
+// ------------------------------------------------------------ edge access
+
+template <int MODE>
+__device__ __forceinline__ void load_ends(const View& g, int64_t p, int32_t& a, int32_t& b) {
+    if constexpr (MODE == kFull16) {
+        const uint32_t x = g.p16[p];
+        a = (int32_t)(x & 0xffffu);
+        b = (int32_t)(x >> 16);
+    } else {
+        a = g.u[p];
+        b = g.v[p];
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ uint32_t edge_id(const View& g, int64_t p) {
+    if constexpr (MODE == kCompact) return g.id[p];
+    else return (uint32_t)p;
+}
+
+// ---------------------------------------------------------------- round 0
+
+// Lightest incident edge on the caller's arrays (4 edges per lane when the
+// arrays are 16-byte aligned).  Validates ids (kErrRange), skips self-loops.
+template <int VEC>
 __global__ __launch_bounds__(kBlock) void k_minedge_r0(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
     int64_t m, int64_t n, uint64_t* __restrict__ best, Ctrl* ctrl) {
     bool bad = false;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a = u[e], b = v[e];
-        if ((uint32_t)a >= (uint64_t)n || (uint32_t)b >= (uint64_t)n) { bad = true; continue; }
-        if (a == b) continue;
-        const uint64_t key = ((uint64_t)w[e] << 32) | (uint64_t)e;
-        atomic_min_key(&best[a], key);
-        atomic_min_key(&best[b], key);
+    const int64_t groups = (m + VEC - 1) / VEC;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int32_t aa[VEC], bb[VEC];
+        uint32_t ww[VEC];
+        if (VEC == 4 && g * 4 + 3 < m) {
+            const int4 a4 = reinterpret_cast<const int4*>(u)[g];
+            const int4 b4 = reinterpret_cast<const int4*>(v)[g];
+            const uint4 w4 = reinterpret_cast<const uint4*>(w)[g];
+            aa[0] = a4.x; aa[1] = a4.y; aa[2] = a4.z; aa[3] = a4.w;
+            bb[0] = b4.x; bb[1] = b4.y; bb[2] = b4.z; bb[3] = b4.w;
+            ww[0] = w4.x; ww[1] = w4.y; ww[2] = w4.z; ww[3] = w4.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                const int64_t e = g * VEC + k;
+                aa[k] = bb[k] = 0;
+                ww[k] = 0;
+                if (e < m) { aa[k] = u[e]; bb[k] = v[e]; ww[k] = w[e]; }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+            const int64_t e = g * VEC + k;
+            if (e >= m) continue;
+            const int32_t a = aa[k], b = bb[k];
+            if ((uint32_t)a >= (uint64_t)n || (uint32_t)b >= (uint64_t)n) { bad = true; continue; }
+            if (a == b) continue;
+            const uint64_t key = ((uint64_t)ww[k] << 32) | (uint64_t)e;
+            atomic_min_key(&best[a], key);
+            atomic_min_key(&best[b], key);
+        }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrRange);
 }
 
-// Hook: parent[x] = other endpoint of x's lightest edge.  Both vertices of a
+// ------------------------------------------------------------------ hook
+
+// parent[x] = other endpoint of x's lightest edge.  Both vertices of a
 // 2-cycle picked the same edge (strict order), recognised as best[other] ==
 // best[x]; the smaller id is the root.  Every other live vertex owns exactly
-// one MSF edge and marks it, so each MSF edge is counted once.
-template <bool kR0>
-__global__ __launch_bounds__(kBlock) void k_hook(
-    const uint64_t* __restrict__ best, int64_t nr, const int32_t* __restrict__ U,
-    const int32_t* __restrict__ V, const uint32_t* __restrict__ ID, int32_t* __restrict__ parent,
-    uint8_t* __restrict__ mask, Ctrl* ctrl) {
+// one MSF edge and marks it, so each MSF edge is counted once.  `cmap` maps
+// the view's stored labels to this round's labels (null: identity).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_hook(const uint64_t* __restrict__ best, int64_t nr,
+                                                 View g, const int32_t* __restrict__ cmap,
+                                                 int32_t* __restrict__ parent,
+                                                 uint8_t* __restrict__ mask, Ctrl* ctrl) {
     uint64_t wsum = 0, nfound = 0, nlive = 0;
     bool bad = false;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nr;
@@ -84,15 +140,17 @@ __global__ __launch_bounds__(kBlock) void k_hook(
         if (b == kKeyMax) { parent[x] = (int32_t)x; continue; }
         ++nlive;
         const uint32_t pos = (uint32_t)b;
-        const int32_t eu = U[pos], ev = V[pos];
+        int32_t eu, ev;
+        load_ends<MODE>(g, pos, eu, ev);
+        if (cmap) { eu = cmap[eu]; ev = cmap[ev]; }
         if (eu != x && ev != x) bad = true;
         const int32_t other = eu == (int32_t)x ? ev : eu;
+        if ((uint32_t)other >= (uint64_t)nr) { bad = true; parent[x] = (int32_t)x; continue; }
         if (best[other] == b && (int32_t)x < other) {
             parent[x] = (int32_t)x;
         } else {
             parent[x] = other;
-            const uint32_t id = kR0 ? pos : ID[pos];
-            mask[id] = 1;
+            mask[edge_id<MODE>(g, pos)] = 1;
             wsum += b >> 32;
             ++nfound;
         }
@@ -190,15 +248,154 @@ __global__ __launch_bounds__(kBlock) void k_label(
     }
 }
 
-// Relabel every edge to (label[u], label[v]), drop the self-loops this
-// creates, and compact the survivors stably into `out` (position order stays
-// edge-id order).  Fused: each survivor immediately takes part in the next
-// round's lightest-edge search with key (w << 32 | new position).
-template <bool kR0>
-__global__ __launch_bounds__(kBlock) void k_relabel(
-    const int32_t* __restrict__ U, const int32_t* __restrict__ V, const uint32_t* __restrict__ W,
-    const uint32_t* __restrict__ ID, int64_t mr, const int32_t* __restrict__ label, EdgeSoA out,
-    uint64_t* __restrict__ best_next, uint64_t* status, Ctrl* ctrl, uint32_t ntiles) {
+// out[i] = label[cmap[i]] (-1 stays -1): the map from a view's stored labels
+// to the next round's labels.
+__global__ __launch_bounds__(kBlock) void k_compose(const int32_t* __restrict__ cmap, int64_t nc,
+                                                    const int32_t* __restrict__ label,
+                                                    int32_t* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nc;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = cmap[i];
+        out[i] = c < 0 ? -1 : label[c];
+    }
+}
+
+// Representative tracking for Filter-Borůvka (Sec. V: after a round every
+// vertex records the component root it was contracted into; the chains are
+// compressed by pointer doubling at the end).  orig_cur[x] is the input
+// vertex that round vertex x stands for (null: identity).
+__global__ __launch_bounds__(kBlock) void k_rep_update(
+    const int32_t* __restrict__ parent, const uint64_t* __restrict__ best,
+    const int32_t* __restrict__ label, int64_t nr, const int32_t* __restrict__ orig_cur,
+    int32_t* __restrict__ orig_next, int32_t* __restrict__ rep) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nr;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        if (best[x] == kKeyMax) continue;
+        const int32_t p = parent[x];
+        const int32_t ox = orig_cur ? orig_cur[x] : (int32_t)x;
+        if (p != (int32_t)x) rep[ox] = orig_cur ? orig_cur[p] : p;
+        else orig_next[label[x]] = ox;
+    }
+}
+
+// ------------------------------------------------------------ streaming pass
+
+// Relabel + next-round minedge over every position of the view, keeping the
+// positions.  Each lane handles 4 consecutive positions per step (vector
+// loads).  The map M (view labels -> next-round labels, nc entries) and the
+// next round's best[] can be staged in LDS when small.  OUT selects what is
+// written: nothing (the caller composes maps instead), int32 label pairs, or
+// packed 16-bit label pairs.  Dead edges are written as (0, 0).
+template <int IN, int OUT, bool LDS_M, bool LDS_B>
+__global__ __launch_bounds__(kBlock) void k_pass(View g, const int32_t* __restrict__ M,
+                                                 int64_t nc, int32_t* __restrict__ ou,
+                                                 int32_t* __restrict__ ov,
+                                                 uint32_t* __restrict__ op16,
+                                                 uint64_t* __restrict__ best_next, int64_t nn,
+                                                 Ctrl* ctrl) {
+    extern __shared__ uint64_t lds[];
+    uint64_t* s_best = lds;                                        // nn entries (LDS_B)
+    int32_t* s_map = reinterpret_cast<int32_t*>(lds + (LDS_B ? nn : 0));  // nc entries (LDS_M)
+    if constexpr (LDS_B)
+        for (int64_t i = threadIdx.x; i < nn; i += blockDim.x) s_best[i] = kKeyMax;
+    if constexpr (LDS_M)
+        for (int64_t i = threadIdx.x; i < nc; i += blockDim.x) s_map[i] = M[i];
+    if constexpr (LDS_B || LDS_M) __syncthreads();
+    const int32_t* map = LDS_M ? s_map : M;
+    uint64_t* bst = LDS_B ? s_best : best_next;
+
+    const int64_t m = g.len;
+    const int64_t groups = (m + 3) / 4;
+    uint32_t kept = 0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < groups;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e0 = q * 4;
+        const bool full = e0 + 3 < m;
+        int32_t a[4], b[4];
+        uint32_t w[4];
+        if (full) {
+            if constexpr (IN == kFull16) {
+                const uint4 p = reinterpret_cast<const uint4*>(g.p16)[q];
+                a[0] = p.x & 0xffff; b[0] = p.x >> 16; a[1] = p.y & 0xffff; b[1] = p.y >> 16;
+                a[2] = p.z & 0xffff; b[2] = p.z >> 16; a[3] = p.w & 0xffff; b[3] = p.w >> 16;
+            } else {
+                const int4 a4 = reinterpret_cast<const int4*>(g.u)[q];
+                const int4 b4 = reinterpret_cast<const int4*>(g.v)[q];
+                a[0] = a4.x; a[1] = a4.y; a[2] = a4.z; a[3] = a4.w;
+                b[0] = b4.x; b[1] = b4.y; b[2] = b4.z; b[3] = b4.w;
+            }
+            const uint4 w4 = reinterpret_cast<const uint4*>(g.w)[q];
+            w[0] = w4.x; w[1] = w4.y; w[2] = w4.z; w[3] = w4.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                a[k] = b[k] = 0;
+                w[k] = 0;
+                if (e0 + k < m) {
+                    load_ends<IN>(g, e0 + k, a[k], b[k]);
+                    w[k] = g.w[e0 + k];
+                }
+            }
+        }
+        int32_t ra[4], rb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            ra[k] = rb[k] = 0;
+            if (e0 + k < m && a[k] != b[k]) {     // equal stored labels stay a self-loop
+                const int32_t x = map[a[k]], y = map[b[k]];
+                if (x != y) {
+                    ra[k] = x;
+                    rb[k] = y;
+                    ++kept;
+                    const uint64_t key = ((uint64_t)w[k] << 32) | (uint64_t)(e0 + k);
+                    atomic_min_key(&bst[x], key);
+                    atomic_min_key(&bst[y], key);
+                }
+            }
+        }
+        if constexpr (OUT == kOut32) {
+            if (full) {
+                reinterpret_cast<int4*>(ou)[q] = make_int4(ra[0], ra[1], ra[2], ra[3]);
+                reinterpret_cast<int4*>(ov)[q] = make_int4(rb[0], rb[1], rb[2], rb[3]);
+            } else {
+                for (int k = 0; k < 4; ++k)
+                    if (e0 + k < m) { ou[e0 + k] = ra[k]; ov[e0 + k] = rb[k]; }
+            }
+        } else if constexpr (OUT == kOut16) {
+            uint32_t pk[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pk[k] = (uint32_t)ra[k] | ((uint32_t)rb[k] << 16);
+            if (full) {
+                reinterpret_cast<uint4*>(op16)[q] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+            } else {
+                for (int k = 0; k < 4; ++k)
+                    if (e0 + k < m) op16[e0 + k] = pk[k];
+            }
+        }
+    }
+    const uint64_t wk = wave_sum_u64(kept);
+    if (lane_id() == 0 && wk) atomicAdd((unsigned long long*)&ctrl->m_next, (unsigned long long)wk);
+    if constexpr (LDS_B) {
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < nn; i += blockDim.x) {
+            const uint64_t k = s_best[i];
+            if (k != kKeyMax) atomic_min_key(&best_next[i], k);
+        }
+    }
+}
+
+// ----------------------------------------------------------- compaction pass
+
+// Relabel through M, drop self-loops and compact the survivors stably into
+// `out` (position order stays edge-id order).  FUSED: each survivor takes
+// part in the next round's minedge with key (w << 32 | new position).  All
+// inputs of a tile are read before its lookback completes and outputs land at
+// or before their inputs, so `out` may alias the view (in-place compaction).
+template <int IN, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_compact(View g, const int32_t* __restrict__ M,
+                                                    EdgeSoA out, uint64_t* __restrict__ best_next,
+                                                    uint64_t* status, Ctrl* ctrl,
+                                                    uint32_t ntiles) {
     constexpr int kIt = kRelabelItems;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wave[kBlock / kWave];
@@ -206,27 +403,37 @@ __global__ __launch_bounds__(kBlock) void k_relabel(
     const uint32_t tile = take_tile(ctrl, &s_tile);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t e0 = (int64_t)tile * (kBlock * kIt) + (int64_t)wave * (kWave * kIt) + lane;
+    const int64_t mr = g.len;
     int32_t a[kIt], b[kIt];
+    uint32_t wt[kIt], id[kIt];
     uint64_t mk[kIt];
     uint32_t cnt = 0;
 #pragma unroll
     for (int k = 0; k < kIt; ++k) {
         const int64_t e = e0 + k * kWave;
         a[k] = b[k] = 0;
-        if (e < mr) { a[k] = U[e]; b[k] = V[e]; }
+        wt[k] = id[k] = 0;
+        if (e < mr) {
+            load_ends<IN>(g, e, a[k], b[k]);
+            wt[k] = g.w[e];
+            id[k] = edge_id<IN>(g, e);
+        }
     }
 #pragma unroll
     for (int k = 0; k < kIt; ++k) {
         const int64_t e = e0 + k * kWave;
         bool keep = false;
-        if (e < mr) {
-            a[k] = label[a[k]];
-            b[k] = label[b[k]];
+        if (e < mr && a[k] != b[k]) {
+            a[k] = M[a[k]];
+            b[k] = M[b[k]];
             keep = a[k] != b[k];
         }
         mk[k] = __ballot(keep);
         cnt += __popcll(mk[k]);
     }
+    // Every load of this tile has returned before the tile's aggregate is
+    // published (in-place use: later tiles may overwrite these positions).
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     if (lane == 0) s_wave[wave] = cnt;
     __syncthreads();
     uint32_t agg = 0, woff = 0;
@@ -242,14 +449,15 @@ __global__ __launch_bounds__(kBlock) void k_relabel(
         const int64_t e = e0 + k * kWave;
         if ((mk[k] >> lane) & 1) {
             const uint64_t o = off + lanes_below(mk[k]);
-            const uint32_t wt = W[e];
             out.u[o] = a[k];
             out.v[o] = b[k];
-            out.w[o] = wt;
-            out.id[o] = kR0 ? (uint32_t)e : ID[e];
-            const uint64_t key = ((uint64_t)wt << 32) | o;
-            atomic_min_key(&best_next[a[k]], key);
-            atomic_min_key(&best_next[b[k]], key);
+            out.w[o] = wt[k];
+            out.id[o] = id[k];
+            if constexpr (FUSED) {
+                const uint64_t key = ((uint64_t)wt[k] << 32) | o;
+                atomic_min_key(&best_next[a[k]], key);
+                atomic_min_key(&best_next[b[k]], key);
+            }
         }
         off += __popcll(mk[k]);
     }
@@ -278,18 +486,24 @@ void launch_scan_prep(uint64_t* status, int64_t ntiles, Ctrl* ctrl, int round_be
 }
 void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
                        int64_t n, uint64_t* best, Ctrl* ctrl, hipStream_t s) {
-    if (m > 0)
-        hipLaunchKernelGGL(k_minedge_r0, dim3(grid_for(m)), dim3(kBlock), 0, s, u, v, w, m, n,
-                           best, ctrl);
-}
-void launch_hook(bool r0, const uint64_t* best, int64_t nr, const int32_t* U, const int32_t* V,
-                 const uint32_t* ID, int32_t* parent, uint8_t* mask, Ctrl* ctrl, hipStream_t s) {
-    if (r0)
-        hipLaunchKernelGGL(k_hook<true>, dim3(grid_for(nr)), dim3(kBlock), 0, s, best, nr, U, V,
-                           ID, parent, mask, ctrl);
+    if (m <= 0) return;
+    const bool aligned = (((uintptr_t)u | (uintptr_t)v | (uintptr_t)w) & 15) == 0;
+    if (aligned)
+        hipLaunchKernelGGL(k_minedge_r0<4>, dim3(grid_for((m + 3) / 4)), dim3(kBlock), 0, s, u,
+                           v, w, m, n, best, ctrl);
     else
-        hipLaunchKernelGGL(k_hook<false>, dim3(grid_for(nr)), dim3(kBlock), 0, s, best, nr, U,
-                           V, ID, parent, mask, ctrl);
+        hipLaunchKernelGGL(k_minedge_r0<1>, dim3(grid_for(m)), dim3(kBlock), 0, s, u, v, w, m,
+                           n, best, ctrl);
+}
+void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
+                 int32_t* parent, uint8_t* mask, Ctrl* ctrl, hipStream_t s) {
+    const dim3 gr(grid_for(nr)), bl(kBlock);
+    switch (mode) {
+        case kOrig: hipLaunchKernelGGL(k_hook<kOrig>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+        case kFull32: hipLaunchKernelGGL(k_hook<kFull32>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+        case kFull16: hipLaunchKernelGGL(k_hook<kFull16>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+        default: hipLaunchKernelGGL(k_hook<kCompact>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+    }
 }
 void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s) {
     hipLaunchKernelGGL(k_jump, dim3(grid_for(nr)), dim3(kBlock), 0, s, parent, nr, iters, ctrl);
@@ -305,16 +519,112 @@ void launch_label(const int32_t* parent, const uint64_t* best, int64_t nr, int32
     hipLaunchKernelGGL(k_label, dim3(grid_for(nr)), dim3(kBlock), 0, s, parent, best, nr, label,
                        best_next, ctrl);
 }
-void launch_relabel(bool r0, const int32_t* U, const int32_t* V, const uint32_t* W,
-                    const uint32_t* ID, int64_t mr, const int32_t* label, EdgeSoA out,
-                    uint64_t* best_next, uint64_t* status, Ctrl* ctrl, hipStream_t s) {
-    const uint32_t nt = (uint32_t)((mr + kRelabelTile - 1) / kRelabelTile);
-    if (r0)
-        hipLaunchKernelGGL(k_relabel<true>, dim3(nt), dim3(kBlock), 0, s, U, V, W, ID, mr, label,
-                           out, best_next, status, ctrl, nt);
+void launch_compose(const int32_t* cmap, int64_t nc, const int32_t* label, int32_t* out,
+                    hipStream_t s) {
+    if (nc > 0)
+        hipLaunchKernelGGL(k_compose, dim3(grid_for(nc)), dim3(kBlock), 0, s, cmap, nc, label, out);
+}
+
+void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_t* label,
+                       int64_t nr, const int32_t* orig_cur, int32_t* orig_next, int32_t* rep,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_rep_update, dim3(grid_for(nr)), dim3(kBlock), 0, s, parent, best, label,
+                       nr, orig_cur, orig_next, rep);
+}
+
+// LDS budget of one pass workgroup (two fit in a CU's 160 KiB).
+constexpr int64_t kPassLds = 72 * 1024;
+
+// Raises the dynamic-LDS limit of one pass instantiation once (needed above
+// 64 KiB); returns false when the runtime refuses.
+template <int IN, int OUT, bool LM, bool LB>
+static bool allow_lds(size_t bytes) {
+    if (bytes <= 64 * 1024) return true;
+    static bool tried = false, ok = false;
+    if (!tried) {
+        tried = true;
+        ok = hipFuncSetAttribute((const void*)k_pass<IN, OUT, LM, LB>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)kPassLds) == hipSuccess;
+        if (!ok) (void)hipGetLastError();
+    }
+    return ok;
+}
+
+// MSF_PASS_LDS=0 turns LDS staging off (a tuning and diagnosis knob).
+static bool lds_enabled() {
+    static int on = -1;
+    if (on < 0) {
+        const char* e = getenv("MSF_PASS_LDS");
+        on = (e && e[0] == '0') ? 0 : 1;
+    }
+    return on == 1;
+}
+
+template <int IN, int OUT>
+static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* ou, int32_t* ov,
+                          uint32_t* op16, uint64_t* best_next, int64_t nn, Ctrl* ctrl,
+                          hipStream_t s) {
+    const bool lds_on = lds_enabled();
+    bool ldsb = lds_on && nn * 8 <= kPassLds;
+    bool ldsm = lds_on && nc * 4 + (ldsb ? nn * 8 : 0) <= kPassLds;
+    size_t lds = (ldsb ? nn * 8 : 0) + (ldsm ? nc * 4 : 0);
+    bool ok = true;
+    if (ldsb && ldsm) ok = allow_lds<IN, OUT, true, true>(lds);
+    else if (ldsb) ok = allow_lds<IN, OUT, false, true>(lds);
+    else if (ldsm) ok = allow_lds<IN, OUT, true, false>(lds);
+    if (!ok) {   // stay within 64 KiB
+        ldsb = lds_on && nn * 8 <= 64 * 1024;
+        ldsm = lds_on && nc * 4 + (ldsb ? nn * 8 : 0) <= 64 * 1024;
+        lds = (ldsb ? nn * 8 : 0) + (ldsm ? nc * 4 : 0);
+    }
+    const int64_t groups = (g.len + 3) / 4;
+    unsigned grid = grid_for(groups, lds ? 512 : 2048);
+    const dim3 bl(kBlock);
+    if (ldsb && ldsm)
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, true>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, ctrl);
+    else if (ldsb)
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, true>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, ctrl);
+    else if (ldsm)
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, false>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, ctrl);
     else
-        hipLaunchKernelGGL(k_relabel<false>, dim3(nt), dim3(kBlock), 0, s, U, V, W, ID, mr,
-                           label, out, best_next, status, ctrl, nt);
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, false>), dim3(grid), bl, 0, s, g, M, nc, ou, ov, op16, best_next, nn, ctrl);
+}
+
+// Streaming pass; returns false for a layout/output pair it does not support.
+bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t nc, int32_t* ou,
+                 int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, Ctrl* ctrl,
+                 hipStream_t s) {
+    if (g.len <= 0) return true;
+    switch (in_mode * 3 + out) {
+        case kOrig * 3 + kOut32: pass_dispatch<kOrig, kOut32>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
+        case kOrig * 3 + kOut16: pass_dispatch<kOrig, kOut16>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
+        case kFull32 * 3 + kOutNone: pass_dispatch<kFull32, kOutNone>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
+        case kFull32 * 3 + kOut16: pass_dispatch<kFull32, kOut16>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
+        case kFull16 * 3 + kOutNone: pass_dispatch<kFull16, kOutNone>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
+        case kCompact * 3 + kOutNone: pass_dispatch<kCompact, kOutNone>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
+        default: return false;
+    }
+}
+
+void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
+                    uint64_t* best_next, uint64_t* status, Ctrl* ctrl, hipStream_t s) {
+    if (g.len <= 0) return;
+    const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
+    const dim3 gr(nt), bl(kBlock);
+    if (!best_next) {   // relabel + compact only (Filter-Borůvka's heavy-edge filter)
+        if (in_mode == kOrig)
+            hipLaunchKernelGGL((k_compact<kOrig, false>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt);
+        else
+            hipLaunchKernelGGL((k_compact<kCompact, false>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt);
+        return;
+    }
+    switch (in_mode) {
+        case kOrig: hipLaunchKernelGGL((k_compact<kOrig, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;
+        case kFull32: hipLaunchKernelGGL((k_compact<kFull32, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;
+        case kFull16: hipLaunchKernelGGL((k_compact<kFull16, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;
+        default: hipLaunchKernelGGL((k_compact<kCompact, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;
+    }
 }
 
 }  // namespace msf

@@ -30,7 +30,11 @@ struct Ctrl {
     uint64_t msf_edges;      // MSF edges so far
     uint64_t live;           // vertices with an incident edge, this round
     uint64_t found;          // MSF edges marked this round
-    uint64_t aux[8];         // scratch counters for the filter driver
+    uint64_t light;          // filter: edges with key <= pivot
+    uint64_t pivot;          // filter: pivot key of the current split
+    float q_used;            // filter: sample quantile used
+    uint32_t pad1;
+    uint64_t aux[6];         // spare
 };
 
 // Lookback status word: 2 flag bits over a 62-bit inclusive/aggregate value.
@@ -48,5 +52,28 @@ struct EdgeSoA {
     uint32_t* w;
     uint32_t* id;
 };
+
+// How the edges of the current graph are stored.  In every layout the
+// position of an edge is increasing in its id, so (w << 32 | position) is a
+// key with the paper's tie break.
+//   kOrig     the caller's arrays: u, v, w; id = position
+//   kFull32   int32 endpoint labels for every input edge (dead edges hold an
+//             equal pair); w = caller's w; id = position
+//   kFull16   both endpoint labels packed into one uint32 (a | b << 16) for
+//             every input edge, usable once labels fit in 16 bits
+//   kCompact  only live edges, stably compacted: u, v, w, id arrays
+enum ViewMode { kOrig = 0, kFull32 = 1, kFull16 = 2, kCompact = 3 };
+
+struct View {
+    const int32_t* u;
+    const int32_t* v;
+    const uint32_t* p16;
+    const uint32_t* w;
+    const uint32_t* id;
+    int64_t len;        // positions in the arrays
+};
+
+// Outputs of a streaming pass.
+enum PassOut { kOutNone = 0, kOut32 = 1, kOut16 = 2 };
 
 }  // namespace msf

@@ -1,0 +1,40 @@
+// Borůvka round driver (paper Sec. II-C, Alg. 1's round loop) on one GPU.
+#pragma once
+#include "host.h"
+#include "launch.h"
+
+namespace msf {
+
+// Device buffers of the round loop, carved out of the caller's workspace.
+struct EngineBuffers {
+    Ctrl* ctrl;
+    uint64_t* status;     // lookback tile status words
+    uint64_t* best[2];    // lightest-edge keys, this round / next round
+    int32_t* parent;
+    int32_t* lab[2];      // per-round label arrays (alternating)
+    int32_t* map[2];      // composed label maps (alternating)
+    int32_t* orig[2];     // representative-tracking: input vertex of each round vertex
+    int32_t* f32u;        // kFull32 layout
+    int32_t* f32v;
+    uint32_t* p16;        // kFull16 layout
+    EdgeSoA cbuf[2];      // kCompact layouts (alternating)
+    int64_t ncap, mcap;
+};
+
+size_t engine_bytes(int64_t m, int64_t n);
+// Carves buffers starting at ws; returns the bytes used.
+size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B);
+
+// Runs Borůvka rounds until no edge is left.
+//   view/mode   the current graph: kOrig (the caller's arrays; round 0 runs
+//               the lightest-edge pass first) or kCompact (ids already set)
+//   nv          vertex ids of the view are in [0, nv)
+//   rep         optional int32[nv]: representative tracking for Filter-
+//               Borůvka.  rep[x] = x on entry for the vertices in the view;
+//               on return every vertex that was contracted points (directly
+//               or through a chain) to the vertex it was merged into.
+// Marks MSF edges in mask[] and accumulates total/msf_edges in B.ctrl.
+int engine_solve(EngineBuffers& B, int mode, const View& view, int64_t nv, uint8_t* mask,
+                 int32_t* rep, hipStream_t s, msf_stats* stats);
+
+}  // namespace msf

@@ -1,0 +1,273 @@
+// Borůvka round loop on one GPU (paper Sec. II-C; the while loop of Alg. 1).
+//
+// Each round: hook + 2-cycle break + MSF marking, pointer jumping, dense
+// relabelling of the roots, then one streaming pass over the edges that
+// relabels them, drops self-loops and runs the next round's lightest-edge
+// search.  The host reads two small counter blocks per round to size the
+// next launches; everything else stays on the device.
+//
+// Edge layout policy (all layouts keep position order = edge-id order):
+//   * after round 0 the caller's arrays are rewritten once as label pairs
+//     (16-bit packed when the next round has <= 65535 vertices), so later
+//     passes gather from small label tables instead of the n-sized one;
+//   * while most positions still hold live edges, later passes write nothing
+//     and compose the label maps instead (parallel edges and self-loops are
+//     cheap to skip, a rewrite is not);
+//   * once fewer than half of the positions are live, the survivors are
+//     compacted (stable, decoupled lookback).
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "engine.h"
+
+namespace msf {
+
+namespace {
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr double kCompactBelow = 0.5;   // compact when live / positions drops below this
+constexpr int64_t kMax16 = 65535;       // label count that still fits the packed layout
+}  // namespace
+
+size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes ? bytes : 1);
+        return ws ? ws + o : nullptr;
+    };
+    const size_t nn = (size_t)(n > 0 ? n : 1), mm = (size_t)(m > 0 ? m : 1);
+    const int64_t tile_min = kTile < kRelabelTile ? kTile : kRelabelTile;
+    const size_t tiles = (size_t)((std::max<int64_t>(m, n) + tile_min - 1) / tile_min) + 1;
+    EngineBuffers b;
+    b.ctrl = (Ctrl*)take(sizeof(Ctrl));
+    b.status = (uint64_t*)take(tiles * 8);
+    for (int i = 0; i < 2; ++i) b.best[i] = (uint64_t*)take(nn * 8);
+    b.parent = (int32_t*)take(nn * 4);
+    for (int i = 0; i < 2; ++i) b.lab[i] = (int32_t*)take(nn * 4);
+    for (int i = 0; i < 2; ++i) b.map[i] = (int32_t*)take(nn * 4);
+    for (int i = 0; i < 2; ++i) b.orig[i] = (int32_t*)take(nn * 4);
+    b.f32u = (int32_t*)take(mm * 4);
+    b.f32v = (int32_t*)take(mm * 4);
+    b.p16 = (uint32_t*)take(mm * 4);
+    for (int i = 0; i < 2; ++i) {
+        b.cbuf[i].u = (int32_t*)take(mm * 4);
+        b.cbuf[i].v = (int32_t*)take(mm * 4);
+        b.cbuf[i].w = (uint32_t*)take(mm * 4);
+        b.cbuf[i].id = (uint32_t*)take(mm * 4);
+    }
+    b.ncap = n;
+    b.mcap = m;
+    if (B) *B = b;
+    return off;
+}
+
+size_t engine_bytes(int64_t m, int64_t n) { return engine_carve(nullptr, m, n, nullptr); }
+
+// MSF_ALWAYS_COMPACT=1 compacts after every round (a tuning and diagnosis knob).
+static bool always_compact() {
+    static int on = -1;
+    if (on < 0) {
+        const char* e = getenv("MSF_ALWAYS_COMPACT");
+        on = (e && e[0] == '1') ? 1 : 0;
+    }
+    return on == 1;
+}
+
+// MSF_DUMP_DIR=<dir> writes each round's parent, label, map and next-best
+// arrays to <dir>/<round>_<name>.bin (a diagnosis aid; off by default).
+static const char* dump_dir() {
+    static int init = 0;
+    static const char* d = nullptr;
+    if (!init) { init = 1; d = getenv("MSF_DUMP_DIR"); }
+    return d;
+}
+
+static void dump(const char* name, uint32_t round, const void* dev, size_t bytes, hipStream_t s) {
+    const char* d = dump_dir();
+    if (!d || bytes == 0) return;
+    void* h = malloc(bytes);
+    if (!h) return;
+    if (hipMemcpyAsync(h, dev, bytes, hipMemcpyDeviceToHost, s) == hipSuccess &&
+        hipStreamSynchronize(s) == hipSuccess) {
+        char path[512];
+        snprintf(path, sizeof path, "%s/%02u_%s.bin", d, round, name);
+        FILE* f = fopen(path, "wb");
+        if (f) { fwrite(h, 1, bytes, f); fclose(f); }
+    }
+    free(h);
+}
+
+static double view_read_bytes(int mode) { return mode == kFull16 ? 8.0 : 12.0; }
+
+int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint8_t* mask,
+                 int32_t* rep, hipStream_t s, msf_stats* stats) {
+    Ctrl* hc = host_ctrl();
+    Ctrl* dc = B.ctrl;
+    View view = view0;
+    const int32_t* cmap = nullptr;   // stored labels -> this round's labels (null: identity)
+    int64_t nc = nv;                 // size of the stored-label space
+    int cur = 0, labsel = 0, mapsel = 0, cbsel = 0, origsel = 0;
+    int64_t nr = nv;
+    int st;
+
+    // Round 0 lightest edges (on the caller's arrays, or on a compact view
+    // whose positions are already in id order).
+    int h = prof_begin(K_FILL, s);
+    launch_fill_u64(B.best[cur], nr, kKeyMax, s);
+    prof_end(h, s, 8.0 * nr);
+    h = prof_begin(K_MINEDGE_R0, s);
+    launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, s);
+    prof_end(h, s, 12.0 * view.len + 8.0 * nv);
+    HIP_TRY(hipGetLastError());
+    if ((st = read_ctrl(dc, hc, s))) return st;
+    if (hc->err & kErrRange) return MSF_ERANGE;
+
+    int64_t m_live = view.len;
+    uint32_t rounds = stats ? stats->rounds : 0;
+    const uint32_t first_round = rounds;
+    while (m_live > 0) {
+        launch_scan_prep(B.status, 0, dc, 1, s);
+        const int hh = prof_begin(K_HOOK, s);
+        launch_hook(mode, B.best[cur], nr, view, cmap, B.parent, mask, dc, s);
+        prof_end(hh, s, 12.0 * nr);
+        int32_t* lab = B.lab[labsel];
+        for (int attempt = 0;; ++attempt) {
+            h = prof_begin(K_JUMP, s);
+            launch_jump(B.parent, nr, 32, dc, s);
+            prof_end(h, s, 12.0 * nr);
+            const int64_t ntv = (nr + kTile - 1) / kTile;
+            launch_scan_prep(B.status, ntv, dc, 0, s);
+            h = prof_begin(K_SCAN_ROOTS, s);
+            launch_scan_roots(B.parent, B.best[cur], nr, lab, B.status, dc, s);
+            prof_end(h, s, 12.0 * nr);
+            h = prof_begin(K_LABEL, s);
+            launch_label(B.parent, B.best[cur], nr, lab, B.best[cur ^ 1], dc, s);
+            prof_end(h, s, 16.0 * nr);
+            HIP_TRY(hipGetLastError());
+            if ((st = read_ctrl(dc, hc, s))) return st;
+            if (!hc->jump_more) break;
+            if (attempt > 64) {
+                set_err_text("pointer jumping did not converge");
+                return MSF_EINTERNAL;
+            }
+            HIP_TRY(hipMemsetAsync(&dc->jump_more, 0, sizeof(uint32_t), s));
+        }
+        if (hc->err) {
+            char buf[96];
+            snprintf(buf, sizeof buf, "device error bits 0x%x in round %u", hc->err, rounds);
+            set_err_text(buf);
+            return MSF_EINTERNAL;
+        }
+        const uint64_t live = hc->live, found = hc->found;
+        const int64_t nn = (int64_t)hc->n_next;
+        prof_add(K_HOOK, 17.0 * live);
+        prof_add(K_SCAN_ROOTS, 4.0 * nn);
+        prof_add(K_LABEL, 8.0 * nn);
+        if (stats && rounds < MSF_MAX_TRACE) {
+            stats->round_live[rounds] = live;
+            stats->round_edges[rounds] = (uint64_t)m_live;
+            stats->round_found[rounds] = found;
+        }
+        ++rounds;
+
+        if (rep) {
+            launch_rep_update(B.parent, B.best[cur], lab, nr, rounds - 1 == first_round ? nullptr : B.orig[origsel],
+                              B.orig[origsel ^ 1], rep, s);
+            origsel ^= 1;
+        }
+
+        if (dump_dir() && mode == kCompact) {
+            dump("view_u", rounds - 1, view.u, view.len * 4, s);
+            dump("view_v", rounds - 1, view.v, view.len * 4, s);
+            dump("view_id", rounds - 1, view.id, view.len * 4, s);
+        }
+        // M: stored labels -> next-round labels.
+        const int32_t* M = lab;
+        if (cmap) {
+            h = prof_begin(K_COMPOSE, s);
+            launch_compose(cmap, nc, lab, B.map[mapsel], s);
+            prof_end(h, s, 12.0 * nc);
+            M = B.map[mapsel];
+            mapsel ^= 1;
+        }
+        // the streaming pass uses 16-byte vector loads
+        const bool aligned = ((((uintptr_t)view.u | (uintptr_t)view.v | (uintptr_t)view.w |
+                                (uintptr_t)view.p16 | (uintptr_t)view.id) & 15) == 0);
+        const bool compact = !aligned || always_compact() ||
+                             (mode != kOrig && (double)m_live < kCompactBelow * (double)view.len);
+        View next = view;
+        int next_mode = mode;
+        const int32_t* next_cmap = nullptr;
+        int64_t next_nc = nn;
+        HIP_TRY(hipMemsetAsync(&dc->m_next, 0, sizeof(uint64_t), s));
+        if (compact) {
+            EdgeSoA out = B.cbuf[cbsel];
+            cbsel ^= 1;
+            const int64_t nte = (view.len + kRelabelTile - 1) / kRelabelTile;
+            launch_scan_prep(B.status, nte, dc, 0, s);
+            h = prof_begin(K_COMPACT, s);
+            launch_compact(mode, view, M, out, B.best[cur ^ 1], B.status, dc, s);
+            prof_end(h, s, view_read_bytes(mode) * view.len + 8.0 * m_live);
+            next.u = out.u; next.v = out.v; next.w = out.w; next.id = out.id; next.p16 = nullptr;
+            next_mode = kCompact;
+        } else {
+            int out = kOutNone;
+            if (mode == kOrig) out = nn <= kMax16 ? kOut16 : kOut32;
+            else if (mode == kFull32 && nn <= kMax16) out = kOut16;
+            h = prof_begin(K_PASS, s);
+            if (!launch_pass(mode, out, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1], nn,
+                             dc, s)) {
+                set_err_text("unsupported pass layout");
+                return MSF_EINTERNAL;
+            }
+            prof_end(h, s, view_read_bytes(mode) * view.len + 8.0 * m_live +
+                               (out == kOut32 ? 8.0 : out == kOut16 ? 4.0 : 0.0) * view.len +
+                               8.0 * nn);
+            if (out == kOut32) {
+                next.u = B.f32u; next.v = B.f32v; next.p16 = nullptr; next_mode = kFull32;
+            } else if (out == kOut16) {
+                next.p16 = B.p16; next.u = next.v = nullptr; next_mode = kFull16;
+            } else {
+                next_cmap = M;
+                next_nc = nc;
+            }
+        }
+        HIP_TRY(hipGetLastError());
+        if ((st = read_ctrl(dc, hc, s))) return st;
+        if (hc->err) {
+            set_err_text("device error bits after the relabel pass");
+            return MSF_EINTERNAL;
+        }
+        if (dump_dir()) {
+            dump("parent", rounds - 1, B.parent, nr * 4, s);
+            dump("label", rounds - 1, lab, nr * 4, s);
+            dump("map", rounds - 1, M, (cmap ? nc : nr) * 4, s);
+            dump("best_next", rounds - 1, B.best[cur ^ 1], nn * 8, s);
+            dump("best_cur", rounds - 1, B.best[cur], nr * 8, s);
+        }
+        m_live = (int64_t)hc->m_next;
+        if (compact) {     // only a compaction changes the number of positions
+            next.len = m_live;
+            prof_add(K_COMPACT, 16.0 * m_live);
+        }
+        view = next;
+        mode = next_mode;
+        cmap = next_cmap;
+        nc = next_nc;
+        nr = nn;
+        cur ^= 1;
+        labsel ^= 1;
+        if (rounds - first_round > 70) {
+            set_err_text("too many rounds");
+            return MSF_EINTERNAL;
+        }
+    }
+    if (stats) stats->rounds = rounds;
+    return MSF_OK;
+}
+
+}  // namespace msf

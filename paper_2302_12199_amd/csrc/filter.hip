@@ -1,0 +1,418 @@
+// Filter-Borůvka (paper Sec. V, Alg. 2) on one GPU.
+//
+//   Rec-Filter-MST(E):
+//     if isSparse(E): Borůvka base case on E, recording representatives in P
+//     pivot  <- sample quantile of the keys of E            (PivotSelection)
+//     E<=, E> <- stable split of E by key <= pivot
+//     Rec-Filter-MST(E<=)
+//     E>'    <- {(P[u], P[v]) : (u, v) in E>, P[u] != P[v]} (Filter)
+//     Rec-Filter-MST(E>')
+//
+// Keys are (w << 32 | edge id); comparing whole keys (not only weights) keeps
+// the split proper even when many weights tie.  Every layout keeps edges in
+// id order, so the base case may again use positions as tie-break keys.
+#include <string.h>
+
+#include <algorithm>
+
+#include "filter.h"
+#include "prim.h"
+
+namespace msf {
+
+namespace {
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ULL;
+constexpr uint64_t kPivotTag = 0x50495654ULL;   // stream tag of the pivot sampler
+constexpr int kSampleMax = 8192;
+constexpr int kSampleThreads = 1024;
+constexpr int kMaxDepth = 48;
+}  // namespace
+
+// SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014).
+__host__ __device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t pivot_stream_base(uint64_t seed, uint32_t split) {
+    return sm_mix(sm_mix(seed) ^ (kPivotTag + split));
+}
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void k_iota(int32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+template <int MODE>
+__device__ __forceinline__ uint64_t key_at(const View& g, int64_t p) {
+    const uint64_t id = MODE == kCompact ? (uint64_t)g.id[p] : (uint64_t)p;
+    return ((uint64_t)g.w[p] << 32) | id;
+}
+
+// Pivot selection: `sample` keys drawn with replacement at positions
+// floor(r_i * len / 2^64), r_i the i-th output of the counter-based stream
+// `base`; bitonic sort in LDS; pivot = sorted[floor(q * (sample - 1))].
+// One workgroup.  q comes from q_dev when given (the pivot network's output,
+// already clamped), else from the argument.
+template <int MODE>
+__global__ __launch_bounds__(kSampleThreads) void k_sample_pivot(View g, uint64_t base,
+                                                                 int sample, float q,
+                                                                 const float* q_dev,
+                                                                 Ctrl* ctrl) {
+    __shared__ uint64_t keys[kSampleMax];
+    int p2 = 1;
+    while (p2 < sample) p2 <<= 1;
+    const uint64_t len = (uint64_t)g.len;
+    for (int i = threadIdx.x; i < p2; i += blockDim.x) {
+        uint64_t k = kKeyMax;
+        if (i < sample) {
+            const uint64_t r = sm_mix(base + (uint64_t)(i + 1) * kGamma);
+            const uint64_t pos = __umul64hi(r, len);
+            k = key_at<MODE>(g, (int64_t)pos);
+        }
+        keys[i] = k;
+    }
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < p2; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t a = keys[i], b = keys[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) { keys[i] = b; keys[ixj] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        const float qq = q_dev ? *q_dev : q;
+        int idx = (int)floor((double)qq * (double)(sample - 1));
+        if (idx < 0) idx = 0;
+        if (idx > sample - 1) idx = sample - 1;
+        ctrl->pivot = keys[idx];
+        ctrl->q_used = qq;
+    }
+}
+
+// Light-edge count of a split (key <= pivot), accumulated into ctrl->light.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_count_light(View g,
+                                                        const uint64_t* __restrict__ pivot_dev,
+                                                        Ctrl* ctrl) {
+    const uint64_t pivot = *pivot_dev;
+    uint64_t c = 0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < g.len;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t id = MODE == kCompact ? (uint64_t)g.id[e] : (uint64_t)e;
+        c += (((uint64_t)g.w[e] << 32) | id) <= pivot;
+    }
+    c = wave_sum_u64(c);
+    if (lane_id() == 0 && c) atomicAdd((unsigned long long*)&ctrl->light, (unsigned long long)c);
+}
+
+// Stable two-way split by key <= pivot with one decoupled-lookback scan over
+// the light flags: a light edge goes to out[#light before it], a heavy one to
+// out[nl' + #heavy before it] (nl' = ctrl->light from the count pass rounded
+// up to a multiple of 4, so both parts start 16-byte aligned).  On the
+// caller's arrays the ids are validated.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_split(View g, int64_t n,
+                                                  const uint64_t* __restrict__ pivot_dev,
+                                                  EdgeSoA out, uint64_t* status, Ctrl* ctrl,
+                                                  uint32_t ntiles) {
+    constexpr int kIt = kRelabelItems;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wave[kBlock / kWave];
+    __shared__ uint64_t s_prefix;
+    const uint32_t tile = take_tile(ctrl, &s_tile);
+    const uint64_t pivot = *pivot_dev;
+    const uint64_t nl_al = (ctrl->light + 3) & ~3ull;   // heavy part starts 16-byte aligned
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t e0 = (int64_t)tile * (kBlock * kIt) + (int64_t)wave * (kWave * kIt) + lane;
+    const int64_t m = g.len;
+    int32_t a[kIt], b[kIt];
+    uint32_t w[kIt];
+    uint64_t mk[kIt];
+    uint32_t cnt = 0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        const int64_t e = e0 + k * kWave;
+        a[k] = b[k] = 0;
+        w[k] = 0;
+        bool lt = false;
+        if (e < m) {
+            a[k] = g.u[e];
+            b[k] = g.v[e];
+            w[k] = g.w[e];
+            if (MODE == kOrig && ((uint32_t)a[k] >= (uint64_t)n || (uint32_t)b[k] >= (uint64_t)n)) {
+                bad = true;
+                a[k] = b[k] = 0;
+            }
+            const uint64_t id = MODE == kCompact ? (uint64_t)g.id[e] : (uint64_t)e;
+            lt = (((uint64_t)w[k] << 32) | id) <= pivot;
+        }
+        mk[k] = __ballot(lt);
+        cnt += __popcll(mk[k]);
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(&ctrl->err, kErrRange);
+    if (lane == 0) s_wave[wave] = cnt;
+    __syncthreads();
+    uint32_t agg = 0, woff = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i) {
+        if (i < wave) woff += s_wave[i];
+        agg += s_wave[i];
+    }
+    const uint64_t prefix = tile_prefix(status, tile, agg, ctrl, &s_prefix);
+    uint64_t off = prefix + woff;
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        const int64_t e = e0 + k * kWave;
+        if (e < m) {
+            const uint64_t before = off + lanes_below(mk[k]);   // light edges before e
+            const uint32_t id = MODE == kCompact ? g.id[e] : (uint32_t)e;
+            const uint64_t o = ((mk[k] >> lane) & 1) ? before : nl_al + ((uint64_t)e - before);
+            out.u[o] = a[k];
+            out.v[o] = b[k];
+            out.w[o] = w[k];
+            out.id[o] = id;
+        }
+        off += __popcll(mk[k]);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned grid_cap(int64_t n, unsigned cap = 2048) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    return (unsigned)(g < cap ? g : cap);
+}
+
+void launch_iota(int32_t* p, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_iota, dim3(grid_cap(n)), dim3(kBlock), 0, s, p, n);
+}
+
+void launch_sample_pivot(int in_mode, const View& g, uint64_t base, int sample, float q,
+                         const float* q_dev, Ctrl* ctrl, hipStream_t s) {
+    if (in_mode == kOrig)
+        hipLaunchKernelGGL(k_sample_pivot<kOrig>, dim3(1), dim3(kSampleThreads), 0, s, g, base,
+                           sample, q, q_dev, ctrl);
+    else
+        hipLaunchKernelGGL(k_sample_pivot<kCompact>, dim3(1), dim3(kSampleThreads), 0, s, g,
+                           base, sample, q, q_dev, ctrl);
+}
+
+void launch_count_light(int in_mode, const View& g, const uint64_t* pivot_dev, Ctrl* ctrl,
+                        hipStream_t s) {
+    if (g.len <= 0) return;
+    if (in_mode == kOrig)
+        hipLaunchKernelGGL(k_count_light<kOrig>, dim3(grid_cap(g.len)), dim3(kBlock), 0, s, g,
+                           pivot_dev, ctrl);
+    else
+        hipLaunchKernelGGL(k_count_light<kCompact>, dim3(grid_cap(g.len)), dim3(kBlock), 0, s, g,
+                           pivot_dev, ctrl);
+}
+
+void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_dev, EdgeSoA out,
+                  uint64_t* status, Ctrl* ctrl, hipStream_t s) {
+    if (g.len <= 0) return;
+    const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
+    if (in_mode == kOrig)
+        hipLaunchKernelGGL(k_split<kOrig>, dim3(nt), dim3(kBlock), 0, s, g, n, pivot_dev, out,
+                           status, ctrl, nt);
+    else
+        hipLaunchKernelGGL(k_split<kCompact>, dim3(nt), dim3(kBlock), 0, s, g, n, pivot_dev, out,
+                           status, ctrl, nt);
+}
+
+// ------------------------------------------------------------------ driver
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Two edge buffers X, Y of m + 4 edges each.  A graph being split lives at
+// [0, len) of one buffer (or in the caller's arrays at the top level); its
+// split [light | heavy] goes to [0, len) of the other buffer.  Down the light
+// recursion the lengths only shrink, so a split never reaches the heavy part
+// an ancestor left at offset >= its light count; the filtered heavy edges are
+// compacted leftwards to [0, kept) of their buffer before recursing on them.
+size_t buffer_bytes(int64_t m) { return 4 * align_up((size_t)((m > 0 ? m : 1) + 4) * 4); }
+
+EdgeSoA carve_buffer(char* p, int64_t m) {
+    const size_t one = align_up((size_t)((m > 0 ? m : 1) + 4) * 4);
+    EdgeSoA e;
+    e.u = (int32_t*)p;
+    e.v = (int32_t*)(p + one);
+    e.w = (uint32_t*)(p + 2 * one);
+    e.id = (uint32_t*)(p + 3 * one);
+    return e;
+}
+
+struct Ctx {
+    EngineBuffers B;
+    EdgeSoA buf[2];
+    int32_t* P;
+    int64_t n;
+    uint8_t* mask;
+    hipStream_t s;
+    msf_options opt;
+    msf_stats* st;
+    uint32_t splits;
+    int sample;
+    int64_t min_split;
+    int sparse_deg;
+};
+
+View view_of(const EdgeSoA& e, int64_t len) {
+    View g;
+    g.u = e.u; g.v = e.v; g.w = e.w; g.id = e.id; g.p16 = nullptr; g.len = len;
+    return g;
+}
+
+int compress_p(Ctx& C) {
+    Ctrl* hc = host_ctrl();
+    for (int attempt = 0;; ++attempt) {
+        HIP_TRY(hipMemsetAsync(&C.B.ctrl->jump_more, 0, sizeof(uint32_t), C.s));
+        const int h = prof_begin(K_PMAINT, C.s);
+        launch_jump(C.P, C.n, 32, C.B.ctrl, C.s);
+        prof_end(h, C.s, 12.0 * C.n);
+        HIP_TRY(hipGetLastError());
+        int st = read_ctrl(C.B.ctrl, hc, C.s);
+        if (st) return st;
+        if (!hc->jump_more) return MSF_OK;
+        if (attempt > 64) {
+            set_err_text("representative compression did not converge");
+            return MSF_EINTERNAL;
+        }
+    }
+}
+
+int base_case(Ctx& C, int mode, const View& g) {
+    C.st->base_cases += 1;
+    return engine_solve(C.B, mode, g, C.n, C.mask, C.P, C.s, C.st);
+}
+
+// `where`: 0 / 1 = the graph lives at [0, len) of buffer X / Y, 2 = the
+// caller's arrays.
+int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
+    if (g.len == 0) return MSF_OK;
+    Ctrl* hc = host_ctrl();
+    int st = read_ctrl(C.B.ctrl, hc, C.s);
+    if (st) return st;
+    // isSparse: average degree of the current components, or too few edges
+    const double comps = (double)C.n - (double)hc->msf_edges;
+    const bool sparse = g.len < C.min_split || 2.0 * (double)g.len <= C.sparse_deg * comps ||
+                        depth >= kMaxDepth;
+    if (sparse) return base_case(C, mode, g);
+
+    const uint32_t split = C.splits++;
+    const float q = C.opt.pivot == MSF_PIVOT_QUANTILE ? C.opt.quantile : 0.5f;
+    int h = prof_begin(K_SAMPLE, C.s);
+    launch_sample_pivot(mode, g, pivot_stream_base(C.opt.seed, split), C.sample, q, nullptr,
+                        C.B.ctrl, C.s);
+    prof_end(h, C.s, 8.0 * C.sample);
+    const int tgt = where == 0 ? 1 : 0;
+    const EdgeSoA R = C.buf[tgt];
+    HIP_TRY(hipMemsetAsync(&C.B.ctrl->light, 0, sizeof(uint64_t), C.s));
+    h = prof_begin(K_PARTITION, C.s);
+    launch_count_light(mode, g, &C.B.ctrl->pivot, C.B.ctrl, C.s);
+    const int64_t nt = (g.len + kRelabelTile - 1) / kRelabelTile;
+    launch_scan_prep(C.B.status, nt, C.B.ctrl, 0, C.s);
+    launch_split(mode, g, C.n, &C.B.ctrl->pivot, R, C.B.status, C.B.ctrl, C.s);
+    prof_end(h, C.s, (mode == kOrig ? 16.0 : 24.0) * g.len + 16.0 * g.len);
+    HIP_TRY(hipGetLastError());
+    if ((st = read_ctrl(C.B.ctrl, hc, C.s))) return st;
+    if (hc->err & kErrRange) return MSF_ERANGE;
+    if (hc->err) {
+        set_err_text("device error bits during a split");
+        return MSF_EINTERNAL;
+    }
+    const int64_t nl = (int64_t)hc->light, nh = g.len - nl;
+    if (split < MSF_MAX_TRACE) {
+        C.st->split_edges[split] = (uint64_t)g.len;
+        C.st->split_pivot[split] = hc->pivot;
+        C.st->split_light[split] = (uint64_t)nl;
+        C.st->split_q[split] = hc->q_used;
+        C.st->split_kept[split] = 0;
+    }
+    if (split == 0) C.st->pivot_q_used = hc->q_used;
+    C.st->levels += 1;
+    if (nl == 0 || nh == 0) return base_case(C, mode, g);   // degenerate pivot
+
+    EdgeSoA H = R;
+    const int64_t nl_al = (nl + 3) & ~(int64_t)3;
+    H.u += nl_al; H.v += nl_al; H.w += nl_al; H.id += nl_al;
+    if ((st = rec_filter(C, kCompact, view_of(R, nl), tgt, depth + 1))) return st;
+
+    // Filter: drop heavy edges inside a light component, compacting the rest
+    // leftwards to [0, kept) of the same buffer (a stable lookback compaction
+    // never writes past what it has read).
+    if ((st = compress_p(C))) return st;
+    const int64_t nth = (nh + kRelabelTile - 1) / kRelabelTile;
+    launch_scan_prep(C.B.status, nth, C.B.ctrl, 0, C.s);
+    HIP_TRY(hipMemsetAsync(&C.B.ctrl->m_next, 0, sizeof(uint64_t), C.s));
+    h = prof_begin(K_FILTER, C.s);
+    launch_compact(kCompact, view_of(H, nh), C.P, R, nullptr, C.B.status, C.B.ctrl, C.s);
+    prof_end(h, C.s, 24.0 * nh);
+    HIP_TRY(hipGetLastError());
+    if ((st = read_ctrl(C.B.ctrl, hc, C.s))) return st;
+    const int64_t kept = (int64_t)hc->m_next;
+    prof_add(K_FILTER, 16.0 * kept);
+    C.st->filtered_in += (uint64_t)nh;
+    C.st->filtered_out += (uint64_t)kept;
+    if (split < MSF_MAX_TRACE) C.st->split_kept[split] = (uint64_t)kept;
+    return rec_filter(C, kCompact, view_of(R, kept), tgt, depth + 1);
+}
+
+}  // namespace
+
+size_t filter_bytes(int64_t m, int64_t n, const msf_options& opt) {
+    (void)opt;
+    return engine_bytes(m, n) + align_up((size_t)(n > 0 ? n : 1) * 4) + 2 * buffer_bytes(m);
+}
+
+int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,
+                 uint8_t* mask, char* ws, hipStream_t s, const msf_options& opt,
+                 msf_stats* stats) {
+    Ctx C;
+    size_t off = engine_carve(ws, m, n, &C.B);
+    C.P = (int32_t*)(ws + off);
+    off += align_up((size_t)(n > 0 ? n : 1) * 4);
+    C.buf[0] = carve_buffer(ws + off, m);
+    C.buf[1] = carve_buffer(ws + off + buffer_bytes(m), m);
+    C.n = n;
+    C.mask = mask;
+    C.s = s;
+    C.opt = opt;
+    C.st = stats;
+    C.splits = 0;
+    C.sample = opt.sample_size > 0 ? opt.sample_size : 4096;
+    C.min_split = opt.min_split_edges > 0 ? opt.min_split_edges : (1 << 20);
+    C.sparse_deg = opt.sparse_degree > 0 ? opt.sparse_degree : 4;
+
+    HIP_TRY(hipMemsetAsync(C.B.ctrl, 0, sizeof(Ctrl), s));
+    int h = prof_begin(K_FILL, s);
+    launch_zero_bytes(mask, m, s);
+    launch_iota(C.P, n, s);
+    prof_end(h, s, (double)m + 4.0 * n);
+    View g{u, v, nullptr, w, nullptr, m};
+    int st = rec_filter(C, kOrig, g, 2, 0);
+    if (st) return st;
+    Ctrl* hc = host_ctrl();
+    if ((st = read_ctrl(C.B.ctrl, hc, s))) return st;
+    stats->total_weight = hc->total;
+    stats->msf_edges = hc->msf_edges;
+    return MSF_OK;
+}
+
+}  // namespace msf

@@ -1,0 +1,33 @@
+// Host-side launchers of the device kernels (each in the .hip file that
+// defines the kernel).  All take the stream to launch on.
+#pragma once
+#include "common.h"
+
+namespace msf {
+
+// boruvka.hip
+void launch_fill_u64(uint64_t* p, int64_t n, uint64_t val, hipStream_t s);
+void launch_zero_bytes(uint8_t* p, int64_t n, hipStream_t s);
+void launch_scan_prep(uint64_t* status, int64_t ntiles, Ctrl* ctrl, int round_begin,
+                      hipStream_t s);
+void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
+                       int64_t n, uint64_t* best, Ctrl* ctrl, hipStream_t s);
+void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
+                 int32_t* parent, uint8_t* mask, Ctrl* ctrl, hipStream_t s);
+void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s);
+void launch_scan_roots(const int32_t* parent, const uint64_t* best, int64_t nr, int32_t* label,
+                       uint64_t* status, Ctrl* ctrl, hipStream_t s);
+void launch_label(const int32_t* parent, const uint64_t* best, int64_t nr, int32_t* label,
+                  uint64_t* best_next, const Ctrl* ctrl, hipStream_t s);
+void launch_compose(const int32_t* cmap, int64_t nc, const int32_t* label, int32_t* out,
+                    hipStream_t s);
+bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t nc, int32_t* ou,
+                 int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, Ctrl* ctrl,
+                 hipStream_t s);
+void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_t* label,
+                       int64_t nr, const int32_t* orig_cur, int32_t* orig_next, int32_t* rep,
+                       hipStream_t s);
+void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
+                    uint64_t* best_next, uint64_t* status, Ctrl* ctrl, hipStream_t s);
+
+}  // namespace msf

@@ -189,3 +189,12 @@ def test_single_vertex_and_two_vertex_multigraph():
     w = np.array([5, 3, 3, 9, 0], np.uint32)
     mask, total, _ = gpu_msf(u, v, w, 2)
     assert list(mask) == [0, 1, 0, 0, 0] and total == 3
+
+
+def test_compose_pass_after_compaction_keeps_all_positions():
+    # regression: a relabel pass that only composes maps on an already
+    # compacted layout must keep every position (grids reach this path)
+    banner("compose after compaction")
+    for rows, cols in [(64, 64), (301, 277)]:
+        u, v, w = graphgen.grid(rows, cols, 0.8, 1, 1, 255, seed=3)
+        check_against_oracle(u, v, w, rows * cols, rounds=True)

@@ -237,3 +237,28 @@ def test_sort_step_matches_library_sort():
     for k in (0, 1, 17, 100000):
         a = rng.integers(0, 2**63, k, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, k).astype(np.uint64)
         assert (oracle.sort_u64(a) == np.sort(a)).all()
+
+
+def test_filter_reference_matches_kruskal_for_any_quantile():
+    # Filter-Kruskal-style filtering is exact for every pivot (Sec. V)
+    u, v, w = graphgen.rmat(11, 40000, wlo=1, whi=2**31 - 1, seed=21)
+    n = 1 << 11
+    km, kt, _ = oracle.kruskal(u, v, w, n)
+    for q in (0.0, 1.0 / 40000, 0.01, 0.5, 0.99, 1.0):
+        mask, total, trace = oracle.filter_boruvka(u, v, w, n, seed=3, sample=512, q=q,
+                                                   min_split=500)
+        assert (mask == km).all() and total == kt
+        if 0.0 < q < 1.0:
+            assert len(trace) > 0
+        for t in trace:
+            assert 0 <= t["light"] <= t["edges"] and t["kept"] <= t["edges"] - t["light"]
+
+
+def test_filter_reference_pivot_is_sample_quantile():
+    from oracle.filter_ref import pivot_index, sample_positions
+    pos = sample_positions(7, 0, 1000, 4096)
+    assert pos.min() >= 0 and pos.max() < 1000
+    # 4096 draws over 1000 positions: every position is hit about 4 times
+    assert len(np.unique(pos)) > 950
+    assert pivot_index(0.5, 4096) == 2047 and pivot_index(0.0, 4096) == 0
+    assert pivot_index(1.0, 4096) == 4095
