@@ -286,13 +286,80 @@ __global__ __launch_bounds__(kBlock) void k_rep_update(
 // next round's best[] can be staged in LDS when small.  OUT selects what is
 // written: nothing (the caller composes maps instead), int32 label pairs, or
 // packed 16-bit label pairs.  Dead edges are written as (0, 0).
-template <int IN, int OUT, bool LDS_M, bool LDS_B>
-__global__ __launch_bounds__(kBlock) void k_pass(View g, const int32_t* __restrict__ M,
-                                                 int64_t nc, int32_t* __restrict__ ou,
-                                                 int32_t* __restrict__ ov,
-                                                 uint32_t* __restrict__ op16,
-                                                 uint64_t* __restrict__ best_next, int64_t nn,
-                                                 Ctrl* ctrl) {
+template <int IN>
+__device__ __forceinline__ void load_group(const View& g, int64_t q, int64_t m, int32_t (&a)[4],
+                                           int32_t (&b)[4], uint32_t (&w)[4]) {
+    const int64_t e0 = q * 4;
+    if (e0 + 3 < m) {
+        if constexpr (IN == kFull16) {
+            const uint4 p = reinterpret_cast<const uint4*>(g.p16)[q];
+            a[0] = p.x & 0xffff; b[0] = p.x >> 16; a[1] = p.y & 0xffff; b[1] = p.y >> 16;
+            a[2] = p.z & 0xffff; b[2] = p.z >> 16; a[3] = p.w & 0xffff; b[3] = p.w >> 16;
+        } else {
+            const int4 a4 = reinterpret_cast<const int4*>(g.u)[q];
+            const int4 b4 = reinterpret_cast<const int4*>(g.v)[q];
+            a[0] = a4.x; a[1] = a4.y; a[2] = a4.z; a[3] = a4.w;
+            b[0] = b4.x; b[1] = b4.y; b[2] = b4.z; b[3] = b4.w;
+        }
+        const uint4 w4 = reinterpret_cast<const uint4*>(g.w)[q];
+        w[0] = w4.x; w[1] = w4.y; w[2] = w4.z; w[3] = w4.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[k] = b[k] = 0;
+            w[k] = 0;
+            if (e0 + k < m) {
+                load_ends<IN>(g, e0 + k, a[k], b[k]);
+                w[k] = g.w[e0 + k];
+            }
+        }
+    }
+}
+
+template <int OUT>
+__device__ __forceinline__ void store_group(int64_t q, int64_t m, const int32_t (&ra)[4],
+                                            const int32_t (&rb)[4], int32_t* __restrict__ ou,
+                                            int32_t* __restrict__ ov,
+                                            uint32_t* __restrict__ op16) {
+    const int64_t e0 = q * 4;
+    const bool full = e0 + 3 < m;
+    if constexpr (OUT == kOut32) {
+        if (full) {
+            reinterpret_cast<int4*>(ou)[q] = make_int4(ra[0], ra[1], ra[2], ra[3]);
+            reinterpret_cast<int4*>(ov)[q] = make_int4(rb[0], rb[1], rb[2], rb[3]);
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (e0 + k < m) { ou[e0 + k] = ra[k]; ov[e0 + k] = rb[k]; }
+        }
+    } else if constexpr (OUT == kOut16) {
+        uint32_t pk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pk[k] = (uint32_t)ra[k] | ((uint32_t)rb[k] << 16);
+        if (full) {
+            reinterpret_cast<uint4*>(op16)[q] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (e0 + k < m) op16[e0 + k] = pk[k];
+        }
+    }
+}
+
+// Relabel + next-round minedge over every position of the view, keeping the
+// positions.  Each lane handles kPassGroups groups of 4 consecutive positions
+// per step (16-byte vector loads, all issued before any is consumed).  The
+// map M (view labels -> next-round labels, nc entries) and the next round's
+// best[] can be staged in LDS when small.  OUT selects what is written:
+// nothing (the caller composes maps instead), int32 label pairs, or packed
+// 16-bit label pairs.  Dead edges are written as (0, 0).  PAIR (last pass
+// before the tail): instead of the next minedge, keep the lightest edge of
+// every vertex pair in a triangular table.
+template <int IN, int OUT, bool LDS_M, bool LDS_B, bool PAIR>
+__global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __restrict__ M,
+                                                     int64_t nc, int32_t* __restrict__ ou,
+                                                     int32_t* __restrict__ ov,
+                                                     uint32_t* __restrict__ op16,
+                                                     uint64_t* __restrict__ best_next, int64_t nn,
+                                                     uint64_t* __restrict__ pairs, Ctrl* ctrl) {
     extern __shared__ uint64_t lds[];
     uint64_t* s_best = lds;                                        // nn entries (LDS_B)
     int32_t* s_map = reinterpret_cast<int32_t*>(lds + (LDS_B ? nn : 0));  // nc entries (LDS_M)
@@ -304,73 +371,50 @@ __global__ __launch_bounds__(kBlock) void k_pass(View g, const int32_t* __restri
     const int32_t* map = LDS_M ? s_map : M;
     uint64_t* bst = LDS_B ? s_best : best_next;
 
+    constexpr int G = kPassGroups;
     const int64_t m = g.len;
     const int64_t groups = (m + 3) / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     uint32_t kept = 0;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < groups;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e0 = q * 4;
-        const bool full = e0 + 3 < m;
-        int32_t a[4], b[4];
-        uint32_t w[4];
-        if (full) {
-            if constexpr (IN == kFull16) {
-                const uint4 p = reinterpret_cast<const uint4*>(g.p16)[q];
-                a[0] = p.x & 0xffff; b[0] = p.x >> 16; a[1] = p.y & 0xffff; b[1] = p.y >> 16;
-                a[2] = p.z & 0xffff; b[2] = p.z >> 16; a[3] = p.w & 0xffff; b[3] = p.w >> 16;
+    for (int64_t q0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q0 < groups;
+         q0 += stride * G) {
+        int32_t a[G][4], b[G][4];
+        uint32_t w[G][4];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int64_t q = q0 + j * stride;
+            if (q < groups) {
+                load_group<IN>(g, q, m, a[j], b[j], w[j]);
             } else {
-                const int4 a4 = reinterpret_cast<const int4*>(g.u)[q];
-                const int4 b4 = reinterpret_cast<const int4*>(g.v)[q];
-                a[0] = a4.x; a[1] = a4.y; a[2] = a4.z; a[3] = a4.w;
-                b[0] = b4.x; b[1] = b4.y; b[2] = b4.z; b[3] = b4.w;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { a[j][k] = b[j][k] = 0; w[j][k] = 0; }
             }
-            const uint4 w4 = reinterpret_cast<const uint4*>(g.w)[q];
-            w[0] = w4.x; w[1] = w4.y; w[2] = w4.z; w[3] = w4.w;
-        } else {
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int64_t q = q0 + j * stride;
+            int32_t ra[4], rb[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                a[k] = b[k] = 0;
-                w[k] = 0;
-                if (e0 + k < m) {
-                    load_ends<IN>(g, e0 + k, a[k], b[k]);
-                    w[k] = g.w[e0 + k];
+                ra[k] = rb[k] = 0;
+                if (a[j][k] != b[j][k]) {     // equal stored labels stay a self-loop
+                    const int32_t x = map[a[j][k]], y = map[b[j][k]];
+                    if (x != y) {
+                        ra[k] = x;
+                        rb[k] = y;
+                        ++kept;
+                        const uint64_t key = ((uint64_t)w[j][k] << 32) | (uint64_t)(q * 4 + k);
+                        if constexpr (PAIR) {   // lightest edge per vertex pair, for the tail
+                            const int64_t lo = x < y ? x : y, hi = x < y ? y : x;
+                            atomic_min_key(&pairs[hi * (hi - 1) / 2 + lo], key);
+                        } else {
+                            atomic_min_key(&bst[x], key);
+                            atomic_min_key(&bst[y], key);
+                        }
+                    }
                 }
             }
-        }
-        int32_t ra[4], rb[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            ra[k] = rb[k] = 0;
-            if (e0 + k < m && a[k] != b[k]) {     // equal stored labels stay a self-loop
-                const int32_t x = map[a[k]], y = map[b[k]];
-                if (x != y) {
-                    ra[k] = x;
-                    rb[k] = y;
-                    ++kept;
-                    const uint64_t key = ((uint64_t)w[k] << 32) | (uint64_t)(e0 + k);
-                    atomic_min_key(&bst[x], key);
-                    atomic_min_key(&bst[y], key);
-                }
-            }
-        }
-        if constexpr (OUT == kOut32) {
-            if (full) {
-                reinterpret_cast<int4*>(ou)[q] = make_int4(ra[0], ra[1], ra[2], ra[3]);
-                reinterpret_cast<int4*>(ov)[q] = make_int4(rb[0], rb[1], rb[2], rb[3]);
-            } else {
-                for (int k = 0; k < 4; ++k)
-                    if (e0 + k < m) { ou[e0 + k] = ra[k]; ov[e0 + k] = rb[k]; }
-            }
-        } else if constexpr (OUT == kOut16) {
-            uint32_t pk[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) pk[k] = (uint32_t)ra[k] | ((uint32_t)rb[k] << 16);
-            if (full) {
-                reinterpret_cast<uint4*>(op16)[q] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-            } else {
-                for (int k = 0; k < 4; ++k)
-                    if (e0 + k < m) op16[e0 + k] = pk[k];
-            }
+            if (q < groups) store_group<OUT>(q, m, ra, rb, ou, ov, op16);
         }
     }
     const uint64_t wk = wave_sum_u64(kept);
@@ -537,13 +581,13 @@ constexpr int64_t kPassLds = 72 * 1024;
 
 // Raises the dynamic-LDS limit of one pass instantiation once (needed above
 // 64 KiB); returns false when the runtime refuses.
-template <int IN, int OUT, bool LM, bool LB>
+template <int IN, int OUT, bool LM, bool LB, bool PAIR>
 static bool allow_lds(size_t bytes) {
     if (bytes <= 64 * 1024) return true;
     static bool tried = false, ok = false;
     if (!tried) {
         tried = true;
-        ok = hipFuncSetAttribute((const void*)k_pass<IN, OUT, LM, LB>,
+        ok = hipFuncSetAttribute((const void*)k_pass<IN, OUT, LM, LB, PAIR>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kPassLds) == hipSuccess;
         if (!ok) (void)hipGetLastError();
@@ -561,48 +605,60 @@ static bool lds_enabled() {
     return on == 1;
 }
 
-template <int IN, int OUT>
+template <int IN, int OUT, bool PAIR>
 static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* ou, int32_t* ov,
-                          uint32_t* op16, uint64_t* best_next, int64_t nn, Ctrl* ctrl,
-                          hipStream_t s) {
+                          uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
+                          Ctrl* ctrl, hipStream_t s) {
     const bool lds_on = lds_enabled();
-    bool ldsb = lds_on && nn * 8 <= kPassLds;
+    bool ldsb = lds_on && !PAIR && nn * 8 <= kPassLds;
     bool ldsm = lds_on && nc * 4 + (ldsb ? nn * 8 : 0) <= kPassLds;
     size_t lds = (ldsb ? nn * 8 : 0) + (ldsm ? nc * 4 : 0);
     bool ok = true;
-    if (ldsb && ldsm) ok = allow_lds<IN, OUT, true, true>(lds);
-    else if (ldsb) ok = allow_lds<IN, OUT, false, true>(lds);
-    else if (ldsm) ok = allow_lds<IN, OUT, true, false>(lds);
+    if (ldsb && ldsm) ok = allow_lds<IN, OUT, true, true, PAIR>(lds);
+    else if (ldsb) ok = allow_lds<IN, OUT, false, true, PAIR>(lds);
+    else if (ldsm) ok = allow_lds<IN, OUT, true, false, PAIR>(lds);
     if (!ok) {   // stay within 64 KiB
-        ldsb = lds_on && nn * 8 <= 64 * 1024;
+        ldsb = lds_on && !PAIR && nn * 8 <= 64 * 1024;
         ldsm = lds_on && nc * 4 + (ldsb ? nn * 8 : 0) <= 64 * 1024;
         lds = (ldsb ? nn * 8 : 0) + (ldsm ? nc * 4 : 0);
     }
     const int64_t groups = (g.len + 3) / 4;
-    unsigned grid = grid_for(groups, lds ? 512 : 2048);
-    const dim3 bl(kBlock);
+    int64_t want = (groups + (int64_t)kPassBlock * kPassGroups - 1) / ((int64_t)kPassBlock * kPassGroups);
+    const int64_t cap = lds ? 512 : 1024;   // LDS variants: two workgroups per CU
+    const unsigned grid = (unsigned)(want < 1 ? 1 : (want > cap ? cap : want));
+    const dim3 bl(kPassBlock);
     if (ldsb && ldsm)
-        hipLaunchKernelGGL((k_pass<IN, OUT, true, true>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl);
     else if (ldsb)
-        hipLaunchKernelGGL((k_pass<IN, OUT, false, true>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl);
     else if (ldsm)
-        hipLaunchKernelGGL((k_pass<IN, OUT, true, false>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl);
     else
-        hipLaunchKernelGGL((k_pass<IN, OUT, false, false>), dim3(grid), bl, 0, s, g, M, nc, ou, ov, op16, best_next, nn, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, false, PAIR>), dim3(grid), bl, 0, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl);
 }
 
 // Streaming pass; returns false for a layout/output pair it does not support.
+// pairs != null: last pass before the tail (output kOutNone only).
 bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t nc, int32_t* ou,
-                 int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, Ctrl* ctrl,
-                 hipStream_t s) {
+                 int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
+                 Ctrl* ctrl, hipStream_t s) {
     if (g.len <= 0) return true;
+    if (pairs) {
+        if (out != kOutNone) return false;
+        switch (in_mode) {
+            case kOrig: pass_dispatch<kOrig, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl, s); return true;
+            case kFull32: pass_dispatch<kFull32, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl, s); return true;
+            case kFull16: pass_dispatch<kFull16, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl, s); return true;
+            default: pass_dispatch<kCompact, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl, s); return true;
+        }
+    }
     switch (in_mode * 3 + out) {
-        case kOrig * 3 + kOut32: pass_dispatch<kOrig, kOut32>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
-        case kOrig * 3 + kOut16: pass_dispatch<kOrig, kOut16>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
-        case kFull32 * 3 + kOutNone: pass_dispatch<kFull32, kOutNone>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
-        case kFull32 * 3 + kOut16: pass_dispatch<kFull32, kOut16>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
-        case kFull16 * 3 + kOutNone: pass_dispatch<kFull16, kOutNone>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
-        case kCompact * 3 + kOutNone: pass_dispatch<kCompact, kOutNone>(g, M, nc, ou, ov, op16, best_next, nn, ctrl, s); return true;
+        case kOrig * 3 + kOut32: pass_dispatch<kOrig, kOut32, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
+        case kOrig * 3 + kOut16: pass_dispatch<kOrig, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
+        case kFull32 * 3 + kOutNone: pass_dispatch<kFull32, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
+        case kFull32 * 3 + kOut16: pass_dispatch<kFull32, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
+        case kFull16 * 3 + kOutNone: pass_dispatch<kFull16, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
+        case kCompact * 3 + kOutNone: pass_dispatch<kCompact, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
         default: return false;
     }
 }

@@ -11,6 +11,8 @@ constexpr int kItems = 16;                  // items per thread in scan tiles
 constexpr int kTile = kBlock * kItems;      // items per decoupled-lookback tile
 constexpr int kRelabelItems = 8;            // edges per thread in the relabel pass
 constexpr int kRelabelTile = kBlock * kRelabelItems;
+constexpr int kPassBlock = 512;             // threads per streaming-pass workgroup
+constexpr int kPassGroups = 2;              // 4-edge groups per lane per step in a pass
 constexpr uint64_t kKeyMax = ~0ull;         // "no edge" in best[]
 
 // Error bits accumulated on the device.
@@ -34,8 +36,17 @@ struct Ctrl {
     uint64_t pivot;          // filter: pivot key of the current split
     float q_used;            // filter: sample quantile used
     uint32_t pad1;
-    uint64_t aux[6];         // spare
+    uint32_t tail_rounds;    // rounds run by the single-workgroup tail
+    uint32_t tail_edges;     // distinct vertex pairs handed to the tail
+    uint32_t tail_live[24];  // per tail round: vertices with an incident edge
+    uint32_t tail_found[24]; // per tail round: MSF edges found
+    uint32_t tail_scan[24];  // per tail round: live pairs scanned
+    uint64_t aux[4];         // spare
 };
+
+constexpr int kTailMax = 1024;              // vertices the single-workgroup tail handles
+constexpr int kTailThreads = 1024;
+constexpr int kTailRoundsMax = 24;
 
 // Lookback status word: 2 flag bits over a 62-bit inclusive/aggregate value.
 constexpr uint64_t kStatAgg = 1ull << 62;

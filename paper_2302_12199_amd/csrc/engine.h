@@ -18,6 +18,9 @@ struct EngineBuffers {
     int32_t* f32v;
     uint32_t* p16;        // kFull16 layout
     EdgeSoA cbuf[2];      // kCompact layouts (alternating)
+    uint64_t* pairs;      // tail: lightest edge per vertex pair (triangular table)
+    uint32_t* list_xy;    // tail: compacted pair list
+    uint64_t* list_key;
     int64_t ncap, mcap;
 };
 

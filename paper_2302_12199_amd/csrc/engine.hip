@@ -59,6 +59,10 @@ size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B) {
         b.cbuf[i].w = (uint32_t*)take(mm * 4);
         b.cbuf[i].id = (uint32_t*)take(mm * 4);
     }
+    const size_t slots = (size_t)kTailMax * (kTailMax - 1) / 2;
+    b.pairs = (uint64_t*)take(slots * 8);
+    b.list_xy = (uint32_t*)take(slots * 4);
+    b.list_key = (uint64_t*)take(slots * 8);
     b.ncap = n;
     b.mcap = m;
     if (B) *B = b;
@@ -197,6 +201,39 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         // the streaming pass uses 16-byte vector loads
         const bool aligned = ((((uintptr_t)view.u | (uintptr_t)view.v | (uintptr_t)view.w |
                                 (uintptr_t)view.p16 | (uintptr_t)view.id) & 15) == 0);
+        if (nn <= 1) break;        // one component left: every remaining edge is a self-loop
+        if (nn <= kTailMax && aligned) {
+            // Last pass keeps the lightest edge per vertex pair; one workgroup
+            // then finishes all remaining rounds.
+            const int64_t slots = nn * (nn - 1) / 2;
+            h = prof_begin(K_PASS, s);
+            launch_fill_u64(B.pairs, slots, kKeyMax, s);
+            if (!launch_pass(mode, kOutNone, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1],
+                             nn, B.pairs, dc, s)) {
+                set_err_text("unsupported pass layout");
+                return MSF_EINTERNAL;
+            }
+            prof_end(h, s, view_read_bytes(mode) * view.len + 8.0 * m_live + 8.0 * slots);
+            h = prof_begin(K_TAIL, s);
+            launch_tail(B.pairs, nn, B.list_xy, B.list_key, mode == kCompact ? view.id : nullptr,
+                        mask, rep ? B.orig[origsel] : nullptr, rep, dc, s);
+            prof_end(h, s, 16.0 * slots);
+            HIP_TRY(hipGetLastError());
+            if ((st = read_ctrl(dc, hc, s))) return st;
+            if (hc->err) {
+                set_err_text("device error bits in the tail");
+                return MSF_EINTERNAL;
+            }
+            for (uint32_t t = 0; t < hc->tail_rounds; ++t) {
+                if (stats && rounds < MSF_MAX_TRACE) {
+                    stats->round_live[rounds] = hc->tail_live[t];
+                    stats->round_edges[rounds] = hc->tail_scan[t];
+                    stats->round_found[rounds] = hc->tail_found[t];
+                }
+                ++rounds;
+            }
+            break;
+        }
         const bool compact = !aligned || always_compact() ||
                              (mode != kOrig && (double)m_live < kCompactBelow * (double)view.len);
         View next = view;
@@ -220,7 +257,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             else if (mode == kFull32 && nn <= kMax16) out = kOut16;
             h = prof_begin(K_PASS, s);
             if (!launch_pass(mode, out, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1], nn,
-                             dc, s)) {
+                             nullptr, dc, s)) {
                 set_err_text("unsupported pass layout");
                 return MSF_EINTERNAL;
             }

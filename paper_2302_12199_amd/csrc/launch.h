@@ -22,8 +22,12 @@ void launch_label(const int32_t* parent, const uint64_t* best, int64_t nr, int32
 void launch_compose(const int32_t* cmap, int64_t nc, const int32_t* label, int32_t* out,
                     hipStream_t s);
 bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t nc, int32_t* ou,
-                 int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, Ctrl* ctrl,
-                 hipStream_t s);
+                 int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
+                 Ctrl* ctrl, hipStream_t s);
+// tail.hip
+void launch_tail(const uint64_t* pairs, int64_t nn, uint32_t* list_xy, uint64_t* list_key,
+                 const uint32_t* view_id, uint8_t* mask, const int32_t* orig_in, int32_t* rep,
+                 Ctrl* ctrl, hipStream_t s);
 void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_t* label,
                        int64_t nr, const int32_t* orig_cur, int32_t* orig_next, int32_t* rep,
                        hipStream_t s);
