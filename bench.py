@@ -63,6 +63,87 @@ def cpu_baseline(u, v, w, n, sample_edges):
             "seconds": round(dt, 3)}
 
 
+BATCH_WORKLOAD = "batch_gnm_10k_n2^8..2^18_deg4..64"
+
+
+def run_batch(args):
+    """Batched solve of the 10,000-graph GNM batch (n log-uniform in
+    [2^8, 2^18], average degree uniform in [4, 64], w uniform in [1, 2^31)):
+    one hipGraph-captured persistent launch per step, against a loop of
+    per-graph msf_compute calls on a sample of the same batch."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2302_12199_amd as msf
+
+    G = args.graphs
+    t = time.perf_counter()
+    u, v, w, eo, vo = graphgen.batch_gnm(G, lo=8, hi=18, dlo=4, dhi=64, wlo=1, whi=2**31 - 1,
+                                         seed=6)
+    m = int(eo[-1])
+    log(f"generated {G} graphs, {m} edges in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    tu, tv, tw = (torch.from_numpy(x.view(np.int32)).to(dev) for x in (u, v, w))
+    b = msf.Batch(tu, tv, tw, eo, vo)
+    torch.cuda.synchronize()
+    tuned = b.autotune() if args.autotune else None
+    if tuned:
+        log(f"autotuned: {tuned}")
+    b.capture()
+    for _ in range(args.warmup):
+        b.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_batch = (t1 - t0) * 1000.0 / args.steps
+    ticks = b.ticks.cpu().numpy().view(np.uint64).astype(np.float64)
+    khz = msf.wall_clock_khz()
+    lat_ms = (ticks[:-1] - ticks[-1]) / khz if khz else np.zeros(G)
+    log(f"batched: {ms_batch:.2f} ms per batch, {G / ms_batch * 1000:.0f} graphs/s")
+
+    # plain per-graph calls on a sample of the batch (same graphs, same order)
+    k = min(args.plain_sample, G)
+    max_e = int((eo[1:k + 1] - eo[:k]).max())
+    max_n = int((vo[1:k + 1] - vo[:k]).max())
+    ws = torch.empty(msf.workspace_bytes(max_e, max_n), dtype=torch.uint8, device=dev)
+    mk = torch.empty(max(max_e, 1), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for g in range(k):
+        a, c = int(eo[g]), int(eo[g + 1])
+        tg = time.perf_counter()
+        msf.compute(tu[a:c], tv[a:c], tw[a:c], int(vo[g + 1] - vo[g]), workspace=ws,
+                    mask_out=mk[:c - a])
+        per.append(time.perf_counter() - tg)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plain_gps = k / (t1 - t0)
+    batch_gps = G / (ms_batch / 1000.0)
+    log(f"plain: {plain_gps:.0f} graphs/s over {k} graphs")
+    out = {
+        "metric": "batched graphs/s (10,000 GNM graphs) vs per-graph plain calls",
+        "value": batch_gps, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_batch, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": BATCH_WORKLOAD, "graphs": G, "edges": m},
+        "batched_edges_per_s": m / (ms_batch / 1000.0),
+        "plain_graphs_per_s": plain_gps, "plain_sample": k,
+        "speedup_vs_plain": batch_gps / plain_gps,
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                       "p99": float(np.percentile(lat_ms, 99)),
+                       "max": float(lat_ms.max())},
+        "plain_service_ms": {"p50": 1000 * float(np.percentile(per, 50)),
+                             "p99": 1000 * float(np.percentile(per, 99))},
+        "autotuned": tuned,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,13 +155,33 @@ def main():
     ap.add_argument("--quantile", type=float, default=0.5)
     ap.add_argument("--cpu-sample", type=int, default=1 << 27,
                     help="edges given to the timed CPU oracle (0 = skip)")
+    ap.add_argument("--graphs", type=int, default=10000, help="batch workload: graphs")
+    ap.add_argument("--plain-sample", type=int, default=300,
+                    help="batch workload: graphs timed with per-graph calls")
+    ap.add_argument("--autotune", action="store_true", help="batch workload: autotune first")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates byte counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 1 GiB three times")
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this library runs on one GPU; multi-GPU runs are not part of it "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == BATCH_WORKLOAD:
+        return run_batch(args)
 
     import numpy as np
     import torch

@@ -55,6 +55,8 @@ def _load():
         lib.gg_rgg2d_build.argtypes = [i64, dbl, dbl, u64, ctypes.POINTER(i64)]
         lib.gg_rgg2d_build.restype = vp
         lib.gg_take.argtypes = [vp, vp, vp, vp]
+        lib.gg_batch_plan.argtypes = [i64, dbl, dbl, dbl, dbl, u64, vp, vp]
+        lib.gg_batch_fill.argtypes = [i64, i64, i64, vp, vp, vp, u32, u32, u64, vp, vp, vp]
         lib.gg_draw.argtypes = [u64, u64, u64]
         lib.gg_draw.restype = u64
         _lib = lib
@@ -123,6 +125,34 @@ def rgg2d(n: int, r: float, wscale: float = 1e6, seed: int = 4):
 def rgg_radius(n: int, avg_deg: float) -> float:
     """Radius giving expected average degree avg_deg (boundary effects ignored)."""
     return math.sqrt(avg_deg / (math.pi * (n - 1)))
+
+
+def batch_plan(G, lo=8.0, hi=18.0, dlo=4.0, dhi=64.0, seed=6):
+    """Sizes of a batch of GNM graphs: n_g = round(2^U[lo,hi]), d_g ~ U[dlo,dhi],
+    m_g = round(n_g d_g / 2).  Returns (n[G], m[G]) int64 arrays."""
+    n = np.empty(G, np.int64)
+    m = np.empty(G, np.int64)
+    if _load().gg_batch_plan(G, lo, hi, dlo, dhi, seed, _ptr(n), _ptr(m)) != 0:
+        raise ValueError("batch_plan: bad arguments")
+    return n, m
+
+
+def batch_gnm(G, lo=8.0, hi=18.0, dlo=4.0, dhi=64.0, wlo=1, whi=2**31 - 1, seed=6,
+              first=0, count=None):
+    """Graphs [first, first+count) of the batch, concatenated: returns
+    (u, v, w, edge_off[count+1], vert_off[count+1]) with local vertex ids."""
+    nf, mf = batch_plan(G, lo, hi, dlo, dhi, seed)
+    count = G - first if count is None else count
+    n, m = nf[first:first + count], mf[first:first + count]
+    eoff = np.zeros(count + 1, np.int64)
+    np.cumsum(m, out=eoff[1:])
+    voff = np.zeros(count + 1, np.int64)
+    np.cumsum(n, out=voff[1:])
+    u, v, w = _alloc(int(eoff[-1]))
+    if _load().gg_batch_fill(G, first, count, _ptr(nf), _ptr(mf), _ptr(eoff), wlo, whi, seed,
+                             _ptr(u), _ptr(v), _ptr(w)) != 0:
+        raise ValueError("batch_gnm: bad arguments")
+    return u, v, w, eoff, voff
 
 
 # --------------------------------------------------------------------------

@@ -31,7 +31,7 @@
 #define GAMMA 0x9E3779B97F4A7C15ULL
 
 enum { TAG_GNM = 1, TAG_RMAT = 2, TAG_PERM = 3, TAG_RMAT_W = 4, TAG_GRID_KEEP = 5,
-       TAG_GRID_W = 6, TAG_RGG = 7 };
+       TAG_GRID_W = 6, TAG_RGG = 7, TAG_BATCH = 8 };
 
 static inline uint64_t mix(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -406,6 +406,67 @@ int gg_take(void* h, int32_t* u, int32_t* v, uint32_t* w) {
     memcpy(v, b->v, (size_t)b->m * 4);
     memcpy(w, b->w, (size_t)b->m * 4);
     free(b->u); free(b->v); free(b->w); free(b);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ batches */
+/* Many independent GNM graphs.  Graph g: n_g = round(2^(lo + (hi - lo) U)),
+ * U uniform on [0, 1) from the 53-bit draw 2g of the batch stream; average
+ * degree d_g = dlo + (dhi - dlo) U' from draw 2g + 1; m_g = round(n_g d_g / 2).
+ * Its edges are gg_gnm(n_g, m_g, wlo, whi, seed_g) with seed_g = draw 2G + g.
+ * Vertex ids are local to the graph, in [0, n_g). */
+int gg_batch_plan(int64_t G, double lo, double hi, double dlo, double dhi, uint64_t seed,
+                  int64_t* n_out, int64_t* m_out) {
+    if (G < 0 || lo < 1 || hi < lo || dlo < 0 || dhi < dlo) return -1;
+    uint64_t b = base(seed, TAG_BATCH);
+    for (int64_t g = 0; g < G; ++g) {
+        double u1 = (double)(draw(b, 2 * (uint64_t)g) >> 11) * 0x1.0p-53;
+        double u2 = (double)(draw(b, 2 * (uint64_t)g + 1) >> 11) * 0x1.0p-53;
+        int64_t n = (int64_t)llround(pow(2.0, lo + (hi - lo) * u1));
+        if (n < 2) n = 2;
+        double d = dlo + (dhi - dlo) * u2;
+        n_out[g] = n;
+        m_out[g] = (int64_t)llround((double)n * d / 2.0);
+    }
+    return 0;
+}
+
+typedef struct {
+    const int64_t *n, *m, *eoff; int64_t G, first; uint32_t wlo, whi; uint64_t b;
+    int32_t *u, *v; uint32_t* w;
+} batch_ctx;
+
+static void batch_range(void* p, int64_t lo, int64_t hi) {
+    batch_ctx* c = (batch_ctx*)p;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t g = c->first + i;
+        gnm_ctx gc = { c->n[g], c->wlo, c->whi,
+                       base(draw(c->b, 2 * (uint64_t)c->G + (uint64_t)g), TAG_GNM),
+                       c->u + c->eoff[i], c->v + c->eoff[i], c->w + c->eoff[i] };
+        gnm_range(&gc, 0, c->m[g]);
+    }
+}
+
+/* Fills graphs [first, first + count) of a G-graph batch planned by
+ * gg_batch_plan (n, m of the whole batch); graph first + i is written at
+ * offset eoff[i] of u, v, w. */
+int gg_batch_fill(int64_t G, int64_t first, int64_t count, const int64_t* n, const int64_t* m,
+                  const int64_t* eoff, uint32_t wlo, uint32_t whi, uint64_t seed, int32_t* u,
+                  int32_t* v, uint32_t* w) {
+    if (G < 0 || first < 0 || count < 0 || first + count > G || wlo > whi) return -1;
+    batch_ctx c = { n, m, eoff, G, first, wlo, whi, base(seed, TAG_BATCH), u, v, w };
+    int t = gg_threads();
+    if (count < 2 * t) { batch_range(&c, 0, count); return 0; }
+    pthread_t th[64];
+    job_t jobs[64];
+    int64_t chunk = (count + t - 1) / t;
+    for (int i = 0; i < t; ++i) {
+        jobs[i].fn = batch_range; jobs[i].ctx = &c;
+        jobs[i].lo = i * chunk < count ? i * chunk : count;
+        jobs[i].hi = (i + 1) * chunk < count ? (i + 1) * chunk : count;
+        pthread_create(&th[i], NULL, run_job, &jobs[i]);
+    }
+    for (int i = 0; i < t; ++i) pthread_join(th[i], NULL);
     return 0;
 }
 

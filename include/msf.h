@@ -94,6 +94,7 @@ typedef struct msf_stats {
     uint64_t split_light[MSF_MAX_TRACE];  /* edges with key <= pivot */
     uint64_t split_kept[MSF_MAX_TRACE];   /* heavy edges surviving the filter */
     float split_q[MSF_MAX_TRACE];         /* sample quantile used by the split */
+    float top_features[16];     /* pivot-network features of the first split's sample */
 } msf_stats;
 
 /* Bytes of device workspace msf_compute needs for (m, n, opt); opt may be NULL. */
@@ -116,6 +117,103 @@ int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m
                 uint8_t* mask_out, uint64_t* total_weight_out, void* workspace,
                 size_t workspace_bytes, void* stream, const msf_options* opt,
                 msf_stats* stats);
+
+/*
+ * Batched MSF: G independent graphs solved by one persistent kernel (graph g
+ * is a whole problem in the sense of msf_compute; paper Sec. II-C rounds are
+ * run by one workgroup per graph).  Stream-ordered and asynchronous: nothing
+ * is synchronised and nothing is allocated, so the call can be captured in a
+ * hipGraph (see msf_batched_graph_create).
+ *   u, v, w        device arrays of all graphs' edges, concatenated
+ *   edge_off       device int64[G + 1]: graph g owns edges [edge_off[g], edge_off[g+1])
+ *   vert_off       device int64[G + 1]: graph g has vert_off[g+1] - vert_off[g]
+ *                  vertices; its u, v are LOCAL ids in [0, n_g)
+ *   max_n          HOST: upper bound of n_g over the batch (sizes the scratch)
+ *   order          device int32[G] processing order (e.g. largest first), or NULL
+ *   mask_out       device uint8[edge_off[G]]: 1 iff the edge is in its graph's MSF
+ *   totals_out     device uint64[G]: MSF weight per graph; UINT64_MAX marks a graph
+ *                  with an id outside [0, n_g), n_g > max_n or more than 2^32-1 edges
+ *   ticks_out      device uint64[G + 1] or NULL: wall-clock tick at which each
+ *                  graph finished, [G] = tick at which the batch started
+ *                  (rate: msf_wall_clock_khz)
+ *   workspace      device, >= msf_batched_workspace_bytes(G, max_n, opt) bytes
+ * Errors: MSF_EINVAL (bad host arguments), MSF_EWORKSPACE, MSF_EDEVICE.
+ */
+typedef struct msf_batch_options {
+    int32_t block;           /* threads per workgroup: 256, 512 or 1024; 0 = 1024 */
+    int32_t lds_vertices;    /* graphs with at most this many vertices keep their
+                                state in LDS (20 B per vertex); 0 = 2048, -1 = never */
+    int32_t workgroups;      /* persistent workgroups; 0 = 2 per compute unit */
+    int32_t reserved[5];     /* must be zero */
+} msf_batch_options;
+
+size_t msf_batched_workspace_bytes(int64_t G, int64_t max_n, const msf_batch_options* opt);
+int msf_compute_batched(const int32_t* u, const int32_t* v, const uint32_t* w,
+                        const int64_t* edge_off, const int64_t* vert_off, int64_t G,
+                        int64_t max_n, const int32_t* order, uint8_t* mask_out,
+                        uint64_t* totals_out, uint64_t* ticks_out, void* workspace,
+                        size_t workspace_bytes, void* stream, const msf_batch_options* opt);
+
+/* The same launch captured once into an instantiated hipGraph (fixed
+ * arguments); launching it replays the whole batch. */
+typedef struct msf_batch_graph msf_batch_graph;
+int msf_batched_graph_create(const int32_t* u, const int32_t* v, const uint32_t* w,
+                             const int64_t* edge_off, const int64_t* vert_off, int64_t G,
+                             int64_t max_n, const int32_t* order, uint8_t* mask_out,
+                             uint64_t* totals_out, uint64_t* ticks_out, void* workspace,
+                             size_t workspace_bytes, const msf_batch_options* opt,
+                             msf_batch_graph** graph_out);
+int msf_batched_graph_launch(msf_batch_graph* graph, void* stream);
+int msf_batched_graph_destroy(msf_batch_graph* graph);
+
+/*
+ * Autotuner for the batched solver: runs the batch once per candidate
+ * (block in {256, 512, 1024} x lds_vertices in {-1, 1024, 2048, 4096}) on
+ * `stream`, times each with HIP events and writes the fastest to *best_out
+ * (HOST); *best_ms_out (HOST, nullable) gets its time.  Blocking.  Same array
+ * arguments as msf_compute_batched; the workspace must fit every candidate
+ * (msf_batched_workspace_bytes with a NULL options pointer suffices).
+ */
+int msf_batched_autotune(const int32_t* u, const int32_t* v, const uint32_t* w,
+                         const int64_t* edge_off, const int64_t* vert_off, int64_t G,
+                         int64_t max_n, const int32_t* order, uint8_t* mask_out,
+                         uint64_t* totals_out, void* workspace, size_t workspace_bytes,
+                         void* stream, msf_batch_options* best_out, float* best_ms_out);
+
+/*
+ * Pivot network for Filter-Borůvka (MSF_PIVOT_MLP).  Not in the paper, which
+ * uses the sample median: a 16 -> 64 -> 64 -> 1 perceptron (ReLU hidden
+ * layers, logistic output) maps 16 statistics of the pivot sample (listed in
+ * filter.hip) to the sample quantile used as pivot, clamped to
+ * [2^-10, 1 - 2^-10].  Any pivot yields the same MSF; the network only
+ * changes running time.  Inference uses bfloat16 weights and activations with
+ * FP32 accumulation.  Parameters are FP32 in the order W1[64][16], b1[64],
+ * W2[64][64], b2[64], w3[64], b3 (msf_mlp_param_count() floats).
+ */
+/* Loads a model (HOST blob: uint32 magic 0x5046534d, version 1, 16, 64, then
+ * the FP32 parameters).  MSF_EINVAL on a malformed blob or non-finite values.
+ * Process-wide; later MSF_PIVOT_MLP solves use it. */
+int msf_pivot_model_load(const void* blob, size_t bytes);
+int msf_pivot_model_clear(void);          /* back to the median fallback */
+int msf_pivot_model_loaded(void);         /* 1 if a model is loaded */
+int msf_mlp_param_count(void);
+/* Training kernels (all pointers DEVICE, stream-ordered):
+ *   forward: z_out[b] = network output before the logistic, x is [B][16]
+ *   grad:    grad_out[P] = d/dparams of mean_b (z_b - target_b)^2 / 2 and
+ *            *loss_out = that loss (both overwritten); FP32 gradients
+ *   adam:    one Adam step (Kingma & Ba) on FP32 params with moments m, v;
+ *            step counts from 1
+ * bf16 != 0 rounds weights, inputs and activations to bfloat16 in the forward
+ * pass (accumulation stays FP32). */
+int msf_mlp_forward(const float* params, const float* x, int64_t B, float* z_out, int bf16,
+                    void* stream);
+int msf_mlp_grad(const float* params, const float* x, const float* target, int64_t B, int bf16,
+                 float* grad_out, float* loss_out, void* stream);
+int msf_mlp_adam(float* params, const float* grad, float* m, float* v, float lr, float beta1,
+                 float beta2, float eps, int step, void* stream);
+
+/* Rate of the device wall clock used by ticks_out, in kHz. */
+int msf_wall_clock_khz(void);
 
 /* Static description of a status code. */
 const char* msf_status_string(int status);

@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
                 ("split_pivot", ctypes.c_uint64 * MAX_TRACE),
                 ("split_light", ctypes.c_uint64 * MAX_TRACE),
                 ("split_kept", ctypes.c_uint64 * MAX_TRACE),
-                ("split_q", ctypes.c_float * MAX_TRACE)]
+                ("split_q", ctypes.c_float * MAX_TRACE),
+                ("top_features", ctypes.c_float * 16)]
 
     def to_dict(self):
         r = min(self.rounds, MAX_TRACE)
@@ -57,7 +58,8 @@ class Stats(ctypes.Structure):
                 "splits": [{"edges": int(self.split_edges[i]), "pivot": int(self.split_pivot[i]),
                             "light": int(self.split_light[i]), "kept": int(self.split_kept[i]),
                             "q": float(self.split_q[i])}
-                           for i in range(min(self.levels, MAX_TRACE))]}
+                           for i in range(min(self.levels, MAX_TRACE))],
+                "top_features": [float(x) for x in self.top_features]}
 
 
 class MSFError(RuntimeError):
@@ -71,7 +73,17 @@ _LIB = None
 
 # Exported C symbols (each declared in include/msf.h).
 SYMBOLS = ("msf_workspace_bytes", "msf_compute", "msf_status_string", "msf_last_error",
-           "msf_version", "msf_profile_enable", "msf_profile_reset", "msf_profile_read")
+           "msf_version", "msf_profile_enable", "msf_profile_reset", "msf_profile_read",
+           "msf_batched_workspace_bytes", "msf_compute_batched", "msf_batched_graph_create",
+           "msf_batched_graph_launch", "msf_batched_graph_destroy", "msf_batched_autotune",
+           "msf_wall_clock_khz", "msf_pivot_model_load", "msf_pivot_model_clear",
+           "msf_pivot_model_loaded", "msf_mlp_param_count", "msf_mlp_forward", "msf_mlp_grad",
+           "msf_mlp_adam")
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("lds_vertices", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -97,6 +109,22 @@ def _lib():
         lib.msf_last_error.restype = ctypes.c_char_p
         lib.msf_version.restype = ctypes.c_int
         lib.msf_profile_enable.argtypes = [ctypes.c_int]
+        bo = ctypes.POINTER(BatchOptions)
+        lib.msf_batched_workspace_bytes.argtypes = [i64, i64, bo]
+        lib.msf_batched_workspace_bytes.restype = sz
+        lib.msf_compute_batched.argtypes = [vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp, sz,
+                                            vp, bo]
+        lib.msf_batched_graph_create.argtypes = [vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, vp,
+                                                 vp, sz, bo, ctypes.POINTER(vp)]
+        lib.msf_batched_graph_launch.argtypes = [vp, vp]
+        lib.msf_batched_graph_destroy.argtypes = [vp]
+        lib.msf_pivot_model_load.argtypes = [vp, sz]
+        lib.msf_mlp_forward.argtypes = [vp, vp, i64, vp, ctypes.c_int, vp]
+        lib.msf_mlp_grad.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, vp, vp]
+        lib.msf_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_int, vp]
+        lib.msf_batched_autotune.argtypes = [vp, vp, vp, vp, vp, i64, i64, vp, vp, vp, vp, sz, vp,
+                                             bo, ctypes.POINTER(ctypes.c_float)]
         lib.msf_profile_read.argtypes = [ctypes.POINTER(KernelProfile), ctypes.c_int]
         _LIB = lib
     return _LIB
@@ -181,6 +209,188 @@ def profile_read():
     k = _lib().msf_profile_read(buf, 64)
     return {buf[i].name.decode(): {"launches": int(buf[i].launches), "ms": float(buf[i].total_ms),
                                    "bytes": float(buf[i].bytes)} for i in range(k)}
+
+
+def make_batch_options(block=0, lds_vertices=0, workgroups=0):
+    o = BatchOptions()
+    o.block, o.lds_vertices, o.workgroups = int(block), int(lds_vertices), int(workgroups)
+    return o
+
+
+class Batch:
+    """Device buffers of one batch of graphs plus the batched entry points.
+
+    u, v, w: concatenated int32 CUDA tensors with LOCAL vertex ids per graph;
+    edge_off, vert_off: int64 offsets (numpy or CUDA tensors) of length G + 1.
+    order defaults to largest graph first (by edge count).
+    """
+
+    def __init__(self, u, v, w, edge_off, vert_off, order="largest_first", options=None):
+        import numpy as np
+        self.lib = _lib()
+        self.u, self.v, self.w = _dev_i32(u, "u"), _dev_i32(v, "v"), _dev_i32(w, "w")
+        dev = self.u.device
+        eo = np.asarray(edge_off.cpu() if isinstance(edge_off, torch.Tensor) else edge_off,
+                        np.int64)
+        vo = np.asarray(vert_off.cpu() if isinstance(vert_off, torch.Tensor) else vert_off,
+                        np.int64)
+        self.G = len(eo) - 1
+        self.max_n = int((vo[1:] - vo[:-1]).max()) if self.G > 0 else 0
+        self.eoff = torch.from_numpy(eo).to(dev)
+        self.voff = torch.from_numpy(vo).to(dev)
+        if order == "largest_first":
+            o = np.argsort(-(eo[1:] - eo[:-1]), kind="stable").astype(np.int32)
+            self.order = torch.from_numpy(o).to(dev)
+        elif order is None:
+            self.order = None
+        else:
+            self.order = torch.as_tensor(order, dtype=torch.int32, device=dev)
+        self.options = options if options is not None else make_batch_options()
+        m = int(eo[-1]) if self.G > 0 else 0
+        self.mask = torch.empty(max(m, 1), dtype=torch.uint8, device=dev)
+        self.totals = torch.empty(max(self.G, 1), dtype=torch.int64, device=dev)
+        self.ticks = torch.empty(self.G + 1, dtype=torch.int64, device=dev)
+        need = max(int(self.lib.msf_batched_workspace_bytes(self.G, self.max_n, None)),
+                   int(self.lib.msf_batched_workspace_bytes(self.G, self.max_n,
+                                                           ctypes.byref(self.options))))
+        self.workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        self._graph = None
+
+    def _args(self):
+        return (self.u.data_ptr(), self.v.data_ptr(), self.w.data_ptr(), self.eoff.data_ptr(),
+                self.voff.data_ptr(), self.G, self.max_n,
+                self.order.data_ptr() if self.order is not None else None,
+                self.mask.data_ptr(), self.totals.data_ptr())
+
+    def launch(self, stream=None):
+        """Stream-ordered launch (no synchronisation)."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.u.device)
+        rc = self.lib.msf_compute_batched(*self._args(), self.ticks.data_ptr(),
+                                          self.workspace.data_ptr(), self.workspace.numel(),
+                                          ctypes.c_void_p(s.cuda_stream),
+                                          ctypes.byref(self.options))
+        if rc != OK:
+            raise MSFError(rc, self.lib.msf_last_error().decode(errors="replace"))
+
+    def capture(self):
+        """Captures the launch into a hipGraph once; returns self."""
+        if self._graph is None:
+            h = ctypes.c_void_p()
+            rc = self.lib.msf_batched_graph_create(*self._args(), self.ticks.data_ptr(),
+                                                   self.workspace.data_ptr(),
+                                                   self.workspace.numel(),
+                                                   ctypes.byref(self.options), ctypes.byref(h))
+            if rc != OK:
+                raise MSFError(rc, self.lib.msf_last_error().decode(errors="replace"))
+            self._graph = h
+        return self
+
+    def replay(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.u.device)
+        rc = self.lib.msf_batched_graph_launch(self._graph, ctypes.c_void_p(s.cuda_stream))
+        if rc != OK:
+            raise MSFError(rc, self.lib.msf_last_error().decode(errors="replace"))
+
+    def autotune(self, stream=None):
+        """Times every candidate configuration; adopts and returns the fastest."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.u.device)
+        best = BatchOptions()
+        ms = ctypes.c_float()
+        rc = self.lib.msf_batched_autotune(*self._args(), self.workspace.data_ptr(),
+                                           self.workspace.numel(), ctypes.c_void_p(s.cuda_stream),
+                                           ctypes.byref(best), ctypes.byref(ms))
+        if rc != OK:
+            raise MSFError(rc, self.lib.msf_last_error().decode(errors="replace"))
+        self.options = best
+        if self._graph is not None:
+            self.close()
+        return {"block": best.block, "lds_vertices": best.lds_vertices, "ms": ms.value}
+
+    def close(self):
+        if self._graph is not None:
+            self.lib.msf_batched_graph_destroy(self._graph)
+            self._graph = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------- pivot network
+
+MLP_IN, MLP_H = 16, 64
+MLP_PARAMS = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
+MODEL_MAGIC, MODEL_VERSION = 0x5046534d, 1
+DEFAULT_MODEL = os.path.join(_HERE, "data", "pivot_mlp.bin")
+
+
+def model_blob(params):
+    """Serialises FP32 parameters (length MLP_PARAMS) into the load format."""
+    import numpy as np
+    p = np.ascontiguousarray(params, np.float32)
+    if p.shape != (MLP_PARAMS,):
+        raise ValueError(f"expected {MLP_PARAMS} parameters")
+    hdr = np.array([MODEL_MAGIC, MODEL_VERSION, MLP_IN, MLP_H], np.uint32)
+    return hdr.tobytes() + p.tobytes()
+
+
+def load_pivot_model(blob_or_path=None):
+    """Loads a pivot network (bytes or a file path; default: the shipped one)."""
+    if blob_or_path is None:
+        blob_or_path = DEFAULT_MODEL
+    blob = open(blob_or_path, "rb").read() if isinstance(blob_or_path, str) else bytes(blob_or_path)
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    rc = _lib().msf_pivot_model_load(buf, len(blob))
+    if rc != OK:
+        raise MSFError(rc, "bad pivot model")
+
+
+def clear_pivot_model():
+    _lib().msf_pivot_model_clear()
+
+
+def pivot_model_loaded():
+    return bool(_lib().msf_pivot_model_loaded())
+
+
+def mlp_forward(params, x, bf16=True):
+    """params: FP32 CUDA tensor [MLP_PARAMS]; x: FP32 CUDA tensor [B, 16] -> z [B]."""
+    B = x.shape[0]
+    z = torch.empty(B, dtype=torch.float32, device=x.device)
+    s = torch.cuda.current_stream(x.device)
+    rc = _lib().msf_mlp_forward(params.data_ptr(), x.contiguous().data_ptr(), B, z.data_ptr(),
+                                1 if bf16 else 0, ctypes.c_void_p(s.cuda_stream))
+    if rc != OK:
+        raise MSFError(rc)
+    return z
+
+
+def mlp_grad(params, x, target, bf16=True):
+    """Gradient of mean (z - target)^2 / 2; returns (grad [MLP_PARAMS], loss tensor [1])."""
+    B = x.shape[0]
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    s = torch.cuda.current_stream(x.device)
+    rc = _lib().msf_mlp_grad(params.data_ptr(), x.contiguous().data_ptr(),
+                             target.contiguous().data_ptr(), B, 1 if bf16 else 0, g.data_ptr(),
+                             loss.data_ptr(), ctypes.c_void_p(s.cuda_stream))
+    if rc != OK:
+        raise MSFError(rc)
+    return g, loss
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    s = torch.cuda.current_stream(params.device)
+    rc = _lib().msf_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), lr,
+                             beta1, beta2, eps, step, ctypes.c_void_p(s.cuda_stream))
+    if rc != OK:
+        raise MSFError(rc)
+
+
+def wall_clock_khz():
+    return int(_lib().msf_wall_clock_khz())
 
 
 def compute_raw(u_ptr, v_ptr, w_ptr, m, n, mask_ptr, workspace_ptr=0, workspace_bytes=0,

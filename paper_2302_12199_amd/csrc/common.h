@@ -41,6 +41,7 @@ struct Ctrl {
     uint32_t tail_live[24];  // per tail round: vertices with an incident edge
     uint32_t tail_found[24]; // per tail round: MSF edges found
     uint32_t tail_scan[24];  // per tail round: live pairs scanned
+    float feat[16];          // filter: features of the last pivot sample
     uint64_t aux[4];         // spare
 };
 

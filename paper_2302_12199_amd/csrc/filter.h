@@ -15,7 +15,7 @@ uint64_t pivot_stream_base(uint64_t seed, uint32_t split);
 
 // filter.hip launchers
 void launch_sample_pivot(int in_mode, const View& g, uint64_t base, int sample, float q,
-                         const float* q_dev, Ctrl* ctrl, hipStream_t s);
+                         const float* mlp, float comps, int depth, Ctrl* ctrl, hipStream_t s);
 void launch_count_light(int in_mode, const View& g, const uint64_t* pivot_dev, Ctrl* ctrl,
                         hipStream_t s);
 void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_dev, EdgeSoA out,

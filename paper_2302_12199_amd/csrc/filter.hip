@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "filter.h"
+#include "mlp.h"
 #include "prim.h"
 
 namespace msf {
@@ -24,6 +25,7 @@ namespace {
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ULL;
 constexpr uint64_t kPivotTag = 0x50495654ULL;   // stream tag of the pivot sampler
 constexpr int kSampleMax = 8192;
+constexpr int kEndSample = 2048;      // sampled edges whose endpoints feed feature 14
 constexpr int kSampleThreads = 1024;
 constexpr int kMaxDepth = 48;
 }  // namespace
@@ -56,26 +58,54 @@ __device__ __forceinline__ uint64_t key_at(const View& g, int64_t p) {
 // Pivot selection: `sample` keys drawn with replacement at positions
 // floor(r_i * len / 2^64), r_i the i-th output of the counter-based stream
 // `base`; bitonic sort in LDS; pivot = sorted[floor(q * (sample - 1))].
-// One workgroup.  q comes from q_dev when given (the pivot network's output,
-// already clamped), else from the argument.
+// One workgroup.  With a pivot network (`mlp` non-null) q is its output on
+// features of the sorted sample, clamped to [2^-10, 1 - 2^-10] (a non-finite
+// output falls back to the median); otherwise q is the argument.  The
+// features are always written to ctrl->feat:
+//   0-4   L(w) at the 10/25/50/75/90 % sample quantiles, L(w) = log2(1+w)/32
+//   5, 6  mean and standard deviation of L over the sample
+//   7     fraction of adjacent equal weights in the sorted sample (ties)
+//   8, 9  L of the smallest and largest sampled weight
+//   10    log2(1 + current components) / 32
+//   11    log2(1 + edges of this graph) / 32
+//   12    log2(1 + edges / components) / 8
+//   13    recursion depth / 16
+//   14    fraction of repeated endpoints among the first <= 2048 sampled
+//         edges (a degree-skew proxy)
+//   15    1
 template <int MODE>
 __global__ __launch_bounds__(kSampleThreads) void k_sample_pivot(View g, uint64_t base,
                                                                  int sample, float q,
-                                                                 const float* q_dev,
+                                                                 const float* __restrict__ mlp,
+                                                                 float comps, int depth,
                                                                  Ctrl* ctrl) {
     __shared__ uint64_t keys[kSampleMax];
+    __shared__ int32_t ends[kEndSample * 2];
+    __shared__ float red[2 * kSampleThreads / kWave];
+    __shared__ float feat[kMlpIn];
+    __shared__ float hid[2 * kMlpH];
+    __shared__ uint32_t s_cnt[2];
     int p2 = 1;
     while (p2 < sample) p2 <<= 1;
+    const int ke = sample < kEndSample ? sample : kEndSample;
+    int e2 = 1;
+    while (e2 < 2 * ke) e2 <<= 1;
     const uint64_t len = (uint64_t)g.len;
+    if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < p2; i += blockDim.x) {
         uint64_t k = kKeyMax;
         if (i < sample) {
             const uint64_t r = sm_mix(base + (uint64_t)(i + 1) * kGamma);
-            const uint64_t pos = __umul64hi(r, len);
-            k = key_at<MODE>(g, (int64_t)pos);
+            const int64_t pos = (int64_t)__umul64hi(r, len);
+            k = key_at<MODE>(g, pos);
+            if (i < ke) {
+                ends[2 * i] = g.u[pos];
+                ends[2 * i + 1] = g.v[pos];
+            }
         }
         keys[i] = k;
     }
+    for (int i = 2 * ke + threadIdx.x; i < e2; i += blockDim.x) ends[i] = 0x7fffffff;
     __syncthreads();
     for (int k = 2; k <= p2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -90,8 +120,69 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_pivot(View g, uint64_
             __syncthreads();
         }
     }
+    for (int k = 2; k <= e2; k <<= 1) {              // sort sampled endpoints
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < e2; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const int32_t a = ends[i], b = ends[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) { ends[i] = b; ends[ixj] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // sample statistics (FP32)
+    float sl = 0.f, sl2 = 0.f;
+    uint32_t ties = 0, reps = 0;
+    for (int i = threadIdx.x; i < sample; i += blockDim.x) {
+        const float l = __log2f(1.f + (float)(keys[i] >> 32)) * (1.f / 32.f);
+        sl += l;
+        sl2 += l * l;
+        if (i + 1 < sample && (keys[i] >> 32) == (keys[i + 1] >> 32)) ++ties;
+    }
+    for (int i = threadIdx.x; i + 1 < 2 * ke; i += blockDim.x) reps += ends[i] == ends[i + 1];
+    for (int off = 32; off > 0; off >>= 1) {
+        sl += __shfl_xor(sl, off, 64);
+        sl2 += __shfl_xor(sl2, off, 64);
+    }
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == 0) { red[wv] = sl; red[kSampleThreads / kWave + wv] = sl2; }
+    if (ties) atomicAdd(&s_cnt[0], ties);
+    if (reps) atomicAdd(&s_cnt[1], reps);
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const float qq = q_dev ? *q_dev : q;
+        float a = 0.f, b = 0.f;
+        for (int i = 0; i < kSampleThreads / kWave; ++i) { a += red[i]; b += red[kSampleThreads / kWave + i]; }
+        const float mean = a / (float)sample;
+        const float var = b / (float)sample - mean * mean;
+        const float qs[5] = {0.1f, 0.25f, 0.5f, 0.75f, 0.9f};
+        for (int k = 0; k < 5; ++k) {
+            const int idx = (int)(qs[k] * (float)(sample - 1));
+            feat[k] = __log2f(1.f + (float)(keys[idx] >> 32)) * (1.f / 32.f);
+        }
+        feat[5] = mean;
+        feat[6] = sqrtf(var > 0.f ? var : 0.f);
+        feat[7] = sample > 1 ? (float)s_cnt[0] / (float)(sample - 1) : 0.f;
+        feat[8] = __log2f(1.f + (float)(keys[0] >> 32)) * (1.f / 32.f);
+        feat[9] = __log2f(1.f + (float)(keys[sample - 1] >> 32)) * (1.f / 32.f);
+        feat[10] = __log2f(1.f + comps) * (1.f / 32.f);
+        feat[11] = __log2f(1.f + (float)len) * (1.f / 32.f);
+        feat[12] = __log2f(1.f + (float)len / (comps > 1.f ? comps : 1.f)) * (1.f / 8.f);
+        feat[13] = (float)depth * (1.f / 16.f);
+        feat[14] = 2 * ke > 1 ? (float)s_cnt[1] / (float)(2 * ke - 1) : 0.f;
+        feat[15] = 1.f;
+        for (int k = 0; k < kMlpIn; ++k) ctrl->feat[k] = feat[k];
+    }
+    __syncthreads();
+    float qq = q;
+    if (mlp) {
+        const float z = mlp_infer_block(mlp, feat, hid);
+        const float p = 1.f / (1.f + expf(-z));
+        qq = (p == p) ? fminf(fmaxf(p, kQMin), 1.f - kQMin) : 0.5f;
+    }
+    if (threadIdx.x == 0) {
         int idx = (int)floor((double)qq * (double)(sample - 1));
         if (idx < 0) idx = 0;
         if (idx > sample - 1) idx = sample - 1;
@@ -201,13 +292,13 @@ void launch_iota(int32_t* p, int64_t n, hipStream_t s) {
 }
 
 void launch_sample_pivot(int in_mode, const View& g, uint64_t base, int sample, float q,
-                         const float* q_dev, Ctrl* ctrl, hipStream_t s) {
+                         const float* mlp, float comps, int depth, Ctrl* ctrl, hipStream_t s) {
     if (in_mode == kOrig)
         hipLaunchKernelGGL(k_sample_pivot<kOrig>, dim3(1), dim3(kSampleThreads), 0, s, g, base,
-                           sample, q, q_dev, ctrl);
+                           sample, q, mlp, comps, depth, ctrl);
     else
         hipLaunchKernelGGL(k_sample_pivot<kCompact>, dim3(1), dim3(kSampleThreads), 0, s, g,
-                           base, sample, q, q_dev, ctrl);
+                           base, sample, q, mlp, comps, depth, ctrl);
 }
 
 void launch_count_light(int in_mode, const View& g, const uint64_t* pivot_dev, Ctrl* ctrl,
@@ -317,9 +408,10 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
 
     const uint32_t split = C.splits++;
     const float q = C.opt.pivot == MSF_PIVOT_QUANTILE ? C.opt.quantile : 0.5f;
+    const float* net = C.opt.pivot == MSF_PIVOT_MLP ? mlp_device_params() : nullptr;
     int h = prof_begin(K_SAMPLE, C.s);
-    launch_sample_pivot(mode, g, pivot_stream_base(C.opt.seed, split), C.sample, q, nullptr,
-                        C.B.ctrl, C.s);
+    launch_sample_pivot(mode, g, pivot_stream_base(C.opt.seed, split), C.sample, q, net,
+                        (float)comps, depth, C.B.ctrl, C.s);
     prof_end(h, C.s, 8.0 * C.sample);
     const int tgt = where == 0 ? 1 : 0;
     const EdgeSoA R = C.buf[tgt];
@@ -345,7 +437,10 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
         C.st->split_q[split] = hc->q_used;
         C.st->split_kept[split] = 0;
     }
-    if (split == 0) C.st->pivot_q_used = hc->q_used;
+    if (split == 0) {
+        C.st->pivot_q_used = hc->q_used;
+        memcpy(C.st->top_features, hc->feat, sizeof C.st->top_features);
+    }
     C.st->levels += 1;
     if (nl == 0 || nh == 0) return base_case(C, mode, g);   // degenerate pivot
 

@@ -102,3 +102,24 @@ def test_no_cpu_fallback(msf, monkeypatch, tmp_path):
     monkeypatch.setattr(msf, "_LIB", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         msf.library()
+
+
+def test_batched_argument_checks(msf):
+    lib = msf.library()
+    o = msf.make_batch_options(block=300)
+    rc = lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, 3, 10, None, FAKE, FAKE, None,
+                                 FAKE, 1 << 30, None, ctypes.byref(o))
+    assert rc == msf.EINVAL
+    rc = lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, -1, 10, None, FAKE, FAKE, None,
+                                 FAKE, 1 << 30, None, None)
+    assert rc == msf.EINVAL
+    rc = lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, 3, 10, None, FAKE, FAKE, None,
+                                 FAKE, 16, None, None)
+    assert rc == msf.EWORKSPACE
+    o = msf.make_batch_options()
+    o.reserved[0] = 1
+    assert lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, 3, 10, None, FAKE, FAKE, None,
+                                   FAKE, 1 << 30, None, ctypes.byref(o)) == msf.EINVAL
+    # an empty batch needs no device
+    assert lib.msf_compute_batched(None, None, None, None, None, 0, 0, None, None, None, None,
+                                   None, 0, None, None) == msf.OK

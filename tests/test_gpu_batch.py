@@ -1,0 +1,123 @@
+"""Parity of the batched persistent solver (needs a GPU): every graph's MSF
+mask and total against the per-graph CPU oracle."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from gpu_util import banner, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_batch(u, v, w, eo, vo):
+    masks, totals = [], []
+    for g in range(len(eo) - 1):
+        a, b = eo[g], eo[g + 1]
+        mk, t, _ = oracle.kruskal(u[a:b], v[a:b], w[a:b], int(vo[g + 1] - vo[g]))
+        masks.append(mk)
+        totals.append(t)
+    return (np.concatenate(masks) if masks else np.zeros(0, np.uint8)), np.array(totals, np.uint64)
+
+
+def make_batch(u, v, w, eo, vo, **kw):
+    import paper_2302_12199_amd as msf
+    tu, tv, tw = to_dev(u, v, w)
+    return msf.Batch(tu, tv, tw, eo, vo, **kw)
+
+
+def results(b):
+    import torch
+    torch.cuda.synchronize()
+    m = int(b.eoff[-1].item()) if b.G else 0
+    return b.mask[:m].cpu().numpy(), b.totals[:b.G].cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("block,lds", [(1024, 0), (256, -1), (512, 1024), (1024, 4096)])
+def test_batch_matches_oracle(block, lds):
+    import paper_2302_12199_amd as msf
+    banner(f"batch block={block} lds={lds}")
+    u, v, w, eo, vo = graphgen.batch_gnm(300, lo=8, hi=13, seed=11)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    b = make_batch(u, v, w, eo, vo, options=msf.make_batch_options(block=block, lds_vertices=lds))
+    b.launch()
+    mask, totals = results(b)
+    assert (totals == rt).all()
+    assert (mask == rm).all()
+
+
+def test_batch_unordered_and_ticks():
+    banner("batch unordered, ticks")
+    u, v, w, eo, vo = graphgen.batch_gnm(120, lo=8, hi=12, dlo=1, dhi=8, wlo=1, whi=7, seed=12)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    b = make_batch(u, v, w, eo, vo, order=None)
+    b.launch()
+    mask, totals = results(b)
+    assert (mask == rm).all() and (totals == rt).all()
+    ticks = b.ticks.cpu().numpy().view(np.uint64)
+    assert (ticks[:-1] >= ticks[-1]).all()
+
+
+def test_batch_graph_capture_replays_match_eager():
+    import torch
+    banner("batch hipGraph replay")
+    u, v, w, eo, vo = graphgen.batch_gnm(200, lo=8, hi=12, seed=13)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    b = make_batch(u, v, w, eo, vo)
+    b.launch()
+    eager = results(b)
+    assert (eager[0] == rm).all() and (eager[1] == rt).all()
+    b.capture()
+    for _ in range(3):
+        b.mask.fill_(7)                    # eager work between replays
+        b.totals.fill_(0)
+        torch.cuda.synchronize()
+        b.replay()
+        mask, totals = results(b)
+        assert (mask == rm).all() and (totals == rt).all()
+    b.close()
+
+
+def test_batch_edge_cases_and_invalid_graph():
+    banner("batch edge cases")
+    # graph 0: single vertex with self-loops; graph 1: no edges; graph 2: invalid id;
+    # graph 3: two vertices, parallel edges; graph 4: ordinary
+    gs = [(1, [(0, 0, 5), (0, 0, 1)]), (3, []), (4, [(0, 1, 2), (1, 9, 3)]),
+          (2, [(0, 1, 9), (1, 0, 4), (0, 1, 4)]), (5, [(0, 1, 1), (1, 2, 1), (2, 0, 1), (3, 4, 0)])]
+    u, v, w, eo, vo = [], [], [], [0], [0]
+    for n, es in gs:
+        for a, b, c in es:
+            u.append(a); v.append(b); w.append(c)
+        eo.append(eo[-1] + len(es))
+        vo.append(vo[-1] + n)
+    u, v, w = np.array(u, np.int32), np.array(v, np.int32), np.array(w, np.uint32)
+    eo, vo = np.array(eo, np.int64), np.array(vo, np.int64)
+    b = make_batch(u, v, w, eo, vo)
+    b.launch()
+    mask, totals = results(b)
+    assert totals[0] == 0 and totals[1] == 0
+    assert totals[2] == np.uint64(2**64 - 1)
+    assert totals[3] == 4 and list(mask[eo[3]:eo[4]]) == [0, 1, 0]
+    assert totals[4] == 2 and list(mask[eo[4]:eo[5]]) == [1, 1, 0, 1]
+
+
+def test_batch_autotune_then_correct():
+    banner("batch autotune")
+    u, v, w, eo, vo = graphgen.batch_gnm(100, lo=8, hi=12, seed=14)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    b = make_batch(u, v, w, eo, vo)
+    cfg = b.autotune()
+    assert cfg["block"] in (256, 512, 1024) and cfg["ms"] > 0
+    b.launch()
+    mask, totals = results(b)
+    assert (mask == rm).all() and (totals == rt).all()
+
+
+def test_batch_large_graphs_global_scratch():
+    banner("batch large graphs")
+    u, v, w, eo, vo = graphgen.batch_gnm(24, lo=15, hi=17.5, seed=15)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    b = make_batch(u, v, w, eo, vo)
+    b.launch()
+    mask, totals = results(b)
+    assert (totals == rt).all() and (mask == rm).all()

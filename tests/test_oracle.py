@@ -262,3 +262,33 @@ def test_filter_reference_pivot_is_sample_quantile():
     assert len(np.unique(pos)) > 950
     assert pivot_index(0.5, 4096) == 2047 and pivot_index(0.0, 4096) == 0
     assert pivot_index(1.0, 4096) == 4095
+
+
+def test_mlp_reference_gradient_matches_finite_differences():
+    from oracle import mlp_ref
+    rng = np.random.default_rng(3)
+    p = mlp_ref.init_params(1)
+    x = rng.normal(0, 1, (7, mlp_ref.IN))
+    t = rng.normal(0, 1, 7)
+    loss, g = mlp_ref.loss_and_grad(p, x, t)
+    eps = 1e-6
+    idx = rng.choice(mlp_ref.P, 80, replace=False)
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += eps
+        pm[i] -= eps
+        fd = (mlp_ref.loss_and_grad(pp, x, t)[0] - mlp_ref.loss_and_grad(pm, x, t)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 + 1e-5 * abs(fd)
+
+
+def test_mlp_reference_bf16_rounding():
+    from oracle import mlp_ref
+    vals = np.array([1.0, 1.0 + 2**-8, 1.0 + 2**-7 + 2**-9, -3.14159, 0.0, 1e-40], np.float32)
+    r = mlp_ref.bf16(vals)
+    assert r[0] == 1.0 and r[1] == 1.0            # tie -> even
+    assert r[2] == 1.0 + 2**-7                    # below half a step -> down
+    assert mlp_ref.bf16(np.float32(1.0 + 2**-7 + 2**-8))[()] == 1.0 + 2**-6   # tie -> even (up)
+    assert abs(r[3] + 3.140625) < 1e-12
+    # every result is representable in bfloat16
+    bits = r.astype(np.float32).view(np.uint32)
+    assert (bits & 0xFFFF == 0).all()
