@@ -326,6 +326,17 @@ MODEL_MAGIC, MODEL_VERSION = 0x5046534d, 1
 DEFAULT_MODEL = os.path.join(_HERE, "data", "pivot_mlp.bin")
 
 
+def init_pivot_params(seed=0):
+    """He-initialised FP32 network parameters (biases zero), flat in the
+    load layout W1[64][16], b1[64], W2[64][64], b2[64], w3[64], b3."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0, (2.0 / MLP_IN) ** 0.5, MLP_H * MLP_IN), np.zeros(MLP_H),
+             rng.normal(0, (2.0 / MLP_H) ** 0.5, MLP_H * MLP_H), np.zeros(MLP_H),
+             rng.normal(0, (1.0 / MLP_H) ** 0.5, MLP_H), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 def model_blob(params):
     """Serialises FP32 parameters (length MLP_PARAMS) into the load format."""
     import numpy as np

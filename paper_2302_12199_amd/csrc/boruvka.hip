@@ -85,8 +85,11 @@ __global__ __launch_bounds__(kBlock) void k_minedge_r0(
     int64_t m, int64_t n, uint64_t* __restrict__ best, Ctrl* ctrl) {
     bool bad = false;
     const int64_t groups = (m + VEC - 1) / VEC;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < groups;
-         g += (int64_t)gridDim.x * blockDim.x) {
+    // the loop bound is uniform over the workgroup: every wave runs each step
+    // with all lanes (wave_min_update needs whole waves)
+    for (int64_t g0 = blockIdx.x * (int64_t)blockDim.x; g0 < groups;
+         g0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = g0 + threadIdx.x;
         int32_t aa[VEC], bb[VEC];
         uint32_t ww[VEC];
         if (VEC == 4 && g * 4 + 3 < m) {
@@ -108,13 +111,17 @@ __global__ __launch_bounds__(kBlock) void k_minedge_r0(
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
             const int64_t e = g * VEC + k;
-            if (e >= m) continue;
-            const int32_t a = aa[k], b = bb[k];
-            if ((uint32_t)a >= (uint64_t)n || (uint32_t)b >= (uint64_t)n) { bad = true; continue; }
-            if (a == b) continue;
+            int32_t a = aa[k], b = bb[k];
+            bool act = e < m;
+            if (act && ((uint32_t)a >= (uint64_t)n || (uint32_t)b >= (uint64_t)n)) {
+                bad = true;
+                act = false;
+            }
+            act = act && a != b;
+            if (!act) a = b = 0;
             const uint64_t key = ((uint64_t)ww[k] << 32) | (uint64_t)e;
-            atomic_min_key(&best[a], key);
-            atomic_min_key(&best[b], key);
+            wave_min_update(best, a, key, act);
+            wave_min_update(best, b, key, act);
         }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrRange);
@@ -127,8 +134,9 @@ __global__ __launch_bounds__(kBlock) void k_minedge_r0(
 // best[x]; the smaller id is the root.  Every other live vertex owns exactly
 // one MSF edge and marks it, so each MSF edge is counted once.  `cmap` maps
 // the view's stored labels to this round's labels (null: identity).
+constexpr int kHookBlock = 1024;
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_hook(const uint64_t* __restrict__ best, int64_t nr,
+__global__ __launch_bounds__(kHookBlock) void k_hook(const uint64_t* __restrict__ best, int64_t nr,
                                                  View g, const int32_t* __restrict__ cmap,
                                                  int32_t* __restrict__ parent,
                                                  uint8_t* __restrict__ mask, Ctrl* ctrl) {
@@ -155,18 +163,38 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint64_t* __restrict__ be
             ++nfound;
         }
     }
+    // one set of counter atomics per workgroup (same-address atomics from
+    // every wave would serialise)
+    __shared__ uint64_t s_red[3][kHookBlock / kWave];
+    __shared__ uint32_t s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
     wsum = wave_sum_u64(wsum);
     nfound = wave_sum_u64(nfound);
     nlive = wave_sum_u64(nlive);
+    const int wave = threadIdx.x / kWave;
+    __syncthreads();
     if (lane_id() == 0) {
-        if (nfound) {
-            atomicAdd((unsigned long long*)&ctrl->total, (unsigned long long)wsum);
-            atomicAdd((unsigned long long*)&ctrl->msf_edges, (unsigned long long)nfound);
-            atomicAdd((unsigned long long*)&ctrl->found, (unsigned long long)nfound);
-        }
-        if (nlive) atomicAdd((unsigned long long*)&ctrl->live, (unsigned long long)nlive);
+        s_red[0][wave] = wsum;
+        s_red[1][wave] = nfound;
+        s_red[2][wave] = nlive;
     }
-    if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrInternal);
+    if (__ballot(bad) && lane_id() == 0) s_bad = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0, f = 0, l = 0;
+        for (int i = 0; i < kHookBlock / kWave; ++i) {
+            a += s_red[0][i];
+            f += s_red[1][i];
+            l += s_red[2][i];
+        }
+        if (f) {
+            atomicAdd((unsigned long long*)&ctrl->total, (unsigned long long)a);
+            atomicAdd((unsigned long long*)&ctrl->msf_edges, (unsigned long long)f);
+            atomicAdd((unsigned long long*)&ctrl->found, (unsigned long long)f);
+        }
+        if (l) atomicAdd((unsigned long long*)&ctrl->live, (unsigned long long)l);
+        if (s_bad) atomicOr(&ctrl->err, kErrInternal);
+    }
 }
 
 // Pointer jumping in place: each vertex repeatedly replaces its parent by its
@@ -490,7 +518,6 @@ __global__ __launch_bounds__(kBlock) void k_compact(View g, const int32_t* __res
     uint64_t off = prefix + woff;
 #pragma unroll
     for (int k = 0; k < kIt; ++k) {
-        const int64_t e = e0 + k * kWave;
         if ((mk[k] >> lane) & 1) {
             const uint64_t o = off + lanes_below(mk[k]);
             out.u[o] = a[k];
@@ -541,7 +568,9 @@ void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, in
 }
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
                  int32_t* parent, uint8_t* mask, Ctrl* ctrl, hipStream_t s) {
-    const dim3 gr(grid_for(nr)), bl(kBlock);
+    int64_t hb = (nr + kHookBlock - 1) / kHookBlock;
+    hb = hb < 1 ? 1 : (hb > 256 ? 256 : hb);
+    const dim3 gr((unsigned)hb), bl(kHookBlock);
     switch (mode) {
         case kOrig: hipLaunchKernelGGL(k_hook<kOrig>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
         case kFull32: hipLaunchKernelGGL(k_hook<kFull32>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;

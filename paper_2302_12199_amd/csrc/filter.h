@@ -16,10 +16,10 @@ uint64_t pivot_stream_base(uint64_t seed, uint32_t split);
 // filter.hip launchers
 void launch_sample_pivot(int in_mode, const View& g, uint64_t base, int sample, float q,
                          const float* mlp, float comps, int depth, Ctrl* ctrl, hipStream_t s);
-void launch_count_light(int in_mode, const View& g, const uint64_t* pivot_dev, Ctrl* ctrl,
-                        hipStream_t s);
+void launch_split_count(int in_mode, const View& g, const uint64_t* pivot_dev, uint64_t* cnt,
+                        Ctrl* ctrl, hipStream_t s);
 void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_dev, EdgeSoA out,
-                  uint64_t* status, Ctrl* ctrl, hipStream_t s);
+                  const uint64_t* tile_off, Ctrl* ctrl, hipStream_t s);
 void launch_iota(int32_t* p, int64_t n, hipStream_t s);
 
 }  // namespace msf

@@ -191,44 +191,106 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_pivot(View g, uint64_
     }
 }
 
-// Light-edge count of a split (key <= pivot), accumulated into ctrl->light.
+// Split counts, reduce-then-scan: the light-edge count (key <= pivot) of
+// every 2048-edge tile goes to cnt[tile]; k_scan_tiles turns the counts into
+// exclusive offsets, so the split pass needs no inter-tile waiting.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_count_light(View g,
+__global__ __launch_bounds__(kBlock) void k_count_tiles(View g,
                                                         const uint64_t* __restrict__ pivot_dev,
-                                                        Ctrl* ctrl) {
+                                                        uint64_t* __restrict__ cnt,
+                                                        uint32_t ntiles) {
+    __shared__ uint32_t s_wave[kBlock / kWave];
     const uint64_t pivot = *pivot_dev;
-    uint64_t c = 0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < g.len;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t id = MODE == kCompact ? (uint64_t)g.id[e] : (uint64_t)e;
-        c += (((uint64_t)g.w[e] << 32) | id) <= pivot;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t e0 = (int64_t)t * kRelabelTile + threadIdx.x;
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kRelabelItems; ++k) {
+            const int64_t e = e0 + k * kBlock;
+            if (e < g.len) {
+                const uint64_t id = MODE == kCompact ? (uint64_t)g.id[e] : (uint64_t)e;
+                c += (((uint64_t)g.w[e] << 32) | id) <= pivot;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+        if (lane == 0) s_wave[wave] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t sum = 0;
+            for (int i = 0; i < kBlock / kWave; ++i) sum += s_wave[i];
+            cnt[t] = sum;
+        }
+        __syncthreads();
     }
-    c = wave_sum_u64(c);
-    if (lane_id() == 0 && c) atomicAdd((unsigned long long*)&ctrl->light, (unsigned long long)c);
 }
 
-// Stable two-way split by key <= pivot with one decoupled-lookback scan over
-// the light flags: a light edge goes to out[#light before it], a heavy one to
-// out[nl' + #heavy before it] (nl' = ctrl->light from the count pass rounded
-// up to a multiple of 4, so both parts start 16-byte aligned).  On the
-// caller's arrays the ids are validated.
+// Exclusive scan of cnt[0, ntiles) in place by one workgroup of
+// kScanThreads threads, 8 consecutive entries per thread per sweep; the
+// total goes to ctrl->light.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint64_t* __restrict__ cnt,
+                                                             uint32_t ntiles, Ctrl* ctrl) {
+    constexpr int kPer = 8;
+    __shared__ uint64_t s_w[kScanThreads / kWave];
+    __shared__ uint64_t s_carry;
+    const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
+    if (t == 0) s_carry = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < ntiles; base += (uint64_t)kPer * kScanThreads) {
+        const uint64_t i0 = base + (uint64_t)t * kPer;
+        uint64_t c[kPer], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            c[k] = i0 + k < ntiles ? cnt[i0 + k] : 0;
+            sum += c[k];
+        }
+        uint64_t x = sum;   // inclusive scan over the wave
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint64_t y = __shfl_up(x, off, kWave);
+            if (lane >= off) x += y;
+        }
+        if (lane == kWave - 1) s_w[wave] = x;
+        __syncthreads();
+        uint64_t wpre = 0, tot = 0;
+        for (int i = 0; i < kScanThreads / kWave; ++i) {
+            const uint64_t v = s_w[i];
+            if (i < wave) wpre += v;
+            tot += v;
+        }
+        uint64_t run = s_carry + wpre + (x - sum);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (i0 + k < ntiles) cnt[i0 + k] = run;
+            run += c[k];
+        }
+        __syncthreads();
+        if (t == 0) s_carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) ctrl->light = s_carry;
+}
+
+// Stable two-way split by key <= pivot: tile t writes its light edges from
+// off[t] on and its heavy edges from nl' + (t * 2048 - off[t]) on, where
+// nl' = ctrl->light rounded up to a multiple of 4 (both parts start 16-byte
+// aligned).  On the caller's arrays the ids are validated.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_split(View g, int64_t n,
                                                   const uint64_t* __restrict__ pivot_dev,
-                                                  EdgeSoA out, uint64_t* status, Ctrl* ctrl,
-                                                  uint32_t ntiles) {
+                                                  EdgeSoA out,
+                                                  const uint64_t* __restrict__ tile_off,
+                                                  Ctrl* ctrl) {
     constexpr int kIt = kRelabelItems;
-    __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wave[kBlock / kWave];
-    __shared__ uint64_t s_prefix;
-    const uint32_t tile = take_tile(ctrl, &s_tile);
+    const uint32_t tile = blockIdx.x;
     const uint64_t pivot = *pivot_dev;
-    const uint64_t nl_al = (ctrl->light + 3) & ~3ull;   // heavy part starts 16-byte aligned
+    const uint64_t nl_al = (ctrl->light + 3) & ~3ull;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t e0 = (int64_t)tile * (kBlock * kIt) + (int64_t)wave * (kWave * kIt) + lane;
     const int64_t m = g.len;
     int32_t a[kIt], b[kIt];
-    uint32_t w[kIt];
+    uint32_t w[kIt], idv[kIt];
     uint64_t mk[kIt];
     uint32_t cnt = 0;
     bool bad = false;
@@ -236,17 +298,18 @@ __global__ __launch_bounds__(kBlock) void k_split(View g, int64_t n,
     for (int k = 0; k < kIt; ++k) {
         const int64_t e = e0 + k * kWave;
         a[k] = b[k] = 0;
-        w[k] = 0;
+        w[k] = idv[k] = 0;
         bool lt = false;
         if (e < m) {
             a[k] = g.u[e];
             b[k] = g.v[e];
             w[k] = g.w[e];
+            idv[k] = MODE == kCompact ? g.id[e] : (uint32_t)e;
             if (MODE == kOrig && ((uint32_t)a[k] >= (uint64_t)n || (uint32_t)b[k] >= (uint64_t)n)) {
                 bad = true;
                 a[k] = b[k] = 0;
             }
-            const uint64_t id = MODE == kCompact ? (uint64_t)g.id[e] : (uint64_t)e;
+            const uint64_t id = MODE == kCompact ? (uint64_t)idv[k] : (uint64_t)e;
             lt = (((uint64_t)w[k] << 32) | id) <= pivot;
         }
         mk[k] = __ballot(lt);
@@ -255,25 +318,21 @@ __global__ __launch_bounds__(kBlock) void k_split(View g, int64_t n,
     if (__ballot(bad) && lane == 0) atomicOr(&ctrl->err, kErrRange);
     if (lane == 0) s_wave[wave] = cnt;
     __syncthreads();
-    uint32_t agg = 0, woff = 0;
+    uint32_t woff = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i) {
+    for (int i = 0; i < kBlock / kWave; ++i)
         if (i < wave) woff += s_wave[i];
-        agg += s_wave[i];
-    }
-    const uint64_t prefix = tile_prefix(status, tile, agg, ctrl, &s_prefix);
-    uint64_t off = prefix + woff;
+    uint64_t off = tile_off[tile] + woff;
 #pragma unroll
     for (int k = 0; k < kIt; ++k) {
         const int64_t e = e0 + k * kWave;
         if (e < m) {
             const uint64_t before = off + lanes_below(mk[k]);   // light edges before e
-            const uint32_t id = MODE == kCompact ? g.id[e] : (uint32_t)e;
             const uint64_t o = ((mk[k] >> lane) & 1) ? before : nl_al + ((uint64_t)e - before);
             out.u[o] = a[k];
             out.v[o] = b[k];
             out.w[o] = w[k];
-            out.id[o] = id;
+            out.id[o] = idv[k];
         }
         off += __popcll(mk[k]);
     }
@@ -301,27 +360,30 @@ void launch_sample_pivot(int in_mode, const View& g, uint64_t base, int sample, 
                            base, sample, q, mlp, comps, depth, ctrl);
 }
 
-void launch_count_light(int in_mode, const View& g, const uint64_t* pivot_dev, Ctrl* ctrl,
-                        hipStream_t s) {
+void launch_split_count(int in_mode, const View& g, const uint64_t* pivot_dev, uint64_t* cnt,
+                        Ctrl* ctrl, hipStream_t s) {
     if (g.len <= 0) return;
+    const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
+    const unsigned grid = nt < 8192u ? nt : 8192u;
     if (in_mode == kOrig)
-        hipLaunchKernelGGL(k_count_light<kOrig>, dim3(grid_cap(g.len)), dim3(kBlock), 0, s, g,
-                           pivot_dev, ctrl);
+        hipLaunchKernelGGL(k_count_tiles<kOrig>, dim3(grid), dim3(kBlock), 0, s, g, pivot_dev,
+                           cnt, nt);
     else
-        hipLaunchKernelGGL(k_count_light<kCompact>, dim3(grid_cap(g.len)), dim3(kBlock), 0, s, g,
-                           pivot_dev, ctrl);
+        hipLaunchKernelGGL(k_count_tiles<kCompact>, dim3(grid), dim3(kBlock), 0, s, g, pivot_dev,
+                           cnt, nt);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, cnt, nt, ctrl);
 }
 
 void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_dev, EdgeSoA out,
-                  uint64_t* status, Ctrl* ctrl, hipStream_t s) {
+                  const uint64_t* tile_off, Ctrl* ctrl, hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     if (in_mode == kOrig)
         hipLaunchKernelGGL(k_split<kOrig>, dim3(nt), dim3(kBlock), 0, s, g, n, pivot_dev, out,
-                           status, ctrl, nt);
+                           tile_off, ctrl);
     else
         hipLaunchKernelGGL(k_split<kCompact>, dim3(nt), dim3(kBlock), 0, s, g, n, pivot_dev, out,
-                           status, ctrl, nt);
+                           tile_off, ctrl);
 }
 
 // ------------------------------------------------------------------ driver
@@ -362,6 +424,7 @@ struct Ctx {
     int sample;
     int64_t min_split;
     int sparse_deg;
+    float q_net;   // quantile the network chose at the top split (0 = not yet)
 };
 
 View view_of(const EdgeSoA& e, int64_t len) {
@@ -407,19 +470,23 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
     if (sparse) return base_case(C, mode, g);
 
     const uint32_t split = C.splits++;
-    const float q = C.opt.pivot == MSF_PIVOT_QUANTILE ? C.opt.quantile : 0.5f;
-    const float* net = C.opt.pivot == MSF_PIVOT_MLP ? mlp_device_params() : nullptr;
+    // The network picks one quantile per call, on the top split's sample;
+    // deeper splits reuse it (a constant quantile per call is also what its
+    // training targets were measured with).
+    float q = C.opt.pivot == MSF_PIVOT_QUANTILE ? C.opt.quantile : 0.5f;
+    const float* net = nullptr;
+    if (C.opt.pivot == MSF_PIVOT_MLP) {
+        if (C.q_net > 0.f) q = C.q_net;
+        else net = mlp_device_params();
+    }
     int h = prof_begin(K_SAMPLE, C.s);
     launch_sample_pivot(mode, g, pivot_stream_base(C.opt.seed, split), C.sample, q, net,
                         (float)comps, depth, C.B.ctrl, C.s);
     prof_end(h, C.s, 8.0 * C.sample);
     const int tgt = where == 0 ? 1 : 0;
     const EdgeSoA R = C.buf[tgt];
-    HIP_TRY(hipMemsetAsync(&C.B.ctrl->light, 0, sizeof(uint64_t), C.s));
     h = prof_begin(K_PARTITION, C.s);
-    launch_count_light(mode, g, &C.B.ctrl->pivot, C.B.ctrl, C.s);
-    const int64_t nt = (g.len + kRelabelTile - 1) / kRelabelTile;
-    launch_scan_prep(C.B.status, nt, C.B.ctrl, 0, C.s);
+    launch_split_count(mode, g, &C.B.ctrl->pivot, C.B.status, C.B.ctrl, C.s);
     launch_split(mode, g, C.n, &C.B.ctrl->pivot, R, C.B.status, C.B.ctrl, C.s);
     prof_end(h, C.s, (mode == kOrig ? 16.0 : 24.0) * g.len + 16.0 * g.len);
     HIP_TRY(hipGetLastError());
@@ -438,6 +505,7 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
         C.st->split_kept[split] = 0;
     }
     if (split == 0) {
+        C.q_net = hc->q_used;
         C.st->pivot_q_used = hc->q_used;
         memcpy(C.st->top_features, hc->feat, sizeof C.st->top_features);
     }
@@ -491,6 +559,7 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
     C.opt = opt;
     C.st = stats;
     C.splits = 0;
+    C.q_net = 0.f;
     C.sample = opt.sample_size > 0 ? opt.sample_size : 4096;
     C.min_split = opt.min_split_edges > 0 ? opt.min_split_edges : (1 << 20);
     C.sparse_deg = opt.sparse_degree > 0 ? opt.sparse_degree : 4;

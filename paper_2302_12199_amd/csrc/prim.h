@@ -32,6 +32,34 @@ __device__ __forceinline__ void atomic_min_key(uint64_t* p, uint64_t key) {
     if (key < *p) atomicMin((unsigned long long*)p, (unsigned long long)key);
 }
 
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t y = __shfl_xor(x, off, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// atomic_min_key(&best[t], key) for every lane with `act`, called by the
+// whole wave.  Lanes aiming at the same entry as the first active lane are
+// first min-reduced across the wave and update it once: edges of one hot
+// component would otherwise queue on a single address.
+__device__ __forceinline__ void wave_min_update(uint64_t* best, int32_t t, uint64_t key,
+                                                bool act) {
+    const uint64_t am = __ballot(act);
+    if (am == 0) return;
+    const int leader = __builtin_ctzll(am);
+    const int32_t tl = __shfl(t, leader, 64);
+    const bool same = act && t == tl;
+    if (__popcll(__ballot(same)) > 1) {
+        const uint64_t k = wave_min_u64(same ? key : kKeyMax);
+        if (lane_id() == leader) atomic_min_key(&best[tl], k);
+        act = act && !same;
+    }
+    if (act) atomic_min_key(&best[t], key);
+}
+
 // Dynamic tile id: tiles are numbered in the order workgroups start, so a tile
 // only ever waits on tiles that are already running (no deadlock).
 __device__ __forceinline__ uint32_t take_tile(Ctrl* ctrl, uint32_t* s_tile) {

@@ -1,0 +1,190 @@
+"""Pivot network kernels against the float64 CPU reference, and MSF parity
+with the network choosing the Filter-Borůvka pivot."""
+import numpy as np
+import pytest
+
+from gpu_util import banner, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _msf():
+    import paper_2302_12199_amd as msf
+    return msf
+
+
+def _params(seed, scale=1.0):
+    from oracle import mlp_ref
+    p = mlp_ref.init_params(seed) * scale
+    rng = np.random.default_rng(seed + 100)
+    p += rng.normal(0, 0.05, p.shape)          # non-zero biases too
+    return p.astype(np.float32)
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+@pytest.mark.parametrize("B", [1, 37, 256, 1000])
+def test_forward_fp32_matches_reference(B):
+    from oracle import mlp_ref
+    banner(f"mlp forward fp32 B={B}")
+    msf = _msf()
+    rng = np.random.default_rng(B)
+    p = _params(1)
+    x = rng.normal(0, 1, (B, 16)).astype(np.float32)
+    z = msf.mlp_forward(_t(p), _t(x), bf16=False).cpu().numpy()
+    zr, _ = mlp_ref.forward(p.astype(np.float64), x.astype(np.float64))
+    np.testing.assert_allclose(z, zr, rtol=1e-4, atol=1e-4)
+
+
+def test_forward_bf16_matches_reference():
+    from oracle import mlp_ref
+    banner("mlp forward bf16")
+    msf = _msf()
+    rng = np.random.default_rng(5)
+    p = _params(2)
+    x = rng.normal(0, 1, (513, 16)).astype(np.float32)
+    z = msf.mlp_forward(_t(p), _t(x), bf16=True).cpu().numpy()
+    zr, _ = mlp_ref.forward(p.astype(np.float64), x.astype(np.float64), bf=True)
+    z32, _ = mlp_ref.forward(p.astype(np.float64), x.astype(np.float64), bf=False)
+    # rounding of hidden activations can flip one bf16 step where the FP32 and
+    # float64 sums straddle a rounding boundary: allow a few bf16 ulps
+    np.testing.assert_allclose(z, zr, rtol=2e-2, atol=2e-2)
+    # and the bf16 path really rounds: it differs from the fp32 network
+    assert np.abs(z - z32).max() > 1e-5
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_gradient_matches_reference(bf16):
+    from oracle import mlp_ref
+    banner(f"mlp grad bf16={bf16}")
+    msf = _msf()
+    rng = np.random.default_rng(11)
+    p = _params(3)
+    B = 700
+    x = rng.normal(0, 1, (B, 16)).astype(np.float32)
+    t = rng.normal(0, 1, B).astype(np.float32)
+    g, loss = msf.mlp_grad(_t(p), _t(x), _t(t), bf16=bf16)
+    g = g.cpu().numpy()
+    lr, gr = mlp_ref.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t, bf=bf16)
+    tol = 3e-2 if bf16 else 1e-4
+    assert abs(float(loss.item()) - lr) <= tol * max(1.0, abs(lr))
+    scale = np.abs(gr).max()
+    err = np.abs(g - gr).max()
+    assert err <= tol * scale, (err, scale)
+    # per-tensor relative agreement on the big blocks
+    for name, sl in (("W1", slice(0, 1024)), ("W2", slice(1088, 1088 + 4096))):
+        num = np.linalg.norm(g[sl] - gr[sl])
+        den = np.linalg.norm(gr[sl]) + 1e-12
+        assert num / den <= (5e-2 if bf16 else 1e-4), name
+
+
+def test_adam_step_matches_reference():
+    banner("mlp adam")
+    msf = _msf()
+    import torch
+    rng = np.random.default_rng(4)
+    P = msf.MLP_PARAMS
+    p = rng.normal(0, 1, P).astype(np.float32)
+    g = rng.normal(0, 1, P).astype(np.float32)
+    m = rng.normal(0, 0.1, P).astype(np.float32)
+    v = np.abs(rng.normal(0, 0.1, P)).astype(np.float32)
+    tp, tg, tm, tv = _t(p), _t(g), _t(m), _t(v)
+    msf.mlp_adam(tp, tg, tm, tv, step=3, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8)
+    torch.cuda.synchronize()
+    # the ABI takes FP32 hyper-parameters: use their FP32 values (1 - 0.999f
+    # differs from 0.001 by 1.3e-5 relative)
+    b1, b2, lr, eps = (float(np.float32(x)) for x in (0.9, 0.999, 1e-2, 1e-8))
+    g64 = g.astype(np.float64)
+    m2 = b1 * m.astype(np.float64) + (1 - b1) * g64
+    v2 = b2 * v.astype(np.float64) + (1 - b2) * g64 ** 2
+    p2 = p - lr * (m2 / (1 - b1**3)) / (np.sqrt(v2 / (1 - b2**3)) + eps)
+    np.testing.assert_allclose(tm.cpu().numpy(), m2, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(tv.cpu().numpy(), v2, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(tp.cpu().numpy(), p2, rtol=1e-5, atol=1e-5)
+
+
+def test_training_reduces_loss():
+    """A few hundred Adam steps on a smooth synthetic target cut the loss."""
+    from oracle import mlp_ref
+    banner("mlp training")
+    msf = _msf()
+    import torch
+    rng = np.random.default_rng(8)
+    B = 2048
+    x = rng.uniform(0, 1, (B, 16)).astype(np.float32)
+    x[:, 15] = 1.0
+    t = (np.sin(3 * x[:, 0]) + x[:, 1] * x[:, 2] - 0.5 * x[:, 3]).astype(np.float32)
+    p = _t(mlp_ref.init_params(0).astype(np.float32))
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    tx, tt = _t(x), _t(t)
+    first = None
+    for step in range(1, 401):
+        g, loss = msf.mlp_grad(p, tx, tt, bf16=True)
+        if first is None:
+            first = float(loss.item())
+        msf.mlp_adam(p, g, m, v, step, lr=3e-3)
+    _, loss = msf.mlp_grad(p, tx, tt, bf16=True)
+    last = float(loss.item())
+    assert last < 0.1 * first, (first, last)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_msf_parity_with_network_pivot(seed):
+    """Any pivot gives the same MSF: the network only changes the split."""
+    from oracle import mlp_ref
+    import graphgen
+    banner(f"msf filter pivot=mlp seed={seed}")
+    msf = _msf()
+    u, v, w = graphgen.gnm(1 << 14, 1 << 18, 1, 2**31 - 1, seed)
+    n = 1 << 14
+    p = _params(seed, scale=0.5)
+    p[-1] = 2.0 * (seed - 1.5)                  # push q away from 1/2 both ways
+    msf.load_pivot_model(msf.model_blob(p))
+    try:
+        assert msf.pivot_model_loaded()
+        tu, tv, tw = to_dev(u, v, w)
+        mask, total, st = msf.compute(tu, tv, tw, n, algo="filter", pivot="mlp",
+                                      min_split_edges=4096)
+    finally:
+        msf.clear_pivot_model()
+    import oracle
+    ref_mask, ref_total, _ = oracle.kruskal(u, v, w, n)
+    assert total == ref_total
+    assert np.array_equal(mask.cpu().numpy().astype(bool), ref_mask.astype(bool))
+    assert st["levels"] >= 1
+    # the pivot quantile used at the top split is the network's output on the
+    # features the sampler recorded
+    feats = np.array(st["top_features"], np.float64)[None, :]
+    z, _ = mlp_ref.forward(p.astype(np.float64), feats, bf=True)
+    q = mlp_ref.quantile(z)[0]
+    assert abs(st["splits"][0]["q"] - q) <= 2e-2 * max(q, 1 - q), (st["splits"][0]["q"], q)
+    assert abs(st["splits"][0]["q"] - 0.5) > 1e-3
+
+
+def test_network_pivot_without_model_falls_back_to_median():
+    import graphgen
+    banner("msf filter pivot=mlp no model")
+    msf = _msf()
+    msf.clear_pivot_model()
+    u, v, w = graphgen.gnm(4096, 1 << 16, 1, 2**31 - 1, 3)
+    tu, tv, tw = to_dev(u, v, w)
+    _, _, st = msf.compute(tu, tv, tw, 4096, algo="filter", pivot="mlp", min_split_edges=4096)
+    assert st["splits"][0]["q"] == pytest.approx(0.5)
+
+
+def test_model_blob_rejected_when_malformed():
+    msf = _msf()
+    p = np.zeros(msf.MLP_PARAMS, np.float32)
+    blob = bytearray(msf.model_blob(p))
+    blob[0] ^= 1
+    with pytest.raises(msf.MSFError):
+        msf.load_pivot_model(bytes(blob))
+    p[3] = np.nan
+    with pytest.raises(msf.MSFError):
+        msf.load_pivot_model(msf.model_blob(p))
+    with pytest.raises(msf.MSFError):
+        msf.load_pivot_model(b"\x00" * 10)
