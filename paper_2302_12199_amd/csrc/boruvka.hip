@@ -697,13 +697,6 @@ void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     const dim3 gr(nt), bl(kBlock);
-    if (!best_next) {   // relabel + compact only (Filter-Borůvka's heavy-edge filter)
-        if (in_mode == kOrig)
-            hipLaunchKernelGGL((k_compact<kOrig, false>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt);
-        else
-            hipLaunchKernelGGL((k_compact<kCompact, false>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt);
-        return;
-    }
     switch (in_mode) {
         case kOrig: hipLaunchKernelGGL((k_compact<kOrig, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;
         case kFull32: hipLaunchKernelGGL((k_compact<kFull32, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;

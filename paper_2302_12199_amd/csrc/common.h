@@ -35,7 +35,7 @@ struct Ctrl {
     uint64_t light;          // filter: edges with key <= pivot
     uint64_t pivot;          // filter: pivot key of the current split
     float q_used;            // filter: sample quantile used
-    uint32_t pad1;
+    int32_t giant;           // filter: representative of the largest sampled component (-1: none)
     uint32_t tail_rounds;    // rounds run by the single-workgroup tail
     uint32_t tail_edges;     // distinct vertex pairs handed to the tail
     uint32_t tail_live[24];  // per tail round: vertices with an incident edge

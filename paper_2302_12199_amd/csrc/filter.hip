@@ -227,10 +227,11 @@ __global__ __launch_bounds__(kBlock) void k_count_tiles(View g,
 
 // Exclusive scan of cnt[0, ntiles) in place by one workgroup of
 // kScanThreads threads, 8 consecutive entries per thread per sweep; the
-// total goes to ctrl->light.
+// total goes to *total.
 constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint64_t* __restrict__ cnt,
-                                                             uint32_t ntiles, Ctrl* ctrl) {
+                                                             uint32_t ntiles,
+                                                             uint64_t* __restrict__ total) {
     constexpr int kPer = 8;
     __shared__ uint64_t s_w[kScanThreads / kWave];
     __shared__ uint64_t s_carry;
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint64_t* __restric
         if (t == 0) s_carry += tot;
         __syncthreads();
     }
-    if (t == 0) ctrl->light = s_carry;
+    if (t == 0) *total = s_carry;
 }
 
 // Stable two-way split by key <= pivot: tile t writes its light edges from
@@ -338,6 +339,174 @@ __global__ __launch_bounds__(kBlock) void k_split(View g, int64_t n,
     }
 }
 
+// ------------------------------------------------------------------ filter
+
+// Largest component among kGiantSample evenly spaced vertices (P must be
+// fully compressed): ctrl->giant = its representative if it holds at least
+// 1/16 of the sample, else -1.  One workgroup.
+constexpr int kGiantSample = 1024;
+constexpr int kGiantThreads = 1024;
+__global__ __launch_bounds__(kGiantThreads) void k_giant_pick(const int32_t* __restrict__ P,
+                                                              int64_t n, Ctrl* ctrl) {
+    __shared__ int32_t s[kGiantSample];
+    __shared__ unsigned long long s_best;
+    if (threadIdx.x == 0) s_best = 0;
+    for (int i = threadIdx.x; i < kGiantSample; i += blockDim.x)
+        s[i] = P[((int64_t)(2 * i + 1) * n) / (2 * kGiantSample)];
+    __syncthreads();
+    for (int k = 2; k <= kGiantSample; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < kGiantSample; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const int32_t a = s[i], b = s[ixj];
+                    if ((a > b) == ((i & k) == 0)) { s[i] = b; s[ixj] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < kGiantSample; i += blockDim.x) {
+        if (i > 0 && s[i] == s[i - 1]) continue;
+        int lo = i, hi = kGiantSample;   // end of the run of s[i]
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s[mid] <= s[i]) lo = mid + 1;
+            else hi = mid;
+        }
+        atomicMax(&s_best, ((unsigned long long)(lo - i) << 32) | (uint32_t)s[i]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t len = (uint32_t)(s_best >> 32);
+        ctrl->giant = 16 * len >= (uint32_t)kGiantSample ? (int32_t)(uint32_t)s_best : -1;
+    }
+}
+
+// Bits 0, 1, 2, ... of x at bit positions 0, 2, 4, ... (32 -> 64 bits).
+__device__ __forceinline__ uint64_t spread_bits(uint64_t x) {
+    x &= 0xffffffffull;
+    x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+    x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+    x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+// 2-bit representative code of every vertex, 32 vertices per word:
+// bit 0 = P[x] is ctrl->giant, bit 1 = P[x] == x; 0 = look P[x] up.
+__global__ __launch_bounds__(kBlock) void k_rep_codes(const int32_t* __restrict__ P, int64_t n,
+                                                      const Ctrl* ctrl,
+                                                      uint64_t* __restrict__ codes) {
+    const int32_t gi = ctrl->giant;
+    const int64_t chunks = (n + 63) / 64;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    const int lane = threadIdx.x % kWave;
+    for (int64_t c = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; c < chunks;
+         c += waves) {
+        const int64_t x = c * 64 + lane;
+        const int32_t p = x < n ? P[x] : -1;
+        const uint64_t g = __ballot(gi >= 0 && p == gi);
+        const uint64_t self = __ballot(x < n && p == (int32_t)x);
+        if (lane < 2) {
+            const int sh = 32 * lane;
+            codes[2 * c + lane] = spread_bits(g >> sh) | (spread_bits(self >> sh) << 1);
+        }
+    }
+}
+
+// Representative of x from its code (one gather only for code 0).
+__device__ __forceinline__ int32_t rep_of(const uint64_t* __restrict__ codes,
+                                          const int32_t* __restrict__ P, int32_t gi, int32_t x) {
+    const uint32_t c = (uint32_t)(codes[(uint32_t)x >> 5] >> (2 * ((uint32_t)x & 31))) & 3u;
+    return (c & 1u) ? gi : (c ? x : P[x]);
+}
+
+// Filter, pass 1: keep flag of every heavy edge (flags, one bit per edge, word
+// i covering edges [64i, 64i + 64)) and the kept count of every 2048-edge tile.
+// An edge is dropped when both ends have the same representative; the 2-bit
+// codes resolve most ends (largest component, own representative) without
+// reading P.
+__global__ __launch_bounds__(kBlock) void k_filter_flags(View g, const int32_t* __restrict__ P,
+                                                         const uint64_t* __restrict__ codes,
+                                                         const Ctrl* ctrl,
+                                                         uint64_t* __restrict__ flags,
+                                                         uint64_t* __restrict__ cnt) {
+    constexpr int kIt = kRelabelItems;
+    __shared__ uint32_t s_wave[kBlock / kWave];
+    const uint32_t tile = blockIdx.x;
+    const int32_t gi = ctrl->giant;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t w0 = (int64_t)tile * (kBlock * kIt / kWave) + wave * kIt;  // first flag word
+    const int64_t m = g.len;
+    int32_t a[kIt], b[kIt];
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        const int64_t e = (w0 + k) * kWave + lane;
+        a[k] = b[k] = 0;
+        if (e < m) { a[k] = g.u[e]; b[k] = g.v[e]; }
+    }
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        const bool keep = a[k] != b[k] && rep_of(codes, P, gi, a[k]) != rep_of(codes, P, gi, b[k]);
+        const uint64_t mk = __ballot(keep);
+        if (lane == 0) flags[w0 + k] = mk;
+        c += __popcll(mk);
+    }
+    if (lane == 0) s_wave[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0;
+        for (int i = 0; i < kBlock / kWave; ++i) sum += s_wave[i];
+        cnt[tile] = sum;
+    }
+}
+
+// Filter, pass 2: the kept edges, relabelled (P[u], P[v]), in their order to
+// out[0, kept); tile t starts at off[t] (exclusive scan of the tile counts).
+__global__ __launch_bounds__(kBlock) void k_filter_scatter(View g, const int32_t* __restrict__ P,
+                                                           const uint64_t* __restrict__ codes,
+                                                           const Ctrl* ctrl,
+                                                           const uint64_t* __restrict__ flags,
+                                                           const uint64_t* __restrict__ tile_off,
+                                                           EdgeSoA out) {
+    constexpr int kIt = kRelabelItems;
+    __shared__ uint32_t s_wave[kBlock / kWave];
+    const uint32_t tile = blockIdx.x;
+    const int32_t gi = ctrl->giant;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t w0 = (int64_t)tile * (kBlock * kIt / kWave) + wave * kIt;
+    const int64_t words = (g.len + kWave - 1) / kWave;
+    uint64_t mk[kIt];
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        mk[k] = w0 + k < words ? flags[w0 + k] : 0;
+        c += __popcll(mk[k]);
+    }
+    if (lane == 0) s_wave[wave] = c;
+    __syncthreads();
+    uint32_t woff = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; ++i)
+        if (i < wave) woff += s_wave[i];
+    uint64_t off = tile_off[tile] + woff;
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        if ((mk[k] >> lane) & 1) {
+            const int64_t e = (w0 + k) * kWave + lane;
+            const uint64_t o = off + lanes_below(mk[k]);
+            out.u[o] = rep_of(codes, P, gi, g.u[e]);
+            out.v[o] = rep_of(codes, P, gi, g.v[e]);
+            out.w[o] = g.w[e];
+            out.id[o] = g.id[e];
+        }
+        off += __popcll(mk[k]);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline unsigned grid_cap(int64_t n, unsigned cap = 2048) {
@@ -371,7 +540,7 @@ void launch_split_count(int in_mode, const View& g, const uint64_t* pivot_dev, u
     else
         hipLaunchKernelGGL(k_count_tiles<kCompact>, dim3(grid), dim3(kBlock), 0, s, g, pivot_dev,
                            cnt, nt);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, cnt, nt, ctrl);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, cnt, nt, &ctrl->light);
 }
 
 void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_dev, EdgeSoA out,
@@ -384,6 +553,26 @@ void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_d
     else
         hipLaunchKernelGGL(k_split<kCompact>, dim3(nt), dim3(kBlock), 0, s, g, n, pivot_dev, out,
                            tile_off, ctrl);
+}
+
+void launch_rep_codes(const int32_t* P, int64_t n, uint64_t* codes, Ctrl* ctrl, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_giant_pick, dim3(1), dim3(kGiantThreads), 0, s, P, n, ctrl);
+    const int64_t chunks = (n + 63) / 64;
+    int64_t blocks = (chunks + kBlock / kWave - 1) / (kBlock / kWave);
+    blocks = blocks > 4096 ? 4096 : blocks;
+    hipLaunchKernelGGL(k_rep_codes, dim3((unsigned)blocks), dim3(kBlock), 0, s, P, n, ctrl, codes);
+}
+
+void launch_filter(const View& g, const int32_t* P, const uint64_t* codes, const Ctrl* ctrl,
+                   uint64_t* flags, uint64_t* cnt, EdgeSoA out, uint64_t* kept, hipStream_t s) {
+    if (g.len <= 0) return;
+    const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
+    hipLaunchKernelGGL(k_filter_flags, dim3(nt), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
+                       cnt);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, cnt, nt, kept);
+    hipLaunchKernelGGL(k_filter_scatter, dim3(nt), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
+                       cnt, out);
 }
 
 // ------------------------------------------------------------------ driver
@@ -425,6 +614,8 @@ struct Ctx {
     int64_t min_split;
     int sparse_deg;
     float q_net;   // quantile the network chose at the top split (0 = not yet)
+    uint64_t* codes;   // 2-bit representative codes of the vertices
+    uint64_t* flags;   // keep flags of the heavy edges being filtered
 };
 
 View view_of(const EdgeSoA& e, int64_t len) {
@@ -517,31 +708,40 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
     H.u += nl_al; H.v += nl_al; H.w += nl_al; H.id += nl_al;
     if ((st = rec_filter(C, kCompact, view_of(R, nl), tgt, depth + 1))) return st;
 
-    // Filter: drop heavy edges inside a light component, compacting the rest
-    // leftwards to [0, kept) of the same buffer (a stable lookback compaction
-    // never writes past what it has read).
+    // Filter: drop heavy edges inside a light component; the rest, relabelled
+    // and in order, go to [0, kept) of the other buffer, which holds nothing
+    // live below this graph's length (this graph itself is no longer needed).
     if ((st = compress_p(C))) return st;
-    const int64_t nth = (nh + kRelabelTile - 1) / kRelabelTile;
-    launch_scan_prep(C.B.status, nth, C.B.ctrl, 0, C.s);
-    HIP_TRY(hipMemsetAsync(&C.B.ctrl->m_next, 0, sizeof(uint64_t), C.s));
+    h = prof_begin(K_PMAINT, C.s);
+    launch_rep_codes(C.P, C.n, C.codes, C.B.ctrl, C.s);
+    prof_end(h, C.s, 4.0 * C.n + C.n / 4.0);
+    const int o = 1 - tgt;
     h = prof_begin(K_FILTER, C.s);
-    launch_compact(kCompact, view_of(H, nh), C.P, R, nullptr, C.B.status, C.B.ctrl, C.s);
-    prof_end(h, C.s, 24.0 * nh);
+    launch_filter(view_of(H, nh), C.P, C.codes, C.B.ctrl, C.flags, C.B.status, C.buf[o],
+                  &C.B.ctrl->m_next, C.s);
+    prof_end(h, C.s, 8.0 * nh);
     HIP_TRY(hipGetLastError());
     if ((st = read_ctrl(C.B.ctrl, hc, C.s))) return st;
     const int64_t kept = (int64_t)hc->m_next;
-    prof_add(K_FILTER, 16.0 * kept);
+    prof_add(K_FILTER, 24.0 * kept);
     C.st->filtered_in += (uint64_t)nh;
     C.st->filtered_out += (uint64_t)kept;
     if (split < MSF_MAX_TRACE) C.st->split_kept[split] = (uint64_t)kept;
-    return rec_filter(C, kCompact, view_of(R, kept), tgt, depth + 1);
+    return rec_filter(C, kCompact, view_of(C.buf[o], kept), o, depth + 1);
 }
 
 }  // namespace
 
+size_t codes_bytes(int64_t n) { return align_up(((size_t)((n > 0 ? n : 1) + 63) / 64) * 16); }
+size_t flags_bytes(int64_t m) {
+    return align_up(((size_t)((m > 0 ? m : 1) + kRelabelTile - 1) / kRelabelTile) *
+                    (kRelabelTile / 64) * 8);
+}
+
 size_t filter_bytes(int64_t m, int64_t n, const msf_options& opt) {
     (void)opt;
-    return engine_bytes(m, n) + align_up((size_t)(n > 0 ? n : 1) * 4) + 2 * buffer_bytes(m);
+    return engine_bytes(m, n) + align_up((size_t)(n > 0 ? n : 1) * 4) + 2 * buffer_bytes(m) +
+           codes_bytes(n) + flags_bytes(m);
 }
 
 int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,
@@ -553,6 +753,10 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
     off += align_up((size_t)(n > 0 ? n : 1) * 4);
     C.buf[0] = carve_buffer(ws + off, m);
     C.buf[1] = carve_buffer(ws + off + buffer_bytes(m), m);
+    off += 2 * buffer_bytes(m);
+    C.codes = (uint64_t*)(ws + off);
+    off += codes_bytes(n);
+    C.flags = (uint64_t*)(ws + off);
     C.n = n;
     C.mask = mask;
     C.s = s;
