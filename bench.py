@@ -153,6 +153,7 @@ def main():
     ap.add_argument("--algo", default="boruvka", choices=["boruvka", "filter"])
     ap.add_argument("--pivot", default="median")
     ap.add_argument("--quantile", type=float, default=0.5)
+    ap.add_argument("--model", default=None, help="pivot network file (--pivot mlp)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 27,
                     help="edges given to the timed CPU oracle (0 = skip)")
     ap.add_argument("--graphs", type=int, default=10000, help="batch workload: graphs")
@@ -196,6 +197,9 @@ def main():
     dev = torch.device("cuda:0")
     tu, tv, tw = (torch.from_numpy(x.view(np.int32)).to(dev) for x in (u, v, w))
     opts = dict(algo=args.algo, pivot=args.pivot, quantile=args.quantile)
+    if args.algo == "filter" and args.pivot == "mlp":
+        msf.load_pivot_model(args.model)        # default: the shipped network
+        log(f"pivot network loaded from {args.model or msf.DEFAULT_MODEL}")
     ws = torch.empty(msf.workspace_bytes(m, n, **opts), dtype=torch.uint8, device=dev)
     mask = torch.empty(m, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
@@ -218,6 +222,24 @@ def main():
     prof = msf.profile_read()
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step total={total}")
+
+    pivot_cmp = None
+    if args.algo == "filter" and args.pivot == "mlp":
+        # the same graph with the sampled-median pivot, for comparison
+        mopts = dict(opts, pivot="median")
+        for _ in range(args.warmup):
+            msf.compute(tu, tv, tw, n, workspace=ws, mask_out=mask, **mopts)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            _, mtotal, _ = msf.compute(tu, tv, tw, n, workspace=ws, mask_out=mask, **mopts)
+        torch.cuda.synchronize()
+        med_ms = (time.perf_counter() - t2) * 1000.0 / args.steps
+        if mtotal != total:
+            raise RuntimeError("median-pivot run gave a different total")
+        pivot_cmp = {"median_ms_per_step": round(med_ms, 4), "network_q": stats["pivot_q_used"],
+                     "speedup_vs_median": round(med_ms / ms_per_step, 4)}
+        log(f"median pivot: {med_ms:.3f} ms/step; network q={stats['pivot_q_used']:.4f}")
 
     dom = max(prof, key=lambda k: prof[k]["ms"]) if prof else None
     roofline = None
@@ -247,7 +269,7 @@ def main():
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": args.workload, "n": int(n), "m": int(m), "algo": args.algo,
                    "pivot": args.pivot if args.algo == "filter" else None},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "pivot_vs_median": pivot_cmp,
         "detail": {"rounds": stats["rounds"], "round_live": stats["round_live"],
                    "round_edges": stats["round_edges"], "msf_edges": stats["msf_edges"],
                    "total_weight": stats["total_weight"], "kernels": kernels},

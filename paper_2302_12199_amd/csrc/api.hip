@@ -28,7 +28,8 @@ const char* last_err() { return g_err; }
 namespace {
 const char* const kKernelNames[K_COUNT] = {
     "minedge_r0", "hook", "jump", "scan_roots", "label", "pass", "compact", "compose",
-    "fill", "scan_prep", "sample", "partition", "filter", "rep_maint", "mlp", "batch", "tail"};
+    "fill", "scan_prep", "sample", "partition", "filter", "rep_maint", "mlp", "batch", "tail",
+    "pass_r0"};
 
 struct Profiler {
     std::mutex mu;

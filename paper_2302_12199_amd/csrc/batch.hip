@@ -16,6 +16,7 @@
 namespace msf {
 
 constexpr int kBatchMaxRounds = 64;
+constexpr int kEdgeIlp = 4;
 
 // Exclusive rank of `flag` among the workgroup's threads; *total gets the count.
 template <int BS>
@@ -58,19 +59,44 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int32_t* lab, uint64_
             for (int64_t x = tid; x < ncur; x += BS) best[x] = kKeyMax;
             __syncthreads();
             int any = 0;
-            for (int64_t e = tid; e < m; e += BS) {                   // lightest edges
-                const int32_t a = U[e], b = V[e];
-                if (round == 0 && ((uint32_t)a >= (uint64_t)n || (uint32_t)b >= (uint64_t)n)) {
-                    bad = true;
-                    continue;
+            // lightest edges, kEdgeIlp independent edges per thread: all loads
+            // and label gathers of a step are issued before any is used
+            for (int64_t base = 0; base < m; base += (int64_t)BS * kEdgeIlp) {
+                int32_t a[kEdgeIlp], b[kEdgeIlp], la[kEdgeIlp], lb[kEdgeIlp];
+                uint32_t wt[kEdgeIlp];
+#pragma unroll
+                for (int k = 0; k < kEdgeIlp; ++k) {
+                    const int64_t e = base + k * BS + tid;
+                    a[k] = b[k] = 0;
+                    wt[k] = 0;
+                    if (e < m) { a[k] = U[e]; b[k] = V[e]; wt[k] = W[e]; }
                 }
-                if (round == 0 && a == b) continue;
-                const int32_t la = lab[a], lb = lab[b];
-                if (la == lb) continue;
-                any = 1;
-                const uint64_t key = ((uint64_t)W[e] << 32) | (uint64_t)e;
-                atomic_min_key(&best[la], key);
-                atomic_min_key(&best[lb], key);
+#pragma unroll
+                for (int k = 0; k < kEdgeIlp; ++k) {
+                    const int64_t e = base + k * BS + tid;
+                    la[k] = lb[k] = -1;                       // dead unless set below
+                    if (e >= m || a[k] == b[k]) continue;
+                    if (round == 0) {                         // labels are the ids
+                        if ((uint32_t)a[k] >= (uint64_t)n || (uint32_t)b[k] >= (uint64_t)n) {
+                            bad = true;
+                            continue;
+                        }
+                        la[k] = a[k];
+                        lb[k] = b[k];
+                    } else {
+                        la[k] = lab[a[k]];
+                        lb[k] = lab[b[k]];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kEdgeIlp; ++k) {
+                    if (la[k] == lb[k]) continue;
+                    const int64_t e = base + k * BS + tid;
+                    any = 1;
+                    const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)e;
+                    atomic_min_key(&best[la[k]], key);
+                    atomic_min_key(&best[lb[k]], key);
+                }
             }
             if (!__syncthreads_or(any) || __syncthreads_or(bad)) break;
             for (int64_t x = tid; x < ncur; x += BS) {                // hook + mark

@@ -255,7 +255,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             int out = kOutNone;
             if (mode == kOrig) out = nn <= kMax16 ? kOut16 : kOut32;
             else if (mode == kFull32 && nn <= kMax16) out = kOut16;
-            h = prof_begin(K_PASS, s);
+            h = prof_begin(mode == kOrig ? K_PASS_R0 : K_PASS, s);
             if (!launch_pass(mode, out, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1], nn,
                              nullptr, dc, s)) {
                 set_err_text("unsupported pass layout");

@@ -188,3 +188,33 @@ def test_model_blob_rejected_when_malformed():
         msf.load_pivot_model(msf.model_blob(p))
     with pytest.raises(msf.MSFError):
         msf.load_pivot_model(b"\x00" * 10)
+
+
+def test_shipped_model_parity_and_its_quantile():
+    """The shipped network drives the pivot; the MSF stays exact and the
+    quantile used is the CPU reference network's output on the recorded
+    features."""
+    from oracle import mlp_ref
+    import graphgen
+    import oracle
+    banner("msf filter shipped model rmat")
+    msf = _msf()
+    u, v, w = graphgen.rmat(17, 1 << 21, wlo=1, whi=2**31 - 1, seed=9)
+    n = 1 << 17
+    msf.load_pivot_model()
+    try:
+        tu, tv, tw = to_dev(u, v, w)
+        mask, total, st = msf.compute(tu, tv, tw, n, algo="filter", pivot="mlp",
+                                      min_split_edges=1 << 16)
+    finally:
+        msf.clear_pivot_model()
+    ref_mask, ref_total, _ = oracle.kruskal(u, v, w, n)
+    assert total == ref_total
+    assert np.array_equal(mask.cpu().numpy().astype(bool), ref_mask.astype(bool))
+    blob = open(msf.DEFAULT_MODEL, "rb").read()
+    p = np.frombuffer(blob[16:], np.float32).astype(np.float64)
+    z, _ = mlp_ref.forward(p, np.array(st["top_features"], np.float64)[None, :], bf=True)
+    q = mlp_ref.quantile(z)[0]
+    assert abs(st["pivot_q_used"] - q) <= 2e-2 * max(q, 1 - q)
+    # every split of the call uses the top split's quantile
+    assert all(abs(s["q"] - st["pivot_q_used"]) < 1e-7 for s in st["splits"])
