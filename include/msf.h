@@ -120,10 +120,14 @@ int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m
 
 /*
  * Batched MSF: G independent graphs solved by one persistent kernel (graph g
- * is a whole problem in the sense of msf_compute; paper Sec. II-C rounds are
- * run by one workgroup per graph).  Stream-ordered and asynchronous: nothing
- * is synchronised and nothing is allocated, so the call can be captured in a
- * hipGraph (see msf_batched_graph_create).
+ * is a whole problem in the sense of msf_compute; all paper Sec. II-C rounds
+ * run inside the kernel).  A graph with at least coop_edges edges is solved
+ * by all workgroups running on one XCD together (one such graph per XCD at a
+ * time); any other graph by one workgroup, with its state in LDS when it has
+ * at most lds_vertices vertices.  Stream-ordered and asynchronous: nothing is
+ * synchronised and nothing is allocated, so the call can be captured in a
+ * hipGraph (see msf_batched_graph_create).  Calls sharing a workspace must
+ * not overlap.
  *   u, v, w        device arrays of all graphs' edges, concatenated
  *   edge_off       device int64[G + 1]: graph g owns edges [edge_off[g], edge_off[g+1])
  *   vert_off       device int64[G + 1]: graph g has vert_off[g+1] - vert_off[g]
@@ -143,8 +147,10 @@ typedef struct msf_batch_options {
     int32_t block;           /* threads per workgroup: 256, 512 or 1024; 0 = 1024 */
     int32_t lds_vertices;    /* graphs with at most this many vertices keep their
                                 state in LDS (20 B per vertex); 0 = 2048, -1 = never */
-    int32_t workgroups;      /* persistent workgroups; 0 = 2 per compute unit */
-    int32_t reserved[5];     /* must be zero */
+    int32_t workgroups;      /* persistent workgroups; 0 = as many as can be resident */
+    int32_t coop_edges;      /* graphs with at least this many edges are solved
+                                cooperatively per XCD; 0 = 2^20, -1 = never */
+    int32_t reserved[4];     /* must be zero */
 } msf_batch_options;
 
 size_t msf_batched_workspace_bytes(int64_t G, int64_t max_n, const msf_batch_options* opt);
@@ -168,7 +174,8 @@ int msf_batched_graph_destroy(msf_batch_graph* graph);
 
 /*
  * Autotuner for the batched solver: runs the batch once per candidate
- * (block in {256, 512, 1024} x lds_vertices in {-1, 1024, 2048, 4096}) on
+ * (block in {512, 1024} x lds_vertices in {1024, 2048, 4096} x coop_edges in
+ * {2^18, 2^20, never}) on
  * `stream`, times each with HIP events and writes the fastest to *best_out
  * (HOST); *best_ms_out (HOST, nullable) gets its time.  Blocking.  Same array
  * arguments as msf_compute_batched; the workspace must fit every candidate

@@ -83,7 +83,8 @@ SYMBOLS = ("msf_workspace_bytes", "msf_compute", "msf_status_string", "msf_last_
 
 class BatchOptions(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("lds_vertices", ctypes.c_int32),
-                ("workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("workgroups", ctypes.c_int32), ("coop_edges", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -211,9 +212,10 @@ def profile_read():
                                    "bytes": float(buf[i].bytes)} for i in range(k)}
 
 
-def make_batch_options(block=0, lds_vertices=0, workgroups=0):
+def make_batch_options(block=0, lds_vertices=0, workgroups=0, coop_edges=0):
     o = BatchOptions()
     o.block, o.lds_vertices, o.workgroups = int(block), int(lds_vertices), int(workgroups)
+    o.coop_edges = int(coop_edges)
     return o
 
 
@@ -304,7 +306,8 @@ class Batch:
         self.options = best
         if self._graph is not None:
             self.close()
-        return {"block": best.block, "lds_vertices": best.lds_vertices, "ms": ms.value}
+        return {"block": best.block, "lds_vertices": best.lds_vertices,
+                "coop_edges": best.coop_edges, "ms": ms.value}
 
     def close(self):
         if self._graph is not None:

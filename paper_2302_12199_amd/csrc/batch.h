@@ -5,6 +5,39 @@
 
 namespace msf {
 
+constexpr int kMaxXcd = 16;          // XCC_ID is a 4-bit field
+constexpr int kCoopVertsPerThread = 8;
+constexpr int kCoopEdgesPerThread = 16;
+constexpr int kMinBatchBlock = 256;
+
+// Per-launch counters at the start of the workspace (zeroed by k_batch_prep).
+struct BatchQueue {
+    uint32_t big_next;              // next index into the cooperative list
+    uint32_t small_next;            // next index into the other list
+    uint32_t nbig;                  // graphs solved cooperatively
+    uint32_t err;                   // a bounded wait ran out (results invalid)
+};
+
+// Cooperative solve of one graph at a time by every workgroup of one XCD.
+// Work is cut into phases of chunks; a workgroup takes a chunk with one
+// atomic on `ticket` (phase << 32 | chunk), and the one that completes the
+// last chunk of a phase sets up the next.  A workgroup waits only for chunks
+// that running workgroups have taken, so no co-residency is assumed.
+struct alignas(256) XcdWork {
+    uint64_t ticket;                // phase << 32 | next chunk
+    uint32_t done[2];               // completed chunks, by phase parity
+    uint32_t kind[2];               // phase kind, by parity
+    uint32_t nchunks[2];            // chunks of the phase, by parity
+    uint32_t state;                 // 0 idle, 1 claimed by a workgroup
+    uint32_t round;                 // Borůvka round of the current graph
+    uint32_t jit;                   // pointer-jumping step
+    uint32_t f_any, f_bad, f_changed;
+    uint32_t pad;
+    int64_t graph, n, m;            // current graph
+    int64_t ncur, nnext;            // live vertices this round / next round
+    uint64_t total;                 // MSF weight so far
+};
+
 struct BatchArgs {
     const int32_t* u;
     const int32_t* v;
@@ -16,15 +49,26 @@ struct BatchArgs {
     uint8_t* mask;           // [eoff[G]]
     uint64_t* totals;        // [G]; ~0 for a graph with invalid input
     uint64_t* ticks;         // [G + 1] completion clock per graph, [G] = batch start; or null
-    char* scratch;           // one slot per workgroup
+    BatchQueue* q;
+    XcdWork* xw;             // [kMaxXcd]
+    int32_t* big;            // [G] cooperative graphs in processing order (first q->nbig)
+    int32_t* small;          // [G] the others in processing order
+    char* xslots;            // kMaxXcd state slots (cooperative solves)
+    char* wslots;            // one state slot per workgroup (graphs above lds_n)
     size_t slot_bytes;
     int64_t nmax;            // vertices per graph the slots are sized for
-    uint32_t* queue;         // work counter, zeroed by the launch
+    int64_t coop_edges;      // graphs with at least this many edges are cooperative (< 0: none)
     int lds_n;               // graphs with n <= lds_n keep their state in LDS
 };
+
+struct BatchLayout {
+    size_t xw_off, lists_off, xslots_off, wslots_off, total;
+};
+BatchLayout batch_layout(int64_t G, int64_t nmax, int workgroups);
 
 int launch_batch(const BatchArgs& A, int block, int workgroups, hipStream_t s);
 size_t batch_slot_bytes(int64_t nmax);
 bool batch_allow_lds(int block, size_t bytes);
+int batch_resident_workgroups(int block, size_t lds_bytes);
 
 }  // namespace msf

@@ -1,22 +1,44 @@
 // Batched MSF: thousands of independent graphs in one persistent launch.
 //
-// Each workgroup repeatedly takes the next graph from an atomic work queue
-// (the caller may pass an order, e.g. largest first) and runs every Borůvka
-// round of that graph itself (paper Sec. II-C): lightest incident edge per
-// vertex with packed (w << 32 | local edge index) keys, hook with the 2-cycle
-// tie break and MSF marking, pointer jumping, dense relabelling of the roots,
-// composition of the labels of the graph's vertices.  Phases are separated by
-// workgroup barriers only, so the whole batch needs no host round trip and the
-// launch can be captured in a hipGraph.  A graph's per-vertex state (label,
-// best key, parent, new id: 20 B per vertex) lives in LDS when the graph is
-// small enough, else in a global scratch slot owned by the workgroup.
+// Every graph runs all Borůvka rounds of the paper's Sec. II-C inside the
+// kernel: lightest incident edge per vertex with packed (w << 32 | local edge
+// index) keys, hook with the 2-cycle tie break and MSF marking, pointer
+// jumping, dense relabelling of the roots, composition of the labels of the
+// graph's vertices.  No host round trip is needed, so the launch can be
+// captured in a hipGraph.
+//
+// Two lists, built by k_batch_prep in the caller's order (largest first by
+// default):
+//  * cooperative graphs (m >= coop_edges) are solved one at a time per XCD by
+//    every workgroup running on that XCD, so the graph's per-vertex state
+//    (20 B per vertex, in a global slot) stays in that XCD's L2.  The rounds
+//    are cut into phases of chunks taken from an atomic ticket; the
+//    workgroup that completes a phase's last chunk sets up the next phase.
+//    A workgroup only ever waits for chunks that running workgroups took, so
+//    nothing assumes the whole grid is resident;
+//  * the other graphs are solved by one workgroup each, the state in LDS when
+//    n <= lds_n, else in the workgroup's own global slot.
+// Every wait is bounded by wall-clock time.
 #include "batch.h"
 #include "prim.h"
 
 namespace msf {
 
 constexpr int kBatchMaxRounds = 64;
+constexpr int kMaxJumps = 64;
 constexpr int kEdgeIlp = 4;
+constexpr uint32_t kNotReady = 0xffffffffu;       // phase id before the first set-up
+constexpr uint64_t kWaitTicks = 200000000ull;     // 2 s of the 100 MHz wall clock
+
+enum CoopKind : uint32_t {
+    C_NONE = 0, C_INIT, C_FILL, C_MINEDGE, C_HOOK, C_JUMP, C_COUNT, C_IDS, C_COMPOSE, C_DONE
+};
+
+__device__ __forceinline__ uint32_t xcc_id() {
+    uint32_t x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(x));
+    return x & (kMaxXcd - 1);
+}
 
 // Exclusive rank of `flag` among the workgroup's threads; *total gets the count.
 template <int BS>
@@ -37,8 +59,98 @@ __device__ __forceinline__ uint32_t block_rank(bool flag, uint32_t* s_wave, uint
 }
 
 template <int BS>
-__device__ void solve_graph(const BatchArgs& A, int64_t g, int32_t* lab, uint64_t* best,
-                            int32_t* par, int32_t* nid, uint32_t* s_wave) {
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t x, uint64_t* s_red) {
+    x = wave_sum_u64(x);
+    if (threadIdx.x % kWave == 0) s_red[threadIdx.x / kWave] = x;
+    __syncthreads();
+    uint64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < BS / kWave; ++i) t += s_red[i];
+    __syncthreads();
+    return t;
+}
+
+// Lightest edge of every endpoint label over edges [lo, hi) of one graph,
+// kEdgeIlp independent edges per thread (all loads and label gathers of a
+// step issued before any is used).  Round 0 reads the ids directly (labels
+// are the ids) and validates them.
+template <int BS>
+__device__ __forceinline__ void min_edges(const int32_t* __restrict__ U,
+                                          const int32_t* __restrict__ V,
+                                          const uint32_t* __restrict__ W, int64_t lo, int64_t hi,
+                                          int64_t n, int round, const int32_t* lab,
+                                          uint64_t* best, int& any, bool& bad) {
+    const int tid = threadIdx.x;
+    for (int64_t base = lo; base < hi; base += (int64_t)BS * kEdgeIlp) {
+        int32_t a[kEdgeIlp], b[kEdgeIlp], la[kEdgeIlp], lb[kEdgeIlp];
+        uint32_t wt[kEdgeIlp];
+#pragma unroll
+        for (int k = 0; k < kEdgeIlp; ++k) {
+            const int64_t e = base + k * BS + tid;
+            a[k] = b[k] = 0;
+            wt[k] = 0;
+            if (e < hi) { a[k] = U[e]; b[k] = V[e]; wt[k] = W[e]; }
+        }
+#pragma unroll
+        for (int k = 0; k < kEdgeIlp; ++k) {
+            const int64_t e = base + k * BS + tid;
+            la[k] = lb[k] = -1;                       // dead unless set below
+            if (e >= hi || a[k] == b[k]) continue;
+            if (round == 0) {
+                if ((uint32_t)a[k] >= (uint64_t)n || (uint32_t)b[k] >= (uint64_t)n) {
+                    bad = true;
+                    continue;
+                }
+                la[k] = a[k];
+                lb[k] = b[k];
+            } else {
+                la[k] = lab[a[k]];
+                lb[k] = lab[b[k]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kEdgeIlp; ++k) {
+            if (la[k] == lb[k]) continue;
+            const int64_t e = base + k * BS + tid;
+            any = 1;
+            const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)e;
+            atomic_min_key(&best[la[k]], key);
+            atomic_min_key(&best[lb[k]], key);
+        }
+    }
+}
+
+// Hook + MSF mark over labels [lo, hi): parent = other end of the lightest
+// edge; of a 2-cycle (same edge chosen by both) the smaller label is the root.
+__device__ __forceinline__ uint64_t hook_range(const int32_t* __restrict__ U,
+                                               const int32_t* __restrict__ V, int64_t lo,
+                                               int64_t hi, int stride, const int32_t* lab,
+                                               const uint64_t* best, int32_t* par,
+                                               uint8_t* mask) {
+    uint64_t wsum = 0;
+    for (int64_t x = lo + threadIdx.x; x < hi; x += stride) {
+        const uint64_t b = best[x];
+        if (b == kKeyMax) { par[x] = (int32_t)x; continue; }
+        const uint32_t pos = (uint32_t)b;
+        const int32_t la = lab[U[pos]], lb = lab[V[pos]];
+        const int32_t other = la == (int32_t)x ? lb : la;
+        if (best[other] == b && (int32_t)x < other) {
+            par[x] = (int32_t)x;
+        } else {
+            par[x] = other;
+            mask[pos] = 1;
+            wsum += b >> 32;
+        }
+    }
+    return wsum;
+}
+
+// --------------------------------------------------- one workgroup per graph
+
+// State arrays of `cap` vertices (LDS or a global slot).
+template <int BS>
+__device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t* lab,
+                            uint64_t* best, int32_t* par, int32_t* nid, uint32_t* s_wave) {
     const int tid = threadIdx.x;
     const int64_t e0 = A.eoff[g];
     const int64_t m = A.eoff[g + 1] - e0;
@@ -47,7 +159,7 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int32_t* lab, uint64_
     const int32_t* V = A.v + e0;
     const uint32_t* W = A.w + e0;
     uint8_t* mask = A.mask + e0;
-    const bool bad_shape = n < 0 || n > A.nmax || m < 0 || m > 0xffffffffLL;
+    const bool bad_shape = n < 0 || n > cap || m < 0 || m > 0xffffffffLL;
     bool bad = bad_shape;
     uint64_t wsum = 0;
     if (!bad_shape) {
@@ -59,62 +171,11 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int32_t* lab, uint64_
             for (int64_t x = tid; x < ncur; x += BS) best[x] = kKeyMax;
             __syncthreads();
             int any = 0;
-            // lightest edges, kEdgeIlp independent edges per thread: all loads
-            // and label gathers of a step are issued before any is used
-            for (int64_t base = 0; base < m; base += (int64_t)BS * kEdgeIlp) {
-                int32_t a[kEdgeIlp], b[kEdgeIlp], la[kEdgeIlp], lb[kEdgeIlp];
-                uint32_t wt[kEdgeIlp];
-#pragma unroll
-                for (int k = 0; k < kEdgeIlp; ++k) {
-                    const int64_t e = base + k * BS + tid;
-                    a[k] = b[k] = 0;
-                    wt[k] = 0;
-                    if (e < m) { a[k] = U[e]; b[k] = V[e]; wt[k] = W[e]; }
-                }
-#pragma unroll
-                for (int k = 0; k < kEdgeIlp; ++k) {
-                    const int64_t e = base + k * BS + tid;
-                    la[k] = lb[k] = -1;                       // dead unless set below
-                    if (e >= m || a[k] == b[k]) continue;
-                    if (round == 0) {                         // labels are the ids
-                        if ((uint32_t)a[k] >= (uint64_t)n || (uint32_t)b[k] >= (uint64_t)n) {
-                            bad = true;
-                            continue;
-                        }
-                        la[k] = a[k];
-                        lb[k] = b[k];
-                    } else {
-                        la[k] = lab[a[k]];
-                        lb[k] = lab[b[k]];
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < kEdgeIlp; ++k) {
-                    if (la[k] == lb[k]) continue;
-                    const int64_t e = base + k * BS + tid;
-                    any = 1;
-                    const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)e;
-                    atomic_min_key(&best[la[k]], key);
-                    atomic_min_key(&best[lb[k]], key);
-                }
-            }
+            min_edges<BS>(U, V, W, 0, m, n, round, lab, best, any, bad);
             if (!__syncthreads_or(any) || __syncthreads_or(bad)) break;
-            for (int64_t x = tid; x < ncur; x += BS) {                // hook + mark
-                const uint64_t b = best[x];
-                if (b == kKeyMax) { par[x] = (int32_t)x; continue; }
-                const uint32_t pos = (uint32_t)b;
-                const int32_t la = lab[U[pos]], lb = lab[V[pos]];
-                const int32_t other = la == (int32_t)x ? lb : la;
-                if (best[other] == b && (int32_t)x < other) {
-                    par[x] = (int32_t)x;
-                } else {
-                    par[x] = other;
-                    mask[pos] = 1;
-                    wsum += b >> 32;
-                }
-            }
+            wsum += hook_range(U, V, 0, ncur, BS, lab, best, par, mask);
             __syncthreads();
-            for (int it = 0; it < 64; ++it) {                          // pointer jumping
+            for (int it = 0; it < kMaxJumps; ++it) {                   // pointer jumping
                 int changed = 0;
                 for (int64_t x = tid; x < ncur; x += BS) {
                     const int32_t p = par[x], pp = par[p];
@@ -153,57 +214,406 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int32_t* lab, uint64_
     __syncthreads();
 }
 
+// ------------------------------------------------- cooperative (one per XCD)
+
+struct SlotView {
+    uint64_t* best;
+    int32_t* lab;
+    int32_t* par;
+    int32_t* nid;
+    uint32_t* cnt;   // roots per vertex chunk, then their exclusive prefix
+};
+
+__device__ __forceinline__ SlotView slot_view(char* slot, int64_t nmax) {
+    SlotView s;
+    const size_t cap = (size_t)nmax;
+    s.best = reinterpret_cast<uint64_t*>(slot);
+    s.lab = reinterpret_cast<int32_t*>(slot + cap * 8);
+    s.par = s.lab + cap;
+    s.nid = s.par + cap;
+    s.cnt = reinterpret_cast<uint32_t*>(s.nid + cap);
+    return s;
+}
+
+__device__ __forceinline__ uint32_t chunks_of(int64_t len, int64_t per) {
+    return (uint32_t)((len + per - 1) / per);
+}
+
+// Publishes phase p (thread 0 of the workgroup that completed phase p - 1).
+__device__ void coop_setup(XcdWork* X, uint32_t p, uint32_t kind, uint32_t nchunks) {
+    X->kind[p & 1] = kind;
+    X->nchunks[p & 1] = nchunks;
+    X->done[p & 1] = 0;
+    __threadfence();
+    atomicExch((unsigned long long*)&X->ticket, (unsigned long long)((uint64_t)p << 32));
+}
+
+// Takes the next cooperative graph (or finishes) and publishes phase p.
+template <int BS>
+__device__ void coop_next_graph(const BatchArgs& A, XcdWork* X, uint32_t p) {
+    constexpr int64_t CV = (int64_t)BS * kCoopVertsPerThread;
+    constexpr int64_t CE = (int64_t)BS * kCoopEdgesPerThread;
+    while (true) {
+        const uint32_t gi = atomicAdd(&A.q->big_next, 1u);
+        if (gi >= A.q->nbig) {
+            coop_setup(X, p, C_DONE, 0);
+            return;
+        }
+        const int64_t g = A.big[gi];
+        const int64_t m = A.eoff[g + 1] - A.eoff[g];
+        const int64_t n = A.voff[g + 1] - A.voff[g];
+        if (n < 0 || n > A.nmax || m < 0 || m > 0xffffffffLL) {
+            A.totals[g] = kKeyMax;
+            if (A.ticks) A.ticks[g] = wall_clock64();
+            continue;
+        }
+        X->graph = g;
+        X->n = n;
+        X->m = m;
+        X->ncur = n;
+        X->round = 0;
+        X->total = 0;
+        X->f_any = X->f_bad = X->f_changed = 0;
+        const uint32_t ce = chunks_of(m, CE), cv = chunks_of(n, CV);
+        coop_setup(X, p, C_INIT, ce > cv ? ce : cv);
+        return;
+    }
+}
+
+template <int BS>
+__device__ void coop_finish(const BatchArgs& A, XcdWork* X, uint32_t p, bool bad) {
+    const int64_t g = X->graph;
+    A.totals[g] = (bad || A.q->err) ? kKeyMax : X->total;
+    if (A.ticks) A.ticks[g] = wall_clock64();
+    coop_next_graph<BS>(A, X, p);
+}
+
+// Sets up phase p + 1 after phase p (of kind `kind`) completed.
+template <int BS>
+__device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& S, uint32_t p,
+                                uint32_t kind) {
+    constexpr int64_t CV = (int64_t)BS * kCoopVertsPerThread;
+    constexpr int64_t CE = (int64_t)BS * kCoopEdgesPerThread;
+    const uint32_t q = p + 1;
+    switch (kind) {
+        case C_INIT:
+            if (X->ncur <= 1 || X->m == 0) coop_finish<BS>(A, X, q, false);
+            else coop_setup(X, q, C_FILL, chunks_of(X->ncur, CV));
+            break;
+        case C_FILL:
+            coop_setup(X, q, C_MINEDGE, chunks_of(X->m, CE));
+            break;
+        case C_MINEDGE: {
+            const uint32_t any = X->f_any, bad = X->f_bad;
+            X->f_any = 0;
+            if (bad || !any) coop_finish<BS>(A, X, q, bad != 0);
+            else coop_setup(X, q, C_HOOK, chunks_of(X->ncur, CV));
+            break;
+        }
+        case C_HOOK:
+            X->jit = 0;
+            X->f_changed = 0;
+            coop_setup(X, q, C_JUMP, chunks_of(X->ncur, CV));
+            break;
+        case C_JUMP: {
+            const uint32_t changed = X->f_changed;
+            X->f_changed = 0;
+            if (changed && ++X->jit < (uint32_t)kMaxJumps)
+                coop_setup(X, q, C_JUMP, chunks_of(X->ncur, CV));
+            else
+                coop_setup(X, q, C_COUNT, chunks_of(X->ncur, CV));
+            break;
+        }
+        case C_COUNT: {
+            const uint32_t nch = chunks_of(X->ncur, CV);
+            uint64_t sum = 0;
+            for (uint32_t c = 0; c < nch; ++c) {
+                const uint32_t v = S.cnt[c];
+                S.cnt[c] = (uint32_t)sum;
+                sum += v;
+            }
+            X->nnext = (int64_t)sum;
+            coop_setup(X, q, C_IDS, nch);
+            break;
+        }
+        case C_IDS:
+            coop_setup(X, q, C_COMPOSE, chunks_of(X->n, CV));
+            break;
+        case C_COMPOSE:
+            X->ncur = X->nnext;
+            X->round += 1;
+            if (X->ncur <= 1 || X->round >= (uint32_t)kBatchMaxRounds)
+                coop_finish<BS>(A, X, q, false);
+            else
+                coop_setup(X, q, C_FILL, chunks_of(X->ncur, CV));
+            break;
+        default:
+            break;
+    }
+}
+
+struct CoopParams {
+    int64_t g, n, m, ncur, e0;
+    uint32_t kind, nchunks, round;
+};
+
+// One chunk of a phase, by the whole workgroup.
+template <int BS>
+__device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
+                           const CoopParams& P, uint32_t chunk, uint32_t* s_wave,
+                           uint64_t* s_red) {
+    constexpr int64_t CV = (int64_t)BS * kCoopVertsPerThread;
+    constexpr int64_t CE = (int64_t)BS * kCoopEdgesPerThread;
+    const int tid = threadIdx.x;
+    const int32_t* U = A.u + P.e0;
+    const int32_t* V = A.v + P.e0;
+    const uint32_t* W = A.w + P.e0;
+    uint8_t* mask = A.mask + P.e0;
+    const int64_t v0 = (int64_t)chunk * CV, e0 = (int64_t)chunk * CE;
+    const int64_t vn = v0 + CV < P.ncur ? v0 + CV : P.ncur;    // vertex chunk end (live labels)
+    switch (P.kind) {
+        case C_INIT: {
+            const int64_t eh = e0 + CE < P.m ? e0 + CE : P.m;
+            for (int64_t i = e0 + tid; i < eh; i += BS) mask[i] = 0;
+            const int64_t xh = v0 + CV < P.n ? v0 + CV : P.n;
+            for (int64_t x = v0 + tid; x < xh; x += BS) S.lab[x] = (int32_t)x;
+            break;
+        }
+        case C_FILL:
+            for (int64_t x = v0 + tid; x < vn; x += BS) S.best[x] = kKeyMax;
+            break;
+        case C_MINEDGE: {
+            const int64_t eh = e0 + CE < P.m ? e0 + CE : P.m;
+            int any = 0;
+            bool bad = false;
+            min_edges<BS>(U, V, W, e0, eh, P.n, (int)P.round, S.lab, S.best, any, bad);
+            const int bany = __syncthreads_or(any), bbad = __syncthreads_or(bad);
+            if (tid == 0) {
+                if (bany) atomicOr(&X->f_any, 1u);
+                if (bbad) atomicOr(&X->f_bad, 1u);
+            }
+            break;
+        }
+        case C_HOOK: {
+            const uint64_t ws = block_sum_u64<BS>(
+                hook_range(U, V, v0, vn, BS, S.lab, S.best, S.par, mask), s_red);
+            if (tid == 0 && ws) atomicAdd((unsigned long long*)&X->total, (unsigned long long)ws);
+            break;
+        }
+        case C_JUMP: {
+            int changed = 0;
+            for (int64_t x = v0 + tid; x < vn; x += BS) {
+                const int32_t p = S.par[x], pp = S.par[p];
+                if (p != pp) { S.par[x] = pp; changed = 1; }
+            }
+            if (__syncthreads_or(changed) && tid == 0) atomicOr(&X->f_changed, 1u);
+            break;
+        }
+        case C_COUNT: {
+            uint32_t c = 0;
+            for (int64_t base = v0; base < v0 + CV; base += BS) {
+                const int64_t x = base + tid;
+                const bool rt = x < vn && S.par[x] == (int32_t)x && S.best[x] != kKeyMax;
+                uint32_t tot;
+                (void)block_rank<BS>(rt, s_wave, &tot);
+                c += tot;
+            }
+            if (tid == 0) S.cnt[chunk] = c;
+            break;
+        }
+        case C_IDS: {
+            int64_t roots = S.cnt[chunk];
+            for (int64_t base = v0; base < v0 + CV; base += BS) {
+                const int64_t x = base + tid;
+                const bool rt = x < vn && S.par[x] == (int32_t)x && S.best[x] != kKeyMax;
+                uint32_t tot;
+                const uint32_t rk = block_rank<BS>(rt, s_wave, &tot);
+                if (rt) S.nid[x] = (int32_t)(roots + rk);
+                roots += tot;
+            }
+            break;
+        }
+        case C_COMPOSE: {
+            const int64_t xh = v0 + CV < P.n ? v0 + CV : P.n;
+            for (int64_t i = v0 + tid; i < xh; i += BS) {
+                const int32_t l = S.lab[i];
+                if (l >= 0) S.lab[i] = S.best[l] == kKeyMax ? -1 : S.nid[S.par[l]];
+            }
+            break;
+        }
+        default:
+            break;
+    }
+}
+
+// Waits (thread 0) until the ticket leaves phase p; false after kWaitTicks.
+__device__ bool coop_wait(XcdWork* X, uint32_t p, BatchQueue* q) {
+    const uint64_t deadline = wall_clock64() + kWaitTicks;
+    uint32_t nap = 1;
+    while ((uint32_t)(__hip_atomic_load(&X->ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >>
+                      32) == p) {
+        if (wall_clock64() > deadline ||
+            __hip_atomic_load(&q->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            atomicOr(&q->err, 1u);
+            return false;
+        }
+        if (nap == 1) __builtin_amdgcn_s_sleep(1);
+        else if (nap == 2) __builtin_amdgcn_s_sleep(4);
+        else __builtin_amdgcn_s_sleep(16);
+        nap = nap < 3 ? nap + 1 : 3;
+    }
+    return true;
+}
+
+template <int BS>
+__device__ void coop_run(const BatchArgs& A, uint32_t* s_wave, uint64_t* s_red) {
+    __shared__ uint64_t s_ticket;
+    __shared__ CoopParams s_p;
+    __shared__ uint32_t s_flag;
+    const uint32_t xcd = xcc_id();
+    XcdWork* X = &A.xw[xcd];
+    const SlotView S = slot_view(A.xslots + (size_t)xcd * A.slot_bytes, A.nmax);
+    if (threadIdx.x == 0 && atomicCAS(&X->state, 0u, 1u) == 0u) {
+        __threadfence();
+        coop_next_graph<BS>(A, X, 0);        // the first workgroup here starts phase 0
+    }
+    while (true) {
+        if (threadIdx.x == 0) {
+            const uint64_t t = __hip_atomic_fetch_add(&X->ticket, (uint64_t)1, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = t;
+            const uint32_t p = (uint32_t)(t >> 32);
+            s_flag = 0;
+            if (p != kNotReady) {
+                __threadfence();
+                s_p.kind = X->kind[p & 1];
+                s_p.nchunks = X->nchunks[p & 1];
+                s_p.g = X->graph;
+                s_p.n = X->n;
+                s_p.m = X->m;
+                s_p.ncur = X->ncur;
+                s_p.round = X->round;
+                s_p.e0 = s_p.kind == C_DONE ? 0 : A.eoff[s_p.g];
+            }
+        }
+        __syncthreads();
+        const uint64_t t = s_ticket;
+        const uint32_t p = (uint32_t)(t >> 32), chunk = (uint32_t)t;
+        const CoopParams P = s_p;
+        __syncthreads();
+        if (p != kNotReady && P.kind == C_DONE) break;
+        if (p == kNotReady || chunk >= P.nchunks) {       // nothing left here: wait
+            if (threadIdx.x == 0) s_flag = coop_wait(X, p, A.q) ? 0u : 1u;
+            __syncthreads();
+            const uint32_t gave_up = s_flag;
+            __syncthreads();
+            if (gave_up) break;
+            continue;
+        }
+        coop_chunk<BS>(A, X, S, P, chunk, s_wave, s_red);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const uint32_t d = atomicAdd(&X->done[p & 1], 1u);
+            if (d + 1 == P.nchunks) {
+                __threadfence();
+                coop_transition<BS>(A, X, S, p, P.kind);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+
 template <int BS>
 __global__ __launch_bounds__(BS) void k_batch(BatchArgs A) {
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t s_wave[BS / kWave];
+    __shared__ uint64_t s_red[BS / kWave];
     __shared__ int64_t s_g;
-    if (threadIdx.x == 0 && A.ticks) atomicMin((unsigned long long*)&A.ticks[A.G],
-                                               (unsigned long long)wall_clock64());
-    char* slot = A.scratch + (size_t)blockIdx.x * A.slot_bytes;
+    if (threadIdx.x == 0 && A.ticks)
+        atomicMin((unsigned long long*)&A.ticks[A.G], (unsigned long long)wall_clock64());
+    if (__hip_atomic_load(&A.q->nbig, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0)
+        coop_run<BS>(A, s_wave, s_red);
+
+    const int64_t nsmall = A.G - (int64_t)A.q->nbig;
+    const int64_t cap = A.lds_n;
+    char* wslot = A.wslots + (size_t)blockIdx.x * A.slot_bytes;
+    const SlotView G = slot_view(wslot, A.nmax);
     while (true) {
-        if (threadIdx.x == 0) s_g = (int64_t)atomicAdd(A.queue, 1u);
+        if (threadIdx.x == 0) s_g = (int64_t)atomicAdd(&A.q->small_next, 1u);
         __syncthreads();
         const int64_t gi = s_g;
         __syncthreads();
-        if (gi >= A.G) break;
-        const int64_t g = A.order ? (int64_t)A.order[gi] : gi;
-        const int64_t n = A.voff[g + 1] - A.voff[g];
-        if (n <= A.lds_n) {
-            const int64_t cap = A.lds_n;
-            uint64_t* best = lds;
+        if (gi >= nsmall) break;
+        const int64_t g = A.small[gi];
+        if (A.voff[g + 1] - A.voff[g] <= cap) {
             int32_t* lab = reinterpret_cast<int32_t*>(lds + cap);
-            int32_t* par = lab + cap;
-            int32_t* nid = par + cap;
-            solve_graph<BS>(A, g, lab, best, par, nid, s_wave);
+            solve_graph<BS>(A, g, cap, lab, lds, lab + cap, lab + 2 * cap, s_wave);
         } else {
-            const size_t cap = (size_t)A.nmax;
-            uint64_t* best = reinterpret_cast<uint64_t*>(slot);
-            int32_t* lab = reinterpret_cast<int32_t*>(slot + cap * 8);
-            int32_t* par = lab + cap;
-            int32_t* nid = par + cap;
-            solve_graph<BS>(A, g, lab, best, par, nid, s_wave);
+            solve_graph<BS>(A, g, A.nmax, G.lab, G.best, G.par, G.nid, s_wave);
         }
     }
 }
 
-__global__ void k_batch_prep(uint32_t* queue, uint64_t* ticks, int64_t G) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *queue = 0;
-        if (ticks) ticks[G] = kKeyMax;
+// Clears the counters and the cooperative blocks, splits the order into the
+// cooperative and other lists (stable), marks the batch start.  One workgroup.
+constexpr int kPrepThreads = 1024;
+__global__ __launch_bounds__(kPrepThreads) void k_batch_prep(BatchArgs A) {
+    __shared__ uint32_t s_wave[kPrepThreads / kWave];
+    if (threadIdx.x < sizeof(BatchQueue) / 4) reinterpret_cast<uint32_t*>(A.q)[threadIdx.x] = 0;
+    uint32_t* xw = reinterpret_cast<uint32_t*>(A.xw);
+    for (uint32_t i = threadIdx.x; i < kMaxXcd * sizeof(XcdWork) / 4; i += blockDim.x) xw[i] = 0;
+    __syncthreads();
+    if (threadIdx.x < kMaxXcd) A.xw[threadIdx.x].ticket = (uint64_t)kNotReady << 32;
+    if (threadIdx.x == 0 && A.ticks) A.ticks[A.G] = kKeyMax;
+    uint32_t nb = 0, ns = 0;
+    for (int64_t base = 0; base < A.G; base += kPrepThreads) {
+        const int64_t i = base + threadIdx.x;
+        int64_t g = -1;
+        bool big = false;
+        if (i < A.G) {
+            g = A.order ? (int64_t)A.order[i] : i;
+            big = A.coop_edges >= 0 && A.eoff[g + 1] - A.eoff[g] >= A.coop_edges;
+        }
+        uint32_t tb, ts;
+        const uint32_t rb = block_rank<kPrepThreads>(big, s_wave, &tb);
+        const uint32_t rs = block_rank<kPrepThreads>(i < A.G && !big, s_wave, &ts);
+        if (i < A.G) {
+            if (big) A.big[nb + rb] = (int32_t)g;
+            else A.small[ns + rs] = (int32_t)g;
+        }
+        nb += tb;
+        ns += ts;
     }
+    if (threadIdx.x == 0) A.q->nbig = nb;
 }
 
 size_t batch_slot_bytes(int64_t nmax) {
-    return ((size_t)(nmax > 0 ? nmax : 1) * 20 + 255) / 256 * 256;
+    const size_t cap = (size_t)(nmax > 0 ? nmax : 1);
+    const size_t chunks = cap / ((size_t)kMinBatchBlock * kCoopVertsPerThread) + 2;
+    return (cap * 20 + chunks * 4 + 255) / 256 * 256;
 }
 
-// Launches the batch; `workgroups` slots of slot_bytes each must follow `scratch`.
-int launch_batch(const BatchArgs& A0, int block, int workgroups, hipStream_t s) {
-    BatchArgs A = A0;
-    A.slot_bytes = batch_slot_bytes(A.nmax);
+BatchLayout batch_layout(int64_t G, int64_t nmax, int workgroups) {
+    BatchLayout L;
+    size_t off = (sizeof(BatchQueue) + 255) / 256 * 256;
+    L.xw_off = off;
+    off += (size_t)kMaxXcd * sizeof(XcdWork);
+    L.lists_off = off;
+    off += ((size_t)(G > 0 ? G : 1) * 8 + 255) / 256 * 256;
+    L.xslots_off = off;
+    off += (size_t)kMaxXcd * batch_slot_bytes(nmax);
+    L.wslots_off = off;
+    off += (size_t)(workgroups > 0 ? workgroups : 1) * batch_slot_bytes(nmax);
+    L.total = off;
+    return L;
+}
+
+int launch_batch(const BatchArgs& A, int block, int workgroups, hipStream_t s) {
     const size_t lds = (size_t)A.lds_n * 20;
-    hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(64), 0, s, A.queue, A.ticks, A.G);
+    hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(kPrepThreads), 0, s, A);
     switch (block) {
         case 256: hipLaunchKernelGGL(k_batch<256>, dim3(workgroups), dim3(256), lds, s, A); break;
         case 512: hipLaunchKernelGGL(k_batch<512>, dim3(workgroups), dim3(512), lds, s, A); break;
@@ -222,6 +632,22 @@ bool batch_allow_lds(int block, size_t bytes) {
     }
     if (e != hipSuccess) (void)hipGetLastError();
     return e == hipSuccess;
+}
+
+int batch_resident_workgroups(int block, size_t lds_bytes) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e;
+    switch (block) {
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<256>, 256, lds_bytes); break;
+        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<512>, 512, lds_bytes); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<1024>, 1024, lds_bytes); break;
+    }
+    if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus;
 }
 
 }  // namespace msf

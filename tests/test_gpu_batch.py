@@ -46,6 +46,50 @@ def test_batch_matches_oracle(block, lds):
     assert (mask == rm).all()
 
 
+@pytest.mark.parametrize("coop,workgroups", [(1 << 16, 0), (1 << 14, 0), (1 << 16, 24),
+                                             (1 << 16, 3)])
+def test_batch_cooperative_match_oracle(coop, workgroups):
+    """Graphs with at least coop edges are solved by all workgroups of an XCD
+    together, the rest by one workgroup each (LDS or a global slot); also with
+    fewer workgroups than XCDs."""
+    import paper_2302_12199_amd as msf
+    banner(f"batch coop={coop} workgroups={workgroups}")
+    u, v, w, eo, vo = graphgen.batch_gnm(160, lo=8, hi=15, dlo=2, dhi=40, seed=21)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    b = make_batch(u, v, w, eo, vo,
+                   options=msf.make_batch_options(block=512, lds_vertices=1024,
+                                                  coop_edges=coop, workgroups=workgroups))
+    for _ in range(2):                    # a second launch reuses the team blocks
+        b.launch()
+        mask, totals = results(b)
+        assert (totals == rt).all()
+        assert (mask == rm).all()
+
+
+def test_batch_bad_graph_flagged_in_every_path():
+    import paper_2302_12199_amd as msf
+    banner("batch invalid ids")
+    u, v, w, eo, vo = graphgen.batch_gnm(40, lo=8, hi=13, seed=22)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    sizes = vo[1:] - vo[:-1]
+    big = int(np.argmax(sizes))
+    small = int(np.argmin(sizes))
+    u = u.copy()
+    mid = int(np.argsort(sizes)[len(sizes) // 2])
+    u[eo[big]] = sizes[big] + 5           # out of range in a cooperative graph
+    u[eo[small] + 1] = sizes[small]       # in an LDS-solved one
+    u[eo[mid] + 2] = -1                   # and in one solved in a global slot
+    b = make_batch(u, v, w, eo, vo,
+                   options=msf.make_batch_options(lds_vertices=1024, coop_edges=int(
+                       (eo[big + 1] - eo[big]))))
+    b.launch()
+    mask, totals = results(b)
+    bad = np.zeros(len(rt), bool)
+    bad[[big, small, mid]] = True
+    assert (totals[bad] == np.uint64(2**64 - 1)).all()
+    assert (totals[~bad] == rt[~bad]).all()
+
+
 def test_batch_unordered_and_ticks():
     banner("batch unordered, ticks")
     u, v, w, eo, vo = graphgen.batch_gnm(120, lo=8, hi=12, dlo=1, dhi=8, wlo=1, whi=7, seed=12)
