@@ -175,7 +175,7 @@ int msf_batched_graph_destroy(msf_batch_graph* graph);
 /*
  * Autotuner for the batched solver: runs the batch once per candidate
  * (block in {512, 1024} x lds_vertices in {1024, 2048, 4096} x coop_edges in
- * {2^18, 2^20, never}) on
+ * {2^19, 2^20, never}) on
  * `stream`, times each with HIP events and writes the fastest to *best_out
  * (HOST); *best_ms_out (HOST, nullable) gets its time.  Blocking.  Same array
  * arguments as msf_compute_batched; the workspace must fit every candidate

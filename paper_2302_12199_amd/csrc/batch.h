@@ -9,6 +9,11 @@ constexpr int kMaxXcd = 16;          // XCC_ID is a 4-bit field
 constexpr int kCoopVertsPerThread = 8;
 constexpr int kCoopEdgesPerThread = 16;
 constexpr int kMinBatchBlock = 256;
+constexpr int kCoopPairsPerThread = 16;
+// Once a cooperative graph has at most kPairMax live vertices, its edges are
+// reduced to the lightest edge per vertex pair (a triangular table) and the
+// remaining rounds scan the table instead of the edges.
+constexpr int64_t kPairMax = 4096;
 
 // Per-launch counters at the start of the workspace (zeroed by k_batch_prep).
 struct BatchQueue {
@@ -32,9 +37,10 @@ struct alignas(256) XcdWork {
     uint32_t round;                 // Borůvka round of the current graph
     uint32_t jit;                   // pointer-jumping step
     uint32_t f_any, f_bad, f_changed;
-    uint32_t pad;
+    uint32_t pair_mode;             // rounds scan the pair table
     int64_t graph, n, m;            // current graph
     int64_t ncur, nnext;            // live vertices this round / next round
+    int64_t pn;                     // vertices of the pair table
     uint64_t total;                 // MSF weight so far
 };
 
@@ -53,9 +59,10 @@ struct BatchArgs {
     XcdWork* xw;             // [kMaxXcd]
     int32_t* big;            // [G] cooperative graphs in processing order (first q->nbig)
     int32_t* small;          // [G] the others in processing order
-    char* xslots;            // kMaxXcd state slots (cooperative solves)
+    char* xslots;            // kMaxXcd state slots (cooperative solves), xslot_bytes each
     char* wslots;            // one state slot per workgroup (graphs above lds_n)
-    size_t slot_bytes;
+    size_t slot_bytes;       // per-vertex state of one graph
+    size_t xslot_bytes;      // slot_bytes + pair table
     int64_t nmax;            // vertices per graph the slots are sized for
     int64_t coop_edges;      // graphs with at least this many edges are cooperative (< 0: none)
     int lds_n;               // graphs with n <= lds_n keep their state in LDS
@@ -68,6 +75,7 @@ BatchLayout batch_layout(int64_t G, int64_t nmax, int workgroups);
 
 int launch_batch(const BatchArgs& A, int block, int workgroups, hipStream_t s);
 size_t batch_slot_bytes(int64_t nmax);
+size_t batch_xslot_bytes(int64_t nmax);
 bool batch_allow_lds(int block, size_t bytes);
 int batch_resident_workgroups(int block, size_t lds_bytes);
 

@@ -31,8 +31,35 @@ constexpr uint32_t kNotReady = 0xffffffffu;       // phase id before the first s
 constexpr uint64_t kWaitTicks = 200000000ull;     // 2 s of the 100 MHz wall clock
 
 enum CoopKind : uint32_t {
-    C_NONE = 0, C_INIT, C_FILL, C_MINEDGE, C_HOOK, C_JUMP, C_COUNT, C_IDS, C_COMPOSE, C_DONE
+    C_NONE = 0, C_INIT, C_FILL, C_MINEDGE, C_HOOK, C_JUMP, C_COUNT, C_IDS, C_COMPOSE, C_PFILL,
+    C_PBUILD, C_DONE
 };
+
+__host__ __device__ __forceinline__ int64_t tri_slot(int64_t x, int64_t y) {
+    const int64_t lo = x < y ? x : y, hi = x < y ? y : x;
+    return hi * (hi - 1) / 2 + lo;
+}
+
+// Inverse of tri_slot: slot s -> (lo, hi), lo < hi.
+__device__ __forceinline__ void tri_pair(int64_t s, int32_t& lo, int32_t& hi) {
+    int64_t h = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)s)) * 0.5);
+    while (h * (h - 1) / 2 > s) --h;
+    while ((h + 1) * h / 2 <= s) ++h;
+    hi = (int32_t)h;
+    lo = (int32_t)(s - h * (h - 1) / 2);
+}
+
+// Ordering between workgroups of ONE XCD, which share its L2: a wave's stores
+// are complete at the L2 once its vmcnt drains (the vector L1 writes through;
+// every wave must drain its own before the workgroup barrier that precedes
+// the signal), and a reader drops its CU's L1 before reading.  No L2
+// write-back is needed, unlike the device-wide __threadfence.
+__device__ __forceinline__ void xcd_release() {
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+}
+__device__ __forceinline__ void xcd_acquire() {
+    asm volatile("buffer_inv sc1" ::: "memory");
+}
 
 __device__ __forceinline__ uint32_t xcc_id() {
     uint32_t x;
@@ -221,10 +248,12 @@ struct SlotView {
     int32_t* lab;
     int32_t* par;
     int32_t* nid;
-    uint32_t* cnt;   // roots per vertex chunk, then their exclusive prefix
+    uint32_t* cnt;     // roots per vertex chunk, then their exclusive prefix
+    uint64_t* pairs;   // cooperative slots: lightest key per vertex pair
+    int32_t* plab;     // cooperative slots: current label of each pair-table vertex
 };
 
-__device__ __forceinline__ SlotView slot_view(char* slot, int64_t nmax) {
+__device__ __forceinline__ SlotView slot_view(char* slot, int64_t nmax, size_t slot_bytes) {
     SlotView s;
     const size_t cap = (size_t)nmax;
     s.best = reinterpret_cast<uint64_t*>(slot);
@@ -232,6 +261,8 @@ __device__ __forceinline__ SlotView slot_view(char* slot, int64_t nmax) {
     s.par = s.lab + cap;
     s.nid = s.par + cap;
     s.cnt = reinterpret_cast<uint32_t*>(s.nid + cap);
+    s.pairs = reinterpret_cast<uint64_t*>(slot + slot_bytes);
+    s.plab = reinterpret_cast<int32_t*>(s.pairs + kPairMax * (kPairMax - 1) / 2);
     return s;
 }
 
@@ -244,7 +275,7 @@ __device__ void coop_setup(XcdWork* X, uint32_t p, uint32_t kind, uint32_t nchun
     X->kind[p & 1] = kind;
     X->nchunks[p & 1] = nchunks;
     X->done[p & 1] = 0;
-    __threadfence();
+    xcd_release();
     atomicExch((unsigned long long*)&X->ticket, (unsigned long long)((uint64_t)p << 32));
 }
 
@@ -273,6 +304,8 @@ __device__ void coop_next_graph(const BatchArgs& A, XcdWork* X, uint32_t p) {
         X->ncur = n;
         X->round = 0;
         X->total = 0;
+        X->pair_mode = 0;
+        X->pn = 0;
         X->f_any = X->f_bad = X->f_changed = 0;
         const uint32_t ce = chunks_of(m, CE), cv = chunks_of(n, CV);
         coop_setup(X, p, C_INIT, ce > cv ? ce : cv);
@@ -294,6 +327,7 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
                                 uint32_t kind) {
     constexpr int64_t CV = (int64_t)BS * kCoopVertsPerThread;
     constexpr int64_t CE = (int64_t)BS * kCoopEdgesPerThread;
+    constexpr int64_t CP = (int64_t)BS * kCoopPairsPerThread;
     const uint32_t q = p + 1;
     switch (kind) {
         case C_INIT:
@@ -301,7 +335,10 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
             else coop_setup(X, q, C_FILL, chunks_of(X->ncur, CV));
             break;
         case C_FILL:
-            coop_setup(X, q, C_MINEDGE, chunks_of(X->m, CE));
+            if (X->pair_mode)
+                coop_setup(X, q, C_MINEDGE, chunks_of(X->pn * (X->pn - 1) / 2, CP));
+            else
+                coop_setup(X, q, C_MINEDGE, chunks_of(X->m, CE));
             break;
         case C_MINEDGE: {
             const uint32_t any = X->f_any, bad = X->f_bad;
@@ -336,16 +373,32 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
             coop_setup(X, q, C_IDS, nch);
             break;
         }
-        case C_IDS:
-            coop_setup(X, q, C_COMPOSE, chunks_of(X->n, CV));
+        case C_IDS: {
+            const uint32_t cn = chunks_of(X->n, CV), cp = chunks_of(X->pn, CV);
+            coop_setup(X, q, C_COMPOSE, cn > cp ? cn : cp);
             break;
+        }
         case C_COMPOSE:
             X->ncur = X->nnext;
             X->round += 1;
-            if (X->ncur <= 1 || X->round >= (uint32_t)kBatchMaxRounds)
+            if (X->ncur <= 1 || X->round >= (uint32_t)kBatchMaxRounds) {
                 coop_finish<BS>(A, X, q, false);
-            else
+            } else if (!X->pair_mode && X->ncur <= kPairMax &&
+                       X->ncur * (X->ncur - 1) / 2 < X->m / 2) {
+                X->pn = X->ncur;
+                const uint32_t cs = chunks_of(X->pn * (X->pn - 1) / 2, CP);
+                const uint32_t cv = chunks_of(X->pn, CV);
+                coop_setup(X, q, C_PFILL, cs > cv ? cs : cv);
+            } else {
                 coop_setup(X, q, C_FILL, chunks_of(X->ncur, CV));
+            }
+            break;
+        case C_PFILL:
+            coop_setup(X, q, C_PBUILD, chunks_of(X->m, CE));
+            break;
+        case C_PBUILD:
+            X->pair_mode = 1;
+            coop_setup(X, q, C_FILL, chunks_of(X->ncur, CV));
             break;
         default:
             break;
@@ -353,8 +406,8 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
 }
 
 struct CoopParams {
-    int64_t g, n, m, ncur, e0;
-    uint32_t kind, nchunks, round;
+    int64_t g, n, m, ncur, e0, pn;
+    uint32_t kind, nchunks, round, pair_mode;
 };
 
 // One chunk of a phase, by the whole workgroup.
@@ -364,6 +417,7 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
                            uint64_t* s_red) {
     constexpr int64_t CV = (int64_t)BS * kCoopVertsPerThread;
     constexpr int64_t CE = (int64_t)BS * kCoopEdgesPerThread;
+    constexpr int64_t CP = (int64_t)BS * kCoopPairsPerThread;
     const int tid = threadIdx.x;
     const int32_t* U = A.u + P.e0;
     const int32_t* V = A.v + P.e0;
@@ -383,10 +437,26 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
             for (int64_t x = v0 + tid; x < vn; x += BS) S.best[x] = kKeyMax;
             break;
         case C_MINEDGE: {
-            const int64_t eh = e0 + CE < P.m ? e0 + CE : P.m;
             int any = 0;
             bool bad = false;
-            min_edges<BS>(U, V, W, e0, eh, P.n, (int)P.round, S.lab, S.best, any, bad);
+            if (P.pair_mode) {            // over the pair table
+                const int64_t np = P.pn * (P.pn - 1) / 2;
+                const int64_t s0 = (int64_t)chunk * CP, sh = s0 + CP < np ? s0 + CP : np;
+                for (int64_t sl = s0 + tid; sl < sh; sl += BS) {
+                    const uint64_t key = S.pairs[sl];
+                    if (key == kKeyMax) continue;
+                    int32_t lo, hi;
+                    tri_pair(sl, lo, hi);
+                    const int32_t lx = S.plab[lo], ly = S.plab[hi];
+                    if (lx == ly) continue;
+                    any = 1;
+                    atomic_min_key(&S.best[lx], key);
+                    atomic_min_key(&S.best[ly], key);
+                }
+            } else {
+                const int64_t eh = e0 + CE < P.m ? e0 + CE : P.m;
+                min_edges<BS>(U, V, W, e0, eh, P.n, (int)P.round, S.lab, S.best, any, bad);
+            }
             const int bany = __syncthreads_or(any), bbad = __syncthreads_or(bad);
             if (tid == 0) {
                 if (bany) atomicOr(&X->f_any, 1u);
@@ -439,6 +509,32 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
                 const int32_t l = S.lab[i];
                 if (l >= 0) S.lab[i] = S.best[l] == kKeyMax ? -1 : S.nid[S.par[l]];
             }
+            if (P.pair_mode) {
+                const int64_t ph = v0 + CV < P.pn ? v0 + CV : P.pn;
+                for (int64_t i = v0 + tid; i < ph; i += BS) {
+                    const int32_t l = S.plab[i];
+                    if (l >= 0) S.plab[i] = S.best[l] == kKeyMax ? -1 : S.nid[S.par[l]];
+                }
+            }
+            break;
+        }
+        case C_PFILL: {                   // empty pair table; pair vertex i = label i
+            const int64_t np = P.pn * (P.pn - 1) / 2;
+            const int64_t s0 = (int64_t)chunk * CP, sh = s0 + CP < np ? s0 + CP : np;
+            for (int64_t sl = s0 + tid; sl < sh; sl += BS) S.pairs[sl] = kKeyMax;
+            const int64_t ph = v0 + CV < P.pn ? v0 + CV : P.pn;
+            for (int64_t i = v0 + tid; i < ph; i += BS) S.plab[i] = (int32_t)i;
+            break;
+        }
+        case C_PBUILD: {                  // lightest edge per pair of current labels
+            const int64_t eh = e0 + CE < P.m ? e0 + CE : P.m;
+            for (int64_t e = e0 + tid; e < eh; e += BS) {
+                const int32_t a = U[e], b = V[e];
+                if (a == b) continue;
+                const int32_t la = S.lab[a], lb = S.lab[b];
+                if (la == lb || la < 0 || lb < 0) continue;
+                atomic_min_key(&S.pairs[tri_slot(la, lb)], ((uint64_t)W[e] << 32) | (uint64_t)e);
+            }
             break;
         }
         default:
@@ -472,20 +568,20 @@ __device__ void coop_run(const BatchArgs& A, uint32_t* s_wave, uint64_t* s_red) 
     __shared__ uint32_t s_flag;
     const uint32_t xcd = xcc_id();
     XcdWork* X = &A.xw[xcd];
-    const SlotView S = slot_view(A.xslots + (size_t)xcd * A.slot_bytes, A.nmax);
+    const SlotView S = slot_view(A.xslots + (size_t)xcd * A.xslot_bytes, A.nmax, A.slot_bytes);
     if (threadIdx.x == 0 && atomicCAS(&X->state, 0u, 1u) == 0u) {
         __threadfence();
         coop_next_graph<BS>(A, X, 0);        // the first workgroup here starts phase 0
     }
     while (true) {
         if (threadIdx.x == 0) {
-            const uint64_t t = __hip_atomic_fetch_add(&X->ticket, (uint64_t)1, __ATOMIC_ACQ_REL,
+            const uint64_t t = __hip_atomic_fetch_add(&X->ticket, (uint64_t)1, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             s_ticket = t;
             const uint32_t p = (uint32_t)(t >> 32);
             s_flag = 0;
             if (p != kNotReady) {
-                __threadfence();
+                xcd_acquire();
                 s_p.kind = X->kind[p & 1];
                 s_p.nchunks = X->nchunks[p & 1];
                 s_p.g = X->graph;
@@ -493,6 +589,8 @@ __device__ void coop_run(const BatchArgs& A, uint32_t* s_wave, uint64_t* s_red) 
                 s_p.m = X->m;
                 s_p.ncur = X->ncur;
                 s_p.round = X->round;
+                s_p.pn = X->pn;
+                s_p.pair_mode = X->pair_mode;
                 s_p.e0 = s_p.kind == C_DONE ? 0 : A.eoff[s_p.g];
             }
         }
@@ -511,12 +609,12 @@ __device__ void coop_run(const BatchArgs& A, uint32_t* s_wave, uint64_t* s_red) 
             continue;
         }
         coop_chunk<BS>(A, X, S, P, chunk, s_wave, s_red);
+        xcd_release();                       // every wave's stores reach the L2 ...
         __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
+        if (threadIdx.x == 0) {              // ... before the chunk counts as done
             const uint32_t d = atomicAdd(&X->done[p & 1], 1u);
             if (d + 1 == P.nchunks) {
-                __threadfence();
+                xcd_acquire();
                 coop_transition<BS>(A, X, S, p, P.kind);
             }
         }
@@ -540,7 +638,7 @@ __global__ __launch_bounds__(BS) void k_batch(BatchArgs A) {
     const int64_t nsmall = A.G - (int64_t)A.q->nbig;
     const int64_t cap = A.lds_n;
     char* wslot = A.wslots + (size_t)blockIdx.x * A.slot_bytes;
-    const SlotView G = slot_view(wslot, A.nmax);
+    const SlotView G = slot_view(wslot, A.nmax, A.slot_bytes);
     while (true) {
         if (threadIdx.x == 0) s_g = (int64_t)atomicAdd(&A.q->small_next, 1u);
         __syncthreads();
@@ -596,6 +694,11 @@ size_t batch_slot_bytes(int64_t nmax) {
     return (cap * 20 + chunks * 4 + 255) / 256 * 256;
 }
 
+size_t batch_xslot_bytes(int64_t nmax) {
+    return batch_slot_bytes(nmax) +
+           ((size_t)kPairMax * (kPairMax - 1) / 2 * 8 + (size_t)kPairMax * 4 + 255) / 256 * 256;
+}
+
 BatchLayout batch_layout(int64_t G, int64_t nmax, int workgroups) {
     BatchLayout L;
     size_t off = (sizeof(BatchQueue) + 255) / 256 * 256;
@@ -604,7 +707,7 @@ BatchLayout batch_layout(int64_t G, int64_t nmax, int workgroups) {
     L.lists_off = off;
     off += ((size_t)(G > 0 ? G : 1) * 8 + 255) / 256 * 256;
     L.xslots_off = off;
-    off += (size_t)kMaxXcd * batch_slot_bytes(nmax);
+    off += (size_t)kMaxXcd * batch_xslot_bytes(nmax);
     L.wslots_off = off;
     off += (size_t)(workgroups > 0 ? workgroups : 1) * batch_slot_bytes(nmax);
     L.total = off;

@@ -9,7 +9,7 @@ using namespace msf;
 
 namespace {
 
-constexpr int kTuneCoop[3] = {1 << 18, 1 << 20, -1};
+constexpr int kTuneCoop[3] = {1 << 19, 1 << 20, -1};
 
 struct Resolved {
     int block, lds_n, workgroups;
@@ -78,6 +78,7 @@ int prepare(const int32_t* u, const int32_t* v, const uint32_t* w, const int64_t
     A->xslots = base + L.xslots_off;
     A->wslots = base + L.wslots_off;
     A->slot_bytes = batch_slot_bytes(max_n);
+    A->xslot_bytes = batch_xslot_bytes(max_n);
     A->nmax = max_n;
     A->coop_edges = r->coop_edges;
     A->lds_n = r->lds_n;
