@@ -154,6 +154,8 @@ def main():
     ap.add_argument("--pivot", default="median")
     ap.add_argument("--quantile", type=float, default=0.5)
     ap.add_argument("--model", default=None, help="pivot network file (--pivot mlp)")
+    ap.add_argument("--no-pivot-compare", action="store_true",
+                    help="with --pivot mlp: skip the timed median-pivot comparison")
     ap.add_argument("--cpu-sample", type=int, default=1 << 27,
                     help="edges given to the timed CPU oracle (0 = skip)")
     ap.add_argument("--graphs", type=int, default=10000, help="batch workload: graphs")
@@ -224,7 +226,7 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step total={total}")
 
     pivot_cmp = None
-    if args.algo == "filter" and args.pivot == "mlp":
+    if args.algo == "filter" and args.pivot == "mlp" and not args.no_pivot_compare:
         # the same graph with the sampled-median pivot, for comparison
         mopts = dict(opts, pivot="median")
         for _ in range(args.warmup):
