@@ -249,11 +249,17 @@ def main():
         p = prof[dom]
         achieved = p["bytes"] / (p["ms"] / 1000.0) / 1e9
         traffic = load_traffic(dom, args.workload)
+        launch_ms = p["ms"] / p["launches"]
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                     "traffic": traffic,
-                    "launch_ms": round(p["ms"] / p["launches"], 4),
+                    "launch_ms": round(launch_ms, 4),
                     "algorithmic_bytes_per_launch": p["bytes"] / p["launches"]}
+        if traffic:
+            # measured HBM bytes (random gathers move whole 128-byte lines) over the same time
+            tg = traffic / (launch_ms / 1000.0) / 1e9
+            roofline["traffic_GBps"] = round(tg, 1)
+            roofline["traffic_frac"] = round(tg / PEAK_HBM_GBS, 4)
     kernels = {k: {"ms_per_step": round(x["ms"] / args.steps, 4),
                    "launches_per_step": x["launches"] / args.steps,
                    "GBps": round(x["bytes"] / (x["ms"] / 1000.0) / 1e9, 1) if x["ms"] > 0 else None}

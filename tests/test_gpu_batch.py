@@ -165,3 +165,19 @@ def test_batch_large_graphs_global_scratch():
     b.launch()
     mask, totals = results(b)
     assert (totals == rt).all() and (mask == rm).all()
+
+
+def test_batch_sample_of_the_10k_workload():
+    """Graphs [4000, 4200) of the 10,000-graph batch workload (the sizes and
+    seeds the benchmark uses), default options, against the oracle per graph."""
+    banner("batch: slice of the 10k workload")
+    u, v, w, eo, vo = graphgen.batch_gnm(10000, lo=8, hi=18, dlo=4, dhi=64, wlo=1,
+                                         whi=2**31 - 1, seed=6, first=4000, count=200)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    b = make_batch(u, v, w, eo, vo)
+    b.capture()
+    b.replay()
+    mask, totals = results(b)
+    assert (totals == rt).all()
+    assert (mask == rm).all()
+    b.close()

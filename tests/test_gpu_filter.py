@@ -92,6 +92,29 @@ def test_filter_fullsize_rmat22_matches_stored_oracle():
     assert st["levels"] >= 3
 
 
+@pytest.mark.parametrize("name,pivot", [("rmat_n2^24_m2^28_w255", "median"),
+                                        ("rmat_n2^24_m2^28_w255", "mlp"),
+                                        ("rmat_n2^22_m2^28_w2^31", "mlp"),
+                                        ("grid_4096x4096_keep0.8_w255", "median"),
+                                        ("rgg2d_n2^24_deg8", "median")])
+def test_filter_fullsize_other_workloads(name, pivot):
+    """Full-size configurations through Filter-Borůvka (the shipped network or
+    the median pivot) against the stored oracle masks."""
+    import paper_2302_12199_amd as msf
+    ref = golden_hashes()[name]
+    banner(f"filter full size {name} pivot={pivot}")
+    u, v, w, n = graphgen.workload(name)
+    if pivot == "mlp":
+        msf.load_pivot_model()
+    try:
+        mask, total, st = gpu_msf(u, v, w, n, algo="filter", pivot=pivot,
+                                  min_split_edges=1 << 16)
+    finally:
+        msf.clear_pivot_model()
+    assert total == ref["total"] and st["msf_edges"] == ref["msf_edges"]
+    assert sha(mask) == ref["mask_sha256"]
+
+
 def test_filter_out_of_range():
     import paper_2302_12199_amd as msf
     banner("filter out of range")
