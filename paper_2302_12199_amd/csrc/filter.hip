@@ -73,6 +73,18 @@ __device__ __forceinline__ uint64_t key_at(const View& g, int64_t p) {
 //   14    fraction of repeated endpoints among the first <= 2048 sampled
 //         edges (a degree-skew proxy)
 //   15    1
+// One compare-exchange stage of an ascending bitonic sort of a[0, n) in LDS.
+template <typename T>
+__device__ __forceinline__ void bitonic_stage(T* a, int n, int k, int j) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+            const T x = a[i], y = a[ixj];
+            if ((x > y) == ((i & k) == 0)) { a[i] = y; a[ixj] = x; }
+        }
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kSampleThreads) void k_sample_pivot(View g, uint64_t base,
                                                                  int sample, float q,
@@ -107,32 +119,21 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_pivot(View g, uint64_
     }
     for (int i = 2 * ke + threadIdx.x; i < e2; i += blockDim.x) ends[i] = 0x7fffffff;
     __syncthreads();
-    for (int k = 2; k <= p2; k <<= 1) {
+    // Both arrays are sorted together.  In a stage with j < 64 the pair
+    // (i, i ^ j) belongs to one wave (thread t handles i = t mod blockDim), so
+    // only stages that cross waves, and the stages right before them, need the
+    // workgroup barrier; the others only drain the wave's LDS operations.
+    const int kmax = p2 > e2 ? p2 : e2;
+    for (int k = 2; k <= kmax; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < p2; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const uint64_t a = keys[i], b = keys[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) { keys[i] = b; keys[ixj] = a; }
-                }
-            }
-            __syncthreads();
+            if (k <= p2) bitonic_stage(keys, p2, k, j);
+            if (k <= e2) bitonic_stage(ends, e2, k, j);
+            const int next_j = j > 1 ? j >> 1 : k;       // first stage of the next k is j = k
+            if (j >= kWave || next_j >= kWave) __syncthreads();
+            else asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         }
     }
-    for (int k = 2; k <= e2; k <<= 1) {              // sort sampled endpoints
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < e2; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const int32_t a = ends[i], b = ends[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) { ends[i] = b; ends[ixj] = a; }
-                }
-            }
-            __syncthreads();
-        }
-    }
+    __syncthreads();
     // sample statistics (FP32)
     float sl = 0.f, sl2 = 0.f;
     uint32_t ties = 0, reps = 0;

@@ -181,3 +181,39 @@ def test_batch_sample_of_the_10k_workload():
     assert (totals == rt).all()
     assert (mask == rm).all()
     b.close()
+
+
+@pytest.mark.timeout(900)
+def test_batch_full_10k_workload_every_graph():
+    """The whole 10,000-graph workload (6.5e9 edges) in one captured launch;
+    every graph's mask and total against the oracle, run on 16 host threads
+    (the oracle's C code releases the GIL)."""
+    import concurrent.futures as cf
+    import torch
+    banner("batch: full 10k workload vs oracle (16 host threads)")
+    u, v, w, eo, vo = graphgen.batch_gnm(10000, lo=8, hi=18, dlo=4, dhi=64, wlo=1,
+                                         whi=2**31 - 1, seed=6)
+    b = make_batch(u, v, w, eo, vo)
+    b.capture()
+    b.replay()
+    torch.cuda.synchronize()
+    mask = b.mask[:int(eo[-1])].cpu().numpy()
+    totals = b.totals[:b.G].cpu().numpy().view(np.uint64)
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+
+    def check(lo, hi):
+        bad = []
+        for g in range(lo, hi):
+            a, c = int(eo[g]), int(eo[g + 1])
+            mk, t, _ = oracle.kruskal(u[a:c], v[a:c], w[a:c], int(vo[g + 1] - vo[g]))
+            if t != int(totals[g]) or not np.array_equal(mk, mask[a:c]):
+                bad.append(g)
+        return bad
+
+    with cf.ThreadPoolExecutor(16) as ex:
+        parts = list(ex.map(lambda r: check(*r), [(i, min(i + 50, 10000))
+                                                  for i in range(0, 10000, 50)]))
+    bad = [g for p in parts for g in p]
+    assert not bad, f"{len(bad)} graphs differ, first {bad[:5]}"
