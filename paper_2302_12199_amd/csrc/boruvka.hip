@@ -79,10 +79,16 @@ __device__ __forceinline__ uint32_t edge_id(const View& g, int64_t p) {
 
 // Lightest incident edge on the caller's arrays (4 edges per lane when the
 // arrays are 16-byte aligned).  Validates ids (kErrRange), skips self-loops.
+// `hot` (or -1) names a vertex expected on very many edges (the largest
+// component after a filter step): its minimum is taken in LDS per workgroup
+// and merged with one global atomic at the end.
 template <int VEC>
 __global__ __launch_bounds__(kBlock) void k_minedge_r0(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
-    int64_t m, int64_t n, uint64_t* __restrict__ best, Ctrl* ctrl) {
+    int64_t m, int64_t n, uint64_t* __restrict__ best, Ctrl* ctrl, int32_t hot) {
+    __shared__ unsigned long long s_hot;
+    if (threadIdx.x == 0) s_hot = kKeyMax;
+    __syncthreads();
     bool bad = false;
     const int64_t groups = (m + VEC - 1) / VEC;
     // the loop bound is uniform over the workgroup: every wave runs each step
@@ -120,11 +126,19 @@ __global__ __launch_bounds__(kBlock) void k_minedge_r0(
             act = act && a != b;
             if (!act) a = b = 0;
             const uint64_t key = ((uint64_t)ww[k] << 32) | (uint64_t)e;
-            wave_min_update(best, a, key, act);
-            wave_min_update(best, b, key, act);
+            bool act_a = act, act_b = act;
+            if (act && (a == hot || b == hot)) {
+                atomicMin(&s_hot, (unsigned long long)key);
+                act_a = a != hot;
+                act_b = b != hot;
+            }
+            wave_min_update(best, a, key, act_a);
+            wave_min_update(best, b, key, act_b);
         }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrRange);
+    __syncthreads();
+    if (threadIdx.x == 0 && hot >= 0 && s_hot != kKeyMax) atomic_min_key(&best[hot], s_hot);
 }
 
 // ------------------------------------------------------------------ hook
@@ -556,15 +570,16 @@ void launch_scan_prep(uint64_t* status, int64_t ntiles, Ctrl* ctrl, int round_be
                        ntiles, ctrl, round_begin);
 }
 void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
-                       int64_t n, uint64_t* best, Ctrl* ctrl, hipStream_t s) {
+                       int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, hipStream_t s) {
     if (m <= 0) return;
+    if (hot >= n) hot = -1;
     const bool aligned = (((uintptr_t)u | (uintptr_t)v | (uintptr_t)w) & 15) == 0;
     if (aligned)
         hipLaunchKernelGGL(k_minedge_r0<4>, dim3(grid_for((m + 3) / 4)), dim3(kBlock), 0, s, u,
-                           v, w, m, n, best, ctrl);
+                           v, w, m, n, best, ctrl, hot);
     else
         hipLaunchKernelGGL(k_minedge_r0<1>, dim3(grid_for(m)), dim3(kBlock), 0, s, u, v, w, m,
-                           n, best, ctrl);
+                           n, best, ctrl, hot);
 }
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
                  int32_t* parent, uint8_t* mask, Ctrl* ctrl, hipStream_t s) {

@@ -36,8 +36,10 @@ size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B);
 //               Borůvka.  rep[x] = x on entry for the vertices in the view;
 //               on return every vertex that was contracted points (directly
 //               or through a chain) to the vertex it was merged into.
+//   hot         a vertex of the view expected on very many edges, or -1
+//               (its round-0 minimum is reduced per workgroup in LDS)
 // Marks MSF edges in mask[] and accumulates total/msf_edges in B.ctrl.
 int engine_solve(EngineBuffers& B, int mode, const View& view, int64_t nv, uint8_t* mask,
-                 int32_t* rep, hipStream_t s, msf_stats* stats);
+                 int32_t* rep, hipStream_t s, msf_stats* stats, int32_t hot = -1);
 
 }  // namespace msf

@@ -108,7 +108,7 @@ static void dump(const char* name, uint32_t round, const void* dev, size_t bytes
 static double view_read_bytes(int mode) { return mode == kFull16 ? 8.0 : 12.0; }
 
 int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint8_t* mask,
-                 int32_t* rep, hipStream_t s, msf_stats* stats) {
+                 int32_t* rep, hipStream_t s, msf_stats* stats, int32_t hot) {
     Ctrl* hc = host_ctrl();
     Ctrl* dc = B.ctrl;
     View view = view0;
@@ -124,7 +124,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
     launch_fill_u64(B.best[cur], nr, kKeyMax, s);
     prof_end(h, s, 8.0 * nr);
     h = prof_begin(K_MINEDGE_R0, s);
-    launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, s);
+    launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, hot, s);
     prof_end(h, s, 12.0 * view.len + 8.0 * nv);
     HIP_TRY(hipGetLastError());
     if ((st = read_ctrl(dc, hc, s))) return st;

@@ -227,13 +227,16 @@ __global__ __launch_bounds__(kBlock) void k_count_tiles(View g,
 }
 
 // Exclusive scan of cnt[0, ntiles) in place by one workgroup of
-// kScanThreads threads, 8 consecutive entries per thread per sweep; the
+// kScanThreads threads, 32 consecutive entries per thread per sweep; the
 // total goes to *total.
 constexpr int kScanThreads = 1024;
+// Workgroups of the tile kernels (split, filter): each loops over tiles, so a
+// launch is not dominated by dispatching one short workgroup per tile.
+constexpr unsigned kTileGrid = 4096;
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint64_t* __restrict__ cnt,
                                                              uint32_t ntiles,
                                                              uint64_t* __restrict__ total) {
-    constexpr int kPer = 8;
+    constexpr int kPer = 32;
     __shared__ uint64_t s_w[kScanThreads / kWave];
     __shared__ uint64_t s_carry;
     const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
@@ -282,61 +285,63 @@ __global__ __launch_bounds__(kBlock) void k_split(View g, int64_t n,
                                                   const uint64_t* __restrict__ pivot_dev,
                                                   EdgeSoA out,
                                                   const uint64_t* __restrict__ tile_off,
-                                                  Ctrl* ctrl) {
+                                                  Ctrl* ctrl, uint32_t ntiles) {
     constexpr int kIt = kRelabelItems;
     __shared__ uint32_t s_wave[kBlock / kWave];
-    const uint32_t tile = blockIdx.x;
     const uint64_t pivot = *pivot_dev;
     const uint64_t nl_al = (ctrl->light + 3) & ~3ull;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t e0 = (int64_t)tile * (kBlock * kIt) + (int64_t)wave * (kWave * kIt) + lane;
-    const int64_t m = g.len;
-    int32_t a[kIt], b[kIt];
-    uint32_t w[kIt], idv[kIt];
-    uint64_t mk[kIt];
-    uint32_t cnt = 0;
-    bool bad = false;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t e0 = (int64_t)tile * (kBlock * kIt) + (int64_t)wave * (kWave * kIt) + lane;
+        const int64_t m = g.len;
+        int32_t a[kIt], b[kIt];
+        uint32_t w[kIt], idv[kIt];
+        uint64_t mk[kIt];
+        uint32_t cnt = 0;
+        bool bad = false;
 #pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        const int64_t e = e0 + k * kWave;
-        a[k] = b[k] = 0;
-        w[k] = idv[k] = 0;
-        bool lt = false;
-        if (e < m) {
-            a[k] = g.u[e];
-            b[k] = g.v[e];
-            w[k] = g.w[e];
-            idv[k] = MODE == kCompact ? g.id[e] : (uint32_t)e;
-            if (MODE == kOrig && ((uint32_t)a[k] >= (uint64_t)n || (uint32_t)b[k] >= (uint64_t)n)) {
-                bad = true;
-                a[k] = b[k] = 0;
+        for (int k = 0; k < kIt; ++k) {
+            const int64_t e = e0 + k * kWave;
+            a[k] = b[k] = 0;
+            w[k] = idv[k] = 0;
+            bool lt = false;
+            if (e < m) {
+                a[k] = g.u[e];
+                b[k] = g.v[e];
+                w[k] = g.w[e];
+                idv[k] = MODE == kCompact ? g.id[e] : (uint32_t)e;
+                if (MODE == kOrig && ((uint32_t)a[k] >= (uint64_t)n || (uint32_t)b[k] >= (uint64_t)n)) {
+                    bad = true;
+                    a[k] = b[k] = 0;
+                }
+                const uint64_t id = MODE == kCompact ? (uint64_t)idv[k] : (uint64_t)e;
+                lt = (((uint64_t)w[k] << 32) | id) <= pivot;
             }
-            const uint64_t id = MODE == kCompact ? (uint64_t)idv[k] : (uint64_t)e;
-            lt = (((uint64_t)w[k] << 32) | id) <= pivot;
+            mk[k] = __ballot(lt);
+            cnt += __popcll(mk[k]);
         }
-        mk[k] = __ballot(lt);
-        cnt += __popcll(mk[k]);
-    }
-    if (__ballot(bad) && lane == 0) atomicOr(&ctrl->err, kErrRange);
-    if (lane == 0) s_wave[wave] = cnt;
-    __syncthreads();
-    uint32_t woff = 0;
+        if (__ballot(bad) && lane == 0) atomicOr(&ctrl->err, kErrRange);
+        if (lane == 0) s_wave[wave] = cnt;
+        __syncthreads();
+        uint32_t woff = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i)
-        if (i < wave) woff += s_wave[i];
-    uint64_t off = tile_off[tile] + woff;
+        for (int i = 0; i < kBlock / kWave; ++i)
+            if (i < wave) woff += s_wave[i];
+        uint64_t off = tile_off[tile] + woff;
 #pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        const int64_t e = e0 + k * kWave;
-        if (e < m) {
-            const uint64_t before = off + lanes_below(mk[k]);   // light edges before e
-            const uint64_t o = ((mk[k] >> lane) & 1) ? before : nl_al + ((uint64_t)e - before);
-            out.u[o] = a[k];
-            out.v[o] = b[k];
-            out.w[o] = w[k];
-            out.id[o] = idv[k];
+        for (int k = 0; k < kIt; ++k) {
+            const int64_t e = e0 + k * kWave;
+            if (e < m) {
+                const uint64_t before = off + lanes_below(mk[k]);   // light edges before e
+                const uint64_t o = ((mk[k] >> lane) & 1) ? before : nl_al + ((uint64_t)e - before);
+                out.u[o] = a[k];
+                out.v[o] = b[k];
+                out.w[o] = w[k];
+                out.id[o] = idv[k];
+            }
+            off += __popcll(mk[k]);
         }
-        off += __popcll(mk[k]);
+        __syncthreads();                      // s_wave is reused by the next tile
     }
 }
 
@@ -433,35 +438,38 @@ __global__ __launch_bounds__(kBlock) void k_filter_flags(View g, const int32_t* 
                                                          const uint64_t* __restrict__ codes,
                                                          const Ctrl* ctrl,
                                                          uint64_t* __restrict__ flags,
-                                                         uint64_t* __restrict__ cnt) {
+                                                         uint64_t* __restrict__ cnt,
+                                                         uint32_t ntiles) {
     constexpr int kIt = kRelabelItems;
     __shared__ uint32_t s_wave[kBlock / kWave];
-    const uint32_t tile = blockIdx.x;
     const int32_t gi = ctrl->giant;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t w0 = (int64_t)tile * (kBlock * kIt / kWave) + wave * kIt;  // first flag word
-    const int64_t m = g.len;
-    int32_t a[kIt], b[kIt];
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t w0 = (int64_t)tile * (kBlock * kIt / kWave) + wave * kIt;  // first flag word
+        const int64_t m = g.len;
+        int32_t a[kIt], b[kIt];
 #pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        const int64_t e = (w0 + k) * kWave + lane;
-        a[k] = b[k] = 0;
-        if (e < m) { a[k] = g.u[e]; b[k] = g.v[e]; }
-    }
-    uint32_t c = 0;
+        for (int k = 0; k < kIt; ++k) {
+            const int64_t e = (w0 + k) * kWave + lane;
+            a[k] = b[k] = 0;
+            if (e < m) { a[k] = g.u[e]; b[k] = g.v[e]; }
+        }
+        uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        const bool keep = a[k] != b[k] && rep_of(codes, P, gi, a[k]) != rep_of(codes, P, gi, b[k]);
-        const uint64_t mk = __ballot(keep);
-        if (lane == 0) flags[w0 + k] = mk;
-        c += __popcll(mk);
-    }
-    if (lane == 0) s_wave[wave] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t sum = 0;
-        for (int i = 0; i < kBlock / kWave; ++i) sum += s_wave[i];
-        cnt[tile] = sum;
+        for (int k = 0; k < kIt; ++k) {
+            const bool keep = a[k] != b[k] && rep_of(codes, P, gi, a[k]) != rep_of(codes, P, gi, b[k]);
+            const uint64_t mk = __ballot(keep);
+            if (lane == 0) flags[w0 + k] = mk;
+            c += __popcll(mk);
+        }
+        if (lane == 0) s_wave[wave] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t sum = 0;
+            for (int i = 0; i < kBlock / kWave; ++i) sum += s_wave[i];
+            cnt[tile] = sum;
+        }
+        __syncthreads();                      // s_wave is reused by the next tile
     }
 }
 
@@ -472,39 +480,65 @@ __global__ __launch_bounds__(kBlock) void k_filter_scatter(View g, const int32_t
                                                            const Ctrl* ctrl,
                                                            const uint64_t* __restrict__ flags,
                                                            const uint64_t* __restrict__ tile_off,
-                                                           EdgeSoA out) {
+                                                           EdgeSoA out, uint32_t ntiles) {
     constexpr int kIt = kRelabelItems;
     __shared__ uint32_t s_wave[kBlock / kWave];
-    const uint32_t tile = blockIdx.x;
     const int32_t gi = ctrl->giant;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t w0 = (int64_t)tile * (kBlock * kIt / kWave) + wave * kIt;
     const int64_t words = (g.len + kWave - 1) / kWave;
-    uint64_t mk[kIt];
-    uint32_t c = 0;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t w0 = (int64_t)tile * (kBlock * kIt / kWave) + wave * kIt;
+        uint64_t mk[kIt];
+        uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        mk[k] = w0 + k < words ? flags[w0 + k] : 0;
-        c += __popcll(mk[k]);
-    }
-    if (lane == 0) s_wave[wave] = c;
-    __syncthreads();
-    uint32_t woff = 0;
-#pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i)
-        if (i < wave) woff += s_wave[i];
-    uint64_t off = tile_off[tile] + woff;
-#pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        if ((mk[k] >> lane) & 1) {
-            const int64_t e = (w0 + k) * kWave + lane;
-            const uint64_t o = off + lanes_below(mk[k]);
-            out.u[o] = rep_of(codes, P, gi, g.u[e]);
-            out.v[o] = rep_of(codes, P, gi, g.v[e]);
-            out.w[o] = g.w[e];
-            out.id[o] = g.id[e];
+        for (int k = 0; k < kIt; ++k) {
+            mk[k] = w0 + k < words ? flags[w0 + k] : 0;
+            c += __popcll(mk[k]);
         }
-        off += __popcll(mk[k]);
+        if (lane == 0) s_wave[wave] = c;
+        __syncthreads();
+        uint32_t woff = 0;
+#pragma unroll
+        for (int i = 0; i < kBlock / kWave; ++i)
+            if (i < wave) woff += s_wave[i];
+        const uint64_t off = tile_off[tile] + woff;
+        // all loads first, then the representative lookups, then the stores:
+        // the kept edges of a tile are scattered, so every step is a gather
+        // and the chains must overlap rather than run one after another
+        int32_t a[kIt], b[kIt];
+        uint32_t wt[kIt], id[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            a[k] = b[k] = 0;
+            wt[k] = id[k] = 0;
+            if ((mk[k] >> lane) & 1) {
+                const int64_t e = (w0 + k) * kWave + lane;
+                a[k] = g.u[e];
+                b[k] = g.v[e];
+                wt[k] = g.w[e];
+                id[k] = g.id[e];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            if ((mk[k] >> lane) & 1) {
+                a[k] = rep_of(codes, P, gi, a[k]);
+                b[k] = rep_of(codes, P, gi, b[k]);
+            }
+        }
+        uint64_t o = off;
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            if ((mk[k] >> lane) & 1) {
+                const uint64_t d = o + lanes_below(mk[k]);
+                out.u[d] = a[k];
+                out.v[d] = b[k];
+                out.w[d] = wt[k];
+                out.id[d] = id[k];
+            }
+            o += __popcll(mk[k]);
+        }
+        __syncthreads();                      // s_wave is reused by the next tile
     }
 }
 
@@ -548,12 +582,13 @@ void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_d
                   const uint64_t* tile_off, Ctrl* ctrl, hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
+    const unsigned grid = nt < kTileGrid ? nt : kTileGrid;
     if (in_mode == kOrig)
-        hipLaunchKernelGGL(k_split<kOrig>, dim3(nt), dim3(kBlock), 0, s, g, n, pivot_dev, out,
-                           tile_off, ctrl);
+        hipLaunchKernelGGL(k_split<kOrig>, dim3(grid), dim3(kBlock), 0, s, g, n, pivot_dev, out,
+                           tile_off, ctrl, nt);
     else
-        hipLaunchKernelGGL(k_split<kCompact>, dim3(nt), dim3(kBlock), 0, s, g, n, pivot_dev, out,
-                           tile_off, ctrl);
+        hipLaunchKernelGGL(k_split<kCompact>, dim3(grid), dim3(kBlock), 0, s, g, n, pivot_dev,
+                           out, tile_off, ctrl, nt);
 }
 
 void launch_rep_codes(const int32_t* P, int64_t n, uint64_t* codes, Ctrl* ctrl, hipStream_t s) {
@@ -569,11 +604,12 @@ void launch_filter(const View& g, const int32_t* P, const uint64_t* codes, const
                    uint64_t* flags, uint64_t* cnt, EdgeSoA out, uint64_t* kept, hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
-    hipLaunchKernelGGL(k_filter_flags, dim3(nt), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
-                       cnt);
+    const unsigned grid = nt < kTileGrid ? nt : kTileGrid;
+    hipLaunchKernelGGL(k_filter_flags, dim3(grid), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
+                       cnt, nt);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, cnt, nt, kept);
-    hipLaunchKernelGGL(k_filter_scatter, dim3(nt), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
-                       cnt, out);
+    hipLaunchKernelGGL(k_filter_scatter, dim3(grid), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
+                       cnt, out, nt);
 }
 
 // ------------------------------------------------------------------ driver
@@ -617,6 +653,7 @@ struct Ctx {
     float q_net;   // quantile the network chose at the top split (0 = not yet)
     uint64_t* codes;   // 2-bit representative codes of the vertices
     uint64_t* flags;   // keep flags of the heavy edges being filtered
+    bool filtered;     // a filter step has run (ctrl->giant is meaningful)
 };
 
 View view_of(const EdgeSoA& e, int64_t len) {
@@ -645,7 +682,10 @@ int compress_p(Ctx& C) {
 
 int base_case(Ctx& C, int mode, const View& g) {
     C.st->base_cases += 1;
-    return engine_solve(C.B, mode, g, C.n, C.mask, C.P, C.s, C.st);
+    // after a filter step the largest component's representative sits on most
+    // of the surviving edges
+    const int32_t hot = C.filtered ? host_ctrl()->giant : -1;
+    return engine_solve(C.B, mode, g, C.n, C.mask, C.P, C.s, C.st, hot);
 }
 
 // `where`: 0 / 1 = the graph lives at [0, len) of buffer X / Y, 2 = the
@@ -715,6 +755,7 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
     if ((st = compress_p(C))) return st;
     h = prof_begin(K_PMAINT, C.s);
     launch_rep_codes(C.P, C.n, C.codes, C.B.ctrl, C.s);
+    C.filtered = true;
     prof_end(h, C.s, 4.0 * C.n + C.n / 4.0);
     const int o = 1 - tgt;
     h = prof_begin(K_FILTER, C.s);
@@ -765,6 +806,7 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
     C.st = stats;
     C.splits = 0;
     C.q_net = 0.f;
+    C.filtered = false;
     C.sample = opt.sample_size > 0 ? opt.sample_size : 4096;
     C.min_split = opt.min_split_edges > 0 ? opt.min_split_edges : (1 << 20);
     C.sparse_deg = opt.sparse_degree > 0 ? opt.sparse_degree : 4;

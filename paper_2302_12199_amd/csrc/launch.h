@@ -11,7 +11,7 @@ void launch_zero_bytes(uint8_t* p, int64_t n, hipStream_t s);
 void launch_scan_prep(uint64_t* status, int64_t ntiles, Ctrl* ctrl, int round_begin,
                       hipStream_t s);
 void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
-                       int64_t n, uint64_t* best, Ctrl* ctrl, hipStream_t s);
+                       int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, hipStream_t s);
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
                  int32_t* parent, uint8_t* mask, Ctrl* ctrl, hipStream_t s);
 void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s);
