@@ -194,35 +194,49 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_pivot(View g, uint64_
 
 // Split counts, reduce-then-scan: the light-edge count (key <= pivot) of
 // every 2048-edge tile goes to cnt[tile]; k_scan_tiles turns the counts into
-// exclusive offsets, so the split pass needs no inter-tile waiting.
-template <int MODE>
+// exclusive offsets, so the split pass needs no inter-tile waiting.  One wave
+// per tile: lane l reads 4 consecutive edges at l*4 + j*256 (j < 8) with
+// 16-byte loads when the arrays allow it, so no workgroup barrier is needed.
+template <int MODE, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_count_tiles(View g,
                                                         const uint64_t* __restrict__ pivot_dev,
                                                         uint64_t* __restrict__ cnt,
                                                         uint32_t ntiles) {
-    __shared__ uint32_t s_wave[kBlock / kWave];
     const uint64_t pivot = *pivot_dev;
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t e0 = (int64_t)t * kRelabelTile + threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const uint32_t waves = gridDim.x * (kBlock / kWave);
+    for (uint32_t t = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; t < ntiles;
+         t += waves) {
+        const int64_t e0 = (int64_t)t * kRelabelTile;
         uint32_t c = 0;
+        if (VEC && e0 + kRelabelTile <= g.len) {
+            uint4 wv[kRelabelTile / 256], iv[kRelabelTile / 256];
 #pragma unroll
-        for (int k = 0; k < kRelabelItems; ++k) {
-            const int64_t e = e0 + k * kBlock;
-            if (e < g.len) {
+            for (int j = 0; j < kRelabelTile / 256; ++j) {
+                const int64_t q = (e0 + j * 256 + lane * 4) / 4;
+                wv[j] = reinterpret_cast<const uint4*>(g.w)[q];
+                iv[j] = MODE == kCompact ? reinterpret_cast<const uint4*>(g.id)[q]
+                                         : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < kRelabelTile / 256; ++j) {
+                const uint64_t e = (uint64_t)(e0 + j * 256 + lane * 4);
+                const uint32_t ws[4] = {wv[j].x, wv[j].y, wv[j].z, wv[j].w};
+                const uint32_t is[4] = {iv[j].x, iv[j].y, iv[j].z, iv[j].w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint64_t id = MODE == kCompact ? (uint64_t)is[i] : e + i;
+                    c += (((uint64_t)ws[i] << 32) | id) <= pivot;
+                }
+            }
+        } else {
+            for (int64_t e = e0 + lane; e < e0 + kRelabelTile && e < g.len; e += kWave) {
                 const uint64_t id = MODE == kCompact ? (uint64_t)g.id[e] : (uint64_t)e;
                 c += (((uint64_t)g.w[e] << 32) | id) <= pivot;
             }
         }
         for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-        if (lane == 0) s_wave[wave] = c;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t sum = 0;
-            for (int i = 0; i < kBlock / kWave; ++i) sum += s_wave[i];
-            cnt[t] = sum;
-        }
-        __syncthreads();
+        if (lane == 0) cnt[t] = c;
     }
 }
 
@@ -568,13 +582,24 @@ void launch_split_count(int in_mode, const View& g, const uint64_t* pivot_dev, u
                         Ctrl* ctrl, hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
-    const unsigned grid = nt < 8192u ? nt : 8192u;
-    if (in_mode == kOrig)
-        hipLaunchKernelGGL(k_count_tiles<kOrig>, dim3(grid), dim3(kBlock), 0, s, g, pivot_dev,
-                           cnt, nt);
-    else
-        hipLaunchKernelGGL(k_count_tiles<kCompact>, dim3(grid), dim3(kBlock), 0, s, g, pivot_dev,
-                           cnt, nt);
+    const unsigned per = kBlock / kWave;                   // tiles per workgroup step
+    const unsigned grid = (nt + per - 1) / per < 4096u ? (nt + per - 1) / per : 4096u;
+    const bool vec = ((((uintptr_t)g.w) | (in_mode == kOrig ? 0 : (uintptr_t)g.id)) & 15) == 0;
+    if (in_mode == kOrig) {
+        if (vec)
+            hipLaunchKernelGGL((k_count_tiles<kOrig, true>), dim3(grid), dim3(kBlock), 0, s, g,
+                               pivot_dev, cnt, nt);
+        else
+            hipLaunchKernelGGL((k_count_tiles<kOrig, false>), dim3(grid), dim3(kBlock), 0, s, g,
+                               pivot_dev, cnt, nt);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((k_count_tiles<kCompact, true>), dim3(grid), dim3(kBlock), 0, s,
+                               g, pivot_dev, cnt, nt);
+        else
+            hipLaunchKernelGGL((k_count_tiles<kCompact, false>), dim3(grid), dim3(kBlock), 0, s,
+                               g, pivot_dev, cnt, nt);
+    }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, cnt, nt, &ctrl->light);
 }
 
