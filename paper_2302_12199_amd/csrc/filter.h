@@ -17,7 +17,7 @@ uint64_t pivot_stream_base(uint64_t seed, uint32_t split);
 void launch_sample_pivot(int in_mode, const View& g, uint64_t base, int sample, float q,
                          const float* mlp, float comps, int depth, Ctrl* ctrl, hipStream_t s);
 void launch_split_count(int in_mode, const View& g, const uint64_t* pivot_dev, uint64_t* cnt,
-                        Ctrl* ctrl, hipStream_t s);
+                        uint64_t* bsum, Ctrl* ctrl, hipStream_t s);
 void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_dev, EdgeSoA out,
                   const uint64_t* tile_off, Ctrl* ctrl, hipStream_t s);
 void launch_iota(int32_t* p, int64_t n, hipStream_t s);

@@ -240,54 +240,86 @@ __global__ __launch_bounds__(kBlock) void k_count_tiles(View g,
     }
 }
 
-// Exclusive scan of cnt[0, ntiles) in place by one workgroup of
-// kScanThreads threads, 32 consecutive entries per thread per sweep; the
-// total goes to *total.
-constexpr int kScanThreads = 1024;
 // Workgroups of the tile kernels (split, filter): each loops over tiles, so a
 // launch is not dominated by dispatching one short workgroup per tile.
 constexpr unsigned kTileGrid = 4096;
-__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint64_t* __restrict__ cnt,
-                                                             uint32_t ntiles,
-                                                             uint64_t* __restrict__ total) {
-    constexpr int kPer = 32;
-    __shared__ uint64_t s_w[kScanThreads / kWave];
-    __shared__ uint64_t s_carry;
-    const int t = threadIdx.x, wave = t / kWave, lane = t % kWave;
-    if (t == 0) s_carry = 0;
-    __syncthreads();
-    for (uint64_t base = 0; base < ntiles; base += (uint64_t)kPer * kScanThreads) {
-        const uint64_t i0 = base + (uint64_t)t * kPer;
-        uint64_t c[kPer], sum = 0;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            c[k] = i0 + k < ntiles ? cnt[i0 + k] : 0;
-            sum += c[k];
-        }
-        uint64_t x = sum;   // inclusive scan over the wave
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint64_t y = __shfl_up(x, off, kWave);
-            if (lane >= off) x += y;
-        }
-        if (lane == kWave - 1) s_w[wave] = x;
-        __syncthreads();
-        uint64_t wpre = 0, tot = 0;
-        for (int i = 0; i < kScanThreads / kWave; ++i) {
-            const uint64_t v = s_w[i];
-            if (i < wave) wpre += v;
-            tot += v;
-        }
-        uint64_t run = s_carry + wpre + (x - sum);
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (i0 + k < ntiles) cnt[i0 + k] = run;
-            run += c[k];
-        }
-        __syncthreads();
-        if (t == 0) s_carry += tot;
-        __syncthreads();
+// Exclusive scan of the tile counts cnt[0, nt) in place, in three short
+// launches: per-chunk sums (kScanChunk counts per workgroup), one workgroup
+// scanning the <= kScanTop chunk sums (and writing the total), per-chunk
+// scans offset by their chunk's prefix.
+constexpr int kScanChunk = kBlock * 8;
+constexpr int kScanTop = 1024;     // chunk sums: nt <= 2^21 tiles covers m < 2^32
+
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t* s_w, uint64_t* total) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    uint64_t inc = x;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
     }
-    if (t == 0) *total = s_carry;
+    if (lane == kWave - 1) s_w[wave] = inc;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+    const int nw = blockDim.x / kWave;
+    for (int i = 0; i < nw; ++i) {
+        const uint64_t v = s_w[i];
+        if (i < wave) pre += v;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_up(const uint64_t* __restrict__ cnt, uint32_t nt,
+                                                    uint64_t* __restrict__ bsum) {
+    __shared__ uint64_t s_w[kBlock / kWave];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+    uint64_t x = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (i0 + k * kBlock < nt) x += cnt[i0 + k * kBlock];
+    uint64_t tot;
+    (void)block_excl_scan(x, s_w, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanTop) void k_scan_top(uint64_t* __restrict__ bsum, uint32_t nb,
+                                                       uint64_t* __restrict__ total) {
+    __shared__ uint64_t s_w[kScanTop / kWave];
+    const uint64_t x = threadIdx.x < nb ? bsum[threadIdx.x] : 0;
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan(x, s_w, &tot);
+    if (threadIdx.x < nb) bsum[threadIdx.x] = ex;
+    if (threadIdx.x == 0) *total = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(uint64_t* __restrict__ cnt, uint32_t nt,
+                                                      const uint64_t* __restrict__ bsum) {
+    __shared__ uint64_t s_w[kBlock / kWave];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * 8;
+    uint64_t c[8], x = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        c[k] = i0 + k < nt ? cnt[i0 + k] : 0;
+        x += c[k];
+    }
+    uint64_t tot;
+    uint64_t run = bsum[blockIdx.x] + block_excl_scan(x, s_w, &tot);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (i0 + k < nt) cnt[i0 + k] = run;
+        run += c[k];
+    }
+}
+
+// Exclusive scan of cnt[0, nt) in place; the sum goes to *total (device).
+void launch_scan_tiles(uint64_t* cnt, uint32_t nt, uint64_t* bsum, uint64_t* total,
+                       hipStream_t s) {
+    const uint32_t nb = (nt + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(k_scan_up, dim3(nb), dim3(kBlock), 0, s, cnt, nt, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTop), 0, s, bsum, nb, total);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, s, cnt, nt, bsum);
 }
 
 // Stable two-way split by key <= pivot: tile t writes its light edges from
@@ -579,7 +611,7 @@ void launch_sample_pivot(int in_mode, const View& g, uint64_t base, int sample, 
 }
 
 void launch_split_count(int in_mode, const View& g, const uint64_t* pivot_dev, uint64_t* cnt,
-                        Ctrl* ctrl, hipStream_t s) {
+                        uint64_t* bsum, Ctrl* ctrl, hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     const unsigned per = kBlock / kWave;                   // tiles per workgroup step
@@ -600,14 +632,14 @@ void launch_split_count(int in_mode, const View& g, const uint64_t* pivot_dev, u
             hipLaunchKernelGGL((k_count_tiles<kCompact, false>), dim3(grid), dim3(kBlock), 0, s,
                                g, pivot_dev, cnt, nt);
     }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, cnt, nt, &ctrl->light);
+    launch_scan_tiles(cnt, nt, bsum, &ctrl->light, s);
 }
 
 void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_dev, EdgeSoA out,
                   const uint64_t* tile_off, Ctrl* ctrl, hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
-    const unsigned grid = nt < kTileGrid ? nt : kTileGrid;
+    const unsigned grid = nt;             // one workgroup per tile measured fastest here
     if (in_mode == kOrig)
         hipLaunchKernelGGL(k_split<kOrig>, dim3(grid), dim3(kBlock), 0, s, g, n, pivot_dev, out,
                            tile_off, ctrl, nt);
@@ -626,13 +658,14 @@ void launch_rep_codes(const int32_t* P, int64_t n, uint64_t* codes, Ctrl* ctrl, 
 }
 
 void launch_filter(const View& g, const int32_t* P, const uint64_t* codes, const Ctrl* ctrl,
-                   uint64_t* flags, uint64_t* cnt, EdgeSoA out, uint64_t* kept, hipStream_t s) {
+                   uint64_t* flags, uint64_t* cnt, uint64_t* bsum, EdgeSoA out, uint64_t* kept,
+                   hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     const unsigned grid = nt < kTileGrid ? nt : kTileGrid;
     hipLaunchKernelGGL(k_filter_flags, dim3(grid), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
                        cnt, nt);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, cnt, nt, kept);
+    launch_scan_tiles(cnt, nt, bsum, kept, s);
     hipLaunchKernelGGL(k_filter_scatter, dim3(grid), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
                        cnt, out, nt);
 }
@@ -678,6 +711,7 @@ struct Ctx {
     float q_net;   // quantile the network chose at the top split (0 = not yet)
     uint64_t* codes;   // 2-bit representative codes of the vertices
     uint64_t* flags;   // keep flags of the heavy edges being filtered
+    uint64_t* bsum;    // chunk sums of the tile-count scans
     bool filtered;     // a filter step has run (ctrl->giant is meaningful)
 };
 
@@ -743,7 +777,7 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
     const int tgt = where == 0 ? 1 : 0;
     const EdgeSoA R = C.buf[tgt];
     h = prof_begin(K_PARTITION, C.s);
-    launch_split_count(mode, g, &C.B.ctrl->pivot, C.B.status, C.B.ctrl, C.s);
+    launch_split_count(mode, g, &C.B.ctrl->pivot, C.B.status, C.bsum, C.B.ctrl, C.s);
     launch_split(mode, g, C.n, &C.B.ctrl->pivot, R, C.B.status, C.B.ctrl, C.s);
     prof_end(h, C.s, (mode == kOrig ? 16.0 : 24.0) * g.len + 16.0 * g.len);
     HIP_TRY(hipGetLastError());
@@ -784,7 +818,7 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
     prof_end(h, C.s, 4.0 * C.n + C.n / 4.0);
     const int o = 1 - tgt;
     h = prof_begin(K_FILTER, C.s);
-    launch_filter(view_of(H, nh), C.P, C.codes, C.B.ctrl, C.flags, C.B.status, C.buf[o],
+    launch_filter(view_of(H, nh), C.P, C.codes, C.B.ctrl, C.flags, C.B.status, C.bsum, C.buf[o],
                   &C.B.ctrl->m_next, C.s);
     prof_end(h, C.s, 8.0 * nh);
     HIP_TRY(hipGetLastError());
@@ -808,7 +842,7 @@ size_t flags_bytes(int64_t m) {
 size_t filter_bytes(int64_t m, int64_t n, const msf_options& opt) {
     (void)opt;
     return engine_bytes(m, n) + align_up((size_t)(n > 0 ? n : 1) * 4) + 2 * buffer_bytes(m) +
-           codes_bytes(n) + flags_bytes(m);
+           codes_bytes(n) + flags_bytes(m) + align_up(kScanTop * 8);
 }
 
 int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,
@@ -824,6 +858,8 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
     C.codes = (uint64_t*)(ws + off);
     off += codes_bytes(n);
     C.flags = (uint64_t*)(ws + off);
+    off += flags_bytes(m);
+    C.bsum = (uint64_t*)(ws + off);
     C.n = n;
     C.mask = mask;
     C.s = s;
