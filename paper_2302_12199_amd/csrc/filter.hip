@@ -325,8 +325,10 @@ void launch_scan_tiles(uint64_t* cnt, uint32_t nt, uint64_t* bsum, uint64_t* tot
 // Stable two-way split by key <= pivot: tile t writes its light edges from
 // off[t] on and its heavy edges from nl' + (t * 2048 - off[t]) on, where
 // nl' = ctrl->light rounded up to a multiple of 4 (both parts start 16-byte
-// aligned).  On the caller's arrays the ids are validated.
-template <int MODE>
+// aligned).  LIGHT_ONLY writes the light part only (the heavy edges are then
+// read where they are, in the caller's arrays).  On the caller's arrays the
+// ids are validated.
+template <int MODE, bool LIGHT_ONLY>
 __global__ __launch_bounds__(kBlock) void k_split(View g, int64_t n,
                                                   const uint64_t* __restrict__ pivot_dev,
                                                   EdgeSoA out,
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_split(View g, int64_t n,
 #pragma unroll
         for (int k = 0; k < kIt; ++k) {
             const int64_t e = e0 + k * kWave;
-            if (e < m) {
+            if (e < m && (!LIGHT_ONLY || ((mk[k] >> lane) & 1))) {
                 const uint64_t before = off + lanes_below(mk[k]);   // light edges before e
                 const uint64_t o = ((mk[k] >> lane) & 1) ? before : nl_al + ((uint64_t)e - before);
                 out.u[o] = a[k];
@@ -479,10 +481,13 @@ __device__ __forceinline__ int32_t rep_of(const uint64_t* __restrict__ codes,
 // i covering edges [64i, 64i + 64)) and the kept count of every 2048-edge tile.
 // An edge is dropped when both ends have the same representative; the 2-bit
 // codes resolve most ends (largest component, own representative) without
-// reading P.
+// reading P.  ORIG: g is the caller's arrays, of which the heavy edges are
+// those with key (w << 32 | position) > pivot; otherwise every edge of g is
+// heavy.
+template <bool ORIG>
 __global__ __launch_bounds__(kBlock) void k_filter_flags(View g, const int32_t* __restrict__ P,
                                                          const uint64_t* __restrict__ codes,
-                                                         const Ctrl* ctrl,
+                                                         const Ctrl* ctrl, uint64_t pivot,
                                                          uint64_t* __restrict__ flags,
                                                          uint64_t* __restrict__ cnt,
                                                          uint32_t ntiles) {
@@ -499,6 +504,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_flags(View g, const int32_t* 
             const int64_t e = (w0 + k) * kWave + lane;
             a[k] = b[k] = 0;
             if (e < m) { a[k] = g.u[e]; b[k] = g.v[e]; }
+            if (ORIG && e < m && (((uint64_t)g.w[e] << 32) | (uint64_t)e) <= pivot)
+                b[k] = a[k];                  // light: already handled, never kept
         }
         uint32_t c = 0;
 #pragma unroll
@@ -521,6 +528,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_flags(View g, const int32_t* 
 
 // Filter, pass 2: the kept edges, relabelled (P[u], P[v]), in their order to
 // out[0, kept); tile t starts at off[t] (exclusive scan of the tile counts).
+// ORIG: ids are positions in the caller's arrays.
+template <bool ORIG>
 __global__ __launch_bounds__(kBlock) void k_filter_scatter(View g, const int32_t* __restrict__ P,
                                                            const uint64_t* __restrict__ codes,
                                                            const Ctrl* ctrl,
@@ -562,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_scatter(View g, const int32_t
                 a[k] = g.u[e];
                 b[k] = g.v[e];
                 wt[k] = g.w[e];
-                id[k] = g.id[e];
+                id[k] = ORIG ? (uint32_t)e : g.id[e];
             }
         }
 #pragma unroll
@@ -641,11 +650,11 @@ void launch_split(int in_mode, const View& g, int64_t n, const uint64_t* pivot_d
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     const unsigned grid = nt;             // one workgroup per tile measured fastest here
     if (in_mode == kOrig)
-        hipLaunchKernelGGL(k_split<kOrig>, dim3(grid), dim3(kBlock), 0, s, g, n, pivot_dev, out,
-                           tile_off, ctrl, nt);
+        hipLaunchKernelGGL((k_split<kOrig, true>), dim3(grid), dim3(kBlock), 0, s, g, n,
+                           pivot_dev, out, tile_off, ctrl, nt);
     else
-        hipLaunchKernelGGL(k_split<kCompact>, dim3(grid), dim3(kBlock), 0, s, g, n, pivot_dev,
-                           out, tile_off, ctrl, nt);
+        hipLaunchKernelGGL((k_split<kCompact, false>), dim3(grid), dim3(kBlock), 0, s, g, n,
+                           pivot_dev, out, tile_off, ctrl, nt);
 }
 
 void launch_rep_codes(const int32_t* P, int64_t n, uint64_t* codes, Ctrl* ctrl, hipStream_t s) {
@@ -657,17 +666,26 @@ void launch_rep_codes(const int32_t* P, int64_t n, uint64_t* codes, Ctrl* ctrl, 
     hipLaunchKernelGGL(k_rep_codes, dim3((unsigned)blocks), dim3(kBlock), 0, s, P, n, ctrl, codes);
 }
 
-void launch_filter(const View& g, const int32_t* P, const uint64_t* codes, const Ctrl* ctrl,
-                   uint64_t* flags, uint64_t* cnt, uint64_t* bsum, EdgeSoA out, uint64_t* kept,
-                   hipStream_t s) {
+// orig: g is the caller's arrays and its heavy edges are those above `pivot`.
+void launch_filter(const View& g, bool orig, uint64_t pivot, const int32_t* P,
+                   const uint64_t* codes, const Ctrl* ctrl, uint64_t* flags, uint64_t* cnt,
+                   uint64_t* bsum, EdgeSoA out, uint64_t* kept, hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     const unsigned grid = nt < kTileGrid ? nt : kTileGrid;
-    hipLaunchKernelGGL(k_filter_flags, dim3(grid), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
-                       cnt, nt);
+    if (orig)
+        hipLaunchKernelGGL(k_filter_flags<true>, dim3(grid), dim3(kBlock), 0, s, g, P, codes,
+                           ctrl, pivot, flags, cnt, nt);
+    else
+        hipLaunchKernelGGL(k_filter_flags<false>, dim3(grid), dim3(kBlock), 0, s, g, P, codes,
+                           ctrl, pivot, flags, cnt, nt);
     launch_scan_tiles(cnt, nt, bsum, kept, s);
-    hipLaunchKernelGGL(k_filter_scatter, dim3(grid), dim3(kBlock), 0, s, g, P, codes, ctrl, flags,
-                       cnt, out, nt);
+    if (orig)
+        hipLaunchKernelGGL(k_filter_scatter<true>, dim3(grid), dim3(kBlock), 0, s, g, P, codes,
+                           ctrl, flags, cnt, out, nt);
+    else
+        hipLaunchKernelGGL(k_filter_scatter<false>, dim3(grid), dim3(kBlock), 0, s, g, P, codes,
+                           ctrl, flags, cnt, out, nt);
 }
 
 // ------------------------------------------------------------------ driver
@@ -779,7 +797,9 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
     h = prof_begin(K_PARTITION, C.s);
     launch_split_count(mode, g, &C.B.ctrl->pivot, C.B.status, C.bsum, C.B.ctrl, C.s);
     launch_split(mode, g, C.n, &C.B.ctrl->pivot, R, C.B.status, C.B.ctrl, C.s);
-    prof_end(h, C.s, (mode == kOrig ? 16.0 : 24.0) * g.len + 16.0 * g.len);
+    // count + split reads (4 + 12 B per edge on the caller's arrays, 8 + 16 B on
+    // a buffer) and writes: everything on a buffer, the light part only on top
+    prof_end(h, C.s, mode == kOrig ? 16.0 * g.len : 40.0 * g.len);
     HIP_TRY(hipGetLastError());
     if ((st = read_ctrl(C.B.ctrl, hc, C.s))) return st;
     if (hc->err & kErrRange) return MSF_ERANGE;
@@ -788,6 +808,7 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
         return MSF_EINTERNAL;
     }
     const int64_t nl = (int64_t)hc->light, nh = g.len - nl;
+    if (mode == kOrig) prof_add(K_PARTITION, 16.0 * nl);
     if (split < MSF_MAX_TRACE) {
         C.st->split_edges[split] = (uint64_t)g.len;
         C.st->split_pivot[split] = hc->pivot;
@@ -803,9 +824,19 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
     C.st->levels += 1;
     if (nl == 0 || nh == 0) return base_case(C, mode, g);   // degenerate pivot
 
-    EdgeSoA H = R;
-    const int64_t nl_al = (nl + 3) & ~(int64_t)3;
-    H.u += nl_al; H.v += nl_al; H.w += nl_al; H.id += nl_al;
+    // Heavy part: right after the light part in R, or (top level) the
+    // caller's arrays themselves, where the split wrote nothing heavy.
+    const bool heavy_in_place = mode == kOrig;
+    const uint64_t pivot = hc->pivot;
+    View Hv;
+    if (heavy_in_place) {
+        Hv = g;
+    } else {
+        EdgeSoA H = R;
+        const int64_t nl_al = (nl + 3) & ~(int64_t)3;
+        H.u += nl_al; H.v += nl_al; H.w += nl_al; H.id += nl_al;
+        Hv = view_of(H, nh);
+    }
     if ((st = rec_filter(C, kCompact, view_of(R, nl), tgt, depth + 1))) return st;
 
     // Filter: drop heavy edges inside a light component; the rest, relabelled
@@ -818,9 +849,9 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
     prof_end(h, C.s, 4.0 * C.n + C.n / 4.0);
     const int o = 1 - tgt;
     h = prof_begin(K_FILTER, C.s);
-    launch_filter(view_of(H, nh), C.P, C.codes, C.B.ctrl, C.flags, C.B.status, C.bsum, C.buf[o],
-                  &C.B.ctrl->m_next, C.s);
-    prof_end(h, C.s, 8.0 * nh);
+    launch_filter(Hv, heavy_in_place, pivot, C.P, C.codes, C.B.ctrl, C.flags, C.B.status,
+                  C.bsum, C.buf[o], &C.B.ctrl->m_next, C.s);
+    prof_end(h, C.s, heavy_in_place ? 12.0 * g.len : 8.0 * nh);
     HIP_TRY(hipGetLastError());
     if ((st = read_ctrl(C.B.ctrl, hc, C.s))) return st;
     const int64_t kept = (int64_t)hc->m_next;
