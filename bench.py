@@ -154,6 +154,8 @@ def main():
     ap.add_argument("--pivot", default="median")
     ap.add_argument("--quantile", type=float, default=0.5)
     ap.add_argument("--model", default=None, help="pivot network file (--pivot mlp)")
+    ap.add_argument("--no-alternative", action="store_true",
+                    help="with --algo boruvka: skip timing Filter-Borůvka on the same graph")
     ap.add_argument("--no-pivot-compare", action="store_true",
                     help="with --pivot mlp: skip the timed median-pivot comparison")
     ap.add_argument("--cpu-sample", type=int, default=1 << 27,
@@ -265,6 +267,29 @@ def main():
                    "GBps": round(x["bytes"] / (x["ms"] / 1000.0) / 1e9, 1) if x["ms"] > 0 else None}
                for k, x in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
 
+    alt = None
+    if args.algo == "boruvka" and not args.no_alternative:
+        # the same graph through Filter-Borůvka with the shipped pivot network
+        # (reported beside the configured plain Borůvka, not as the value)
+        msf.load_pivot_model()
+        fopts = dict(algo="filter", pivot="mlp")
+        fws = torch.empty(msf.workspace_bytes(m, n, **fopts), dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup):
+            msf.compute(tu, tv, tw, n, workspace=fws, mask_out=mask, **fopts)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            _, ftotal, fst = msf.compute(tu, tv, tw, n, workspace=fws, mask_out=mask, **fopts)
+        torch.cuda.synchronize()
+        fms = (time.perf_counter() - t2) * 1000.0 / args.steps
+        msf.clear_pivot_model()
+        del fws
+        if ftotal != total:
+            raise RuntimeError("Filter-Borůvka gave a different total")
+        alt = {"algo": "filter", "pivot": "mlp", "network_q": fst["pivot_q_used"],
+               "ms_per_step": round(fms, 4), "edges_per_s": m / (fms / 1000.0)}
+        log(f"filter + pivot network: {fms:.3f} ms/step (q={fst['pivot_q_used']:.3f})")
+
     cpu = None
     if args.cpu_sample > 0:
         cpu = cpu_baseline(u, v, w, n, args.cpu_sample)
@@ -278,6 +303,7 @@ def main():
         "config": {"workload": args.workload, "n": int(n), "m": int(m), "algo": args.algo,
                    "pivot": args.pivot if args.algo == "filter" else None},
         "roofline": roofline, "cpu_baseline": cpu, "pivot_vs_median": pivot_cmp,
+        "same_graph_filter_boruvka": alt,
         "detail": {"rounds": stats["rounds"], "round_live": stats["round_live"],
                    "round_edges": stats["round_edges"], "msf_edges": stats["msf_edges"],
                    "total_weight": stats["total_weight"], "kernels": kernels},

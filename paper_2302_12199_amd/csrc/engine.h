@@ -19,8 +19,8 @@ struct EngineBuffers {
     uint32_t* p16;        // kFull16 layout
     EdgeSoA cbuf[2];      // kCompact layouts (alternating)
     uint64_t* pairs;      // tail: lightest edge per vertex pair (triangular table)
-    uint32_t* list_xy;    // tail: compacted pair list
-    uint64_t* list_key;
+    uint32_t* list_xy[2];  // tail: pair list (ping-pong, compacted every round)
+    uint64_t* list_key[2];
     int64_t ncap, mcap;
 };
 

@@ -61,8 +61,10 @@ size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B) {
     }
     const size_t slots = (size_t)kTailMax * (kTailMax - 1) / 2;
     b.pairs = (uint64_t*)take(slots * 8);
-    b.list_xy = (uint32_t*)take(slots * 4);
-    b.list_key = (uint64_t*)take(slots * 8);
+    for (int i = 0; i < 2; ++i) {
+        b.list_xy[i] = (uint32_t*)take(slots * 4);
+        b.list_key[i] = (uint64_t*)take(slots * 8);
+    }
     b.ncap = n;
     b.mcap = m;
     if (B) *B = b;

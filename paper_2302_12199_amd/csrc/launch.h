@@ -25,9 +25,9 @@ bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t 
                  int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
                  Ctrl* ctrl, hipStream_t s);
 // tail.hip
-void launch_tail(const uint64_t* pairs, int64_t nn, uint32_t* list_xy, uint64_t* list_key,
-                 const uint32_t* view_id, uint8_t* mask, const int32_t* orig_in, int32_t* rep,
-                 Ctrl* ctrl, hipStream_t s);
+void launch_tail(const uint64_t* pairs, int64_t nn, uint32_t* const list_xy[2],
+                 uint64_t* const list_key[2], const uint32_t* view_id, uint8_t* mask,
+                 const int32_t* orig_in, int32_t* rep, Ctrl* ctrl, hipStream_t s);
 void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_t* label,
                        int64_t nr, const int32_t* orig_cur, int32_t* orig_next, int32_t* rep,
                        hipStream_t s);

@@ -11,64 +11,66 @@
 
 namespace msf {
 
-// Slot of the unordered pair {x, y}, x < y, in a triangular table.
-__device__ __forceinline__ void slot_pair(int64_t s, int32_t& x, int32_t& y) {
-    // y = largest integer with y (y - 1) / 2 <= s
-    int64_t yy = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)s)) * 0.5);
-    while (yy * (yy - 1) / 2 > s) --yy;
-    while ((yy + 1) * yy / 2 <= s) ++yy;
-    y = (int32_t)yy;
-    x = (int32_t)(s - yy * (yy - 1) / 2);
-}
-
 __global__ __launch_bounds__(kTailThreads) void k_tail(
-    const uint64_t* __restrict__ pairs, int64_t nn, uint32_t* __restrict__ list_xy,
-    uint64_t* __restrict__ list_key, const uint32_t* __restrict__ view_id,
+    const uint64_t* __restrict__ pairs, int64_t nn, uint32_t* list_xy0, uint64_t* list_key0,
+    uint32_t* list_xy1, uint64_t* list_key1, const uint32_t* __restrict__ view_id,
     uint8_t* __restrict__ mask, const int32_t* __restrict__ orig_in, int32_t* __restrict__ rep,
     Ctrl* ctrl) {
+    uint32_t* list_xy = list_xy0;
+    uint64_t* list_key = list_key0;
+    // The list always holds pairs of current component roots: it is rebuilt
+    // after every round with both ends mapped through the hook forest, and
+    // pairs that fell inside one component are dropped.
     __shared__ uint64_t best[kTailMax];
-    __shared__ int32_t comp[kTailMax];   // representative of each tail vertex's component
     __shared__ int32_t arg[kTailMax];    // list index of best[]
     __shared__ int32_t par[kTailMax];
-    __shared__ uint32_t s_cnt, s_live, s_found, s_scan;
+    __shared__ uint32_t s_cnt, s_live, s_found;
     const int tid = threadIdx.x;
-    const int64_t nslots = nn * (nn - 1) / 2;
     if (tid == 0) s_cnt = 0;
-    for (int v = tid; v < nn; v += blockDim.x) comp[v] = v;
     __syncthreads();
-    for (int64_t s = tid; s < nslots; s += blockDim.x) {
-        const uint64_t k = pairs[s];
-        if (k == kKeyMax) continue;
-        int32_t x, y;
-        slot_pair(s, x, y);
-        const uint32_t i = atomicAdd(&s_cnt, 1u);
-        list_xy[i] = (uint32_t)x | ((uint32_t)y << 16);
-        list_key[i] = k;
+    // List of the occupied slots: wave w walks rows y = w, w + 16, ... of the
+    // triangle (slots y(y-1)/2 + x, x < y), 64 columns at a time, and appends
+    // with one LDS atomic per step of the wave.
+    {
+        const int wave = tid / kWave, lane = tid % kWave;
+        for (int64_t y = 1 + wave; y < nn; y += kTailThreads / kWave) {
+            const int64_t row = y * (y - 1) / 2;
+            for (int64_t x0 = 0; x0 < y; x0 += kWave) {
+                const int64_t x = x0 + lane;
+                const uint64_t k = x < y ? pairs[row + x] : kKeyMax;
+                const uint64_t occ = __ballot(k != kKeyMax);
+                if (occ == 0) continue;
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(occ));
+                base = __shfl(base, 0, kWave);
+                if (k != kKeyMax) {
+                    const uint32_t i = base + lanes_below(occ);
+                    list_xy[i] = (uint32_t)x | ((uint32_t)y << 16);
+                    list_key[i] = k;
+                }
+            }
+        }
     }
     __syncthreads();
-    const uint32_t L = s_cnt;
+    uint32_t L = s_cnt;
+    const uint32_t L0 = L;
     uint64_t wsum = 0, nfound = 0;
     int round = 0;
     for (; round < kTailRoundsMax; ++round) {
         for (int v = tid; v < nn; v += blockDim.x) best[v] = kKeyMax;
-        if (tid == 0) { s_live = 0; s_found = 0; s_scan = 0; }
+        if (tid == 0) { s_live = 0; s_found = 0; }
         __syncthreads();
-        uint32_t scanned = 0;
         for (uint32_t i = tid; i < L; i += blockDim.x) {          // lightest edges
             const uint32_t xy = list_xy[i];
-            const int32_t x = comp[xy & 0xffff], y = comp[xy >> 16];
-            if (x == y) continue;
-            ++scanned;
+            const int32_t x = xy & 0xffff, y = xy >> 16;
             const uint64_t k = list_key[i];
             atomic_min_key(&best[x], k);
             atomic_min_key(&best[y], k);
         }
-        if (scanned) atomicAdd(&s_scan, scanned);
         __syncthreads();
         for (uint32_t i = tid; i < L; i += blockDim.x) {          // which entry won
             const uint32_t xy = list_xy[i];
-            const int32_t x = comp[xy & 0xffff], y = comp[xy >> 16];
-            if (x == y) continue;
+            const int32_t x = xy & 0xffff, y = xy >> 16;
             const uint64_t k = list_key[i];
             if (best[x] == k) arg[x] = (int32_t)i;
             if (best[y] == k) arg[y] = (int32_t)i;
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(
             if (b == kKeyMax) { par[v] = v; continue; }
             ++live;
             const uint32_t xy = list_xy[arg[v]];
-            const int32_t x = comp[xy & 0xffff], y = comp[xy >> 16];
+            const int32_t x = xy & 0xffff, y = xy >> 16;
             const int32_t other = x == v ? y : x;
             if (best[other] == b && v < other) {
                 par[v] = v;
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(
         if (tid == 0) {
             ctrl->tail_live[round] = s_live;
             ctrl->tail_found[round] = s_found;
-            ctrl->tail_scan[round] = s_scan;
+            ctrl->tail_scan[round] = L;
         }
         nfound += found;
         for (int it = 0; it < 11; ++it) {                         // pointer doubling
@@ -117,8 +119,38 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(
                     rep[orig_in ? orig_in[v] : v] = orig_in ? orig_in[par[v]] : par[v];
             }
         }
-        for (int v = tid; v < nn; v += blockDim.x) comp[v] = par[comp[v]];
+        if (tid == 0) s_cnt = 0;
         __syncthreads();
+        // Next round's list, in the other buffer: both ends mapped to their
+        // new roots, pairs inside one component dropped.
+        {
+            uint32_t* xy_out = list_xy == list_xy0 ? list_xy1 : list_xy0;
+            uint64_t* key_out = list_key == list_key0 ? list_key1 : list_key0;
+            const int wave = tid / kWave, lane = tid % kWave;
+            for (uint32_t i0 = (uint32_t)wave * kWave; i0 < L; i0 += kTailThreads) {
+                const uint32_t i = i0 + lane;
+                int32_t x = 0, y = 0;
+                if (i < L) {
+                    const uint32_t xy = list_xy[i];
+                    x = par[xy & 0xffff];
+                    y = par[xy >> 16];
+                }
+                const uint64_t live = __ballot(i < L && x != y);
+                if (live == 0) continue;
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(live));
+                base = __shfl(base, 0, kWave);
+                if ((live >> lane) & 1) {
+                    const uint32_t j = base + lanes_below(live);
+                    xy_out[j] = (uint32_t)x | ((uint32_t)y << 16);
+                    key_out[j] = list_key[i];
+                }
+            }
+            list_xy = xy_out;
+            list_key = key_out;
+        }
+        __syncthreads();
+        L = s_cnt;
     }
     wsum = wave_sum_u64(wsum);
     nfound = wave_sum_u64(nfound);
@@ -128,16 +160,16 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(
     }
     if (tid == 0) {
         ctrl->tail_rounds = (uint32_t)round;
-        ctrl->tail_edges = L;
+        ctrl->tail_edges = L0;
         if (round == kTailRoundsMax) atomicOr(&ctrl->err, kErrInternal);
     }
 }
 
-void launch_tail(const uint64_t* pairs, int64_t nn, uint32_t* list_xy, uint64_t* list_key,
-                 const uint32_t* view_id, uint8_t* mask, const int32_t* orig_in, int32_t* rep,
-                 Ctrl* ctrl, hipStream_t s) {
-    hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), 0, s, pairs, nn, list_xy, list_key,
-                       view_id, mask, orig_in, rep, ctrl);
+void launch_tail(const uint64_t* pairs, int64_t nn, uint32_t* const list_xy[2],
+                 uint64_t* const list_key[2], const uint32_t* view_id, uint8_t* mask,
+                 const int32_t* orig_in, int32_t* rep, Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), 0, s, pairs, nn, list_xy[0],
+                       list_key[0], list_xy[1], list_key[1], view_id, mask, orig_in, rep, ctrl);
 }
 
 }  // namespace msf
