@@ -59,6 +59,19 @@ typedef enum {
                                 falls back to the median when none is loaded */
 } msf_pivot;
 
+/* How round 0 runs when the graph is the caller's edge list (Sec. II-C's
+ * lightest-edge search and relabelling):
+ *   MSF_ROUND0_AUTO     by vertex buckets where the graph qualifies (2^21 <= n <= 2^24,
+ *                       2^22 <= m < 2^31) and, in a sample of 4096 edges, at most half
+ *                       join ids less than 2^14 apart; else on the edge list;
+ *   MSF_ROUND0_EDGES    on the edge list, with random accesses into n-sized tables
+ *                       (the workspace then holds no bucket buffers);
+ *   MSF_ROUND0_BUCKETS  by vertex buckets wherever the graph qualifies.
+ * By buckets, the edges are split once into per-endpoint arcs grouped by 2^14-vertex
+ * buckets; the minimum and the relabelling then work on one bucket's vertices in LDS.
+ * It costs msf_workspace_bytes about 24 extra bytes per edge. */
+typedef enum { MSF_ROUND0_AUTO = 0, MSF_ROUND0_EDGES = 1, MSF_ROUND0_BUCKETS = 2 } msf_round0;
+
 /* Options; a NULL pointer means {MSF_ALGO_BORUVKA, MSF_PIVOT_MEDIAN, 0.5, seed 1,
  * defaults}.  Every field only changes running time, never the result. */
 typedef struct msf_options {
@@ -69,7 +82,8 @@ typedef struct msf_options {
     uint64_t seed;           /* seed of the pivot sampler's counter-based generator */
     int32_t sparse_degree;   /* filter isSparse: stop splitting when 2m'/n' <= this; 0 = 4 */
     int32_t min_split_edges; /* filter isSparse: stop splitting below this many edges; 0 = 2^20 */
-    int32_t reserved[8];     /* must be zero */
+    int32_t round0;          /* msf_round0: how round 0 on the caller's arrays is organised */
+    int32_t reserved[7];     /* must be zero */
 } msf_options;
 
 #define MSF_MAX_TRACE 64

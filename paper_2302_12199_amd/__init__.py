@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libmsf.so")
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EWORKSPACE, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 ALGOS = {"boruvka": 0, "filter": 1}
 PIVOTS = {"median": 0, "quantile": 1, "mlp": 2}
+ROUND0 = {"auto": 0, "edges": 1, "buckets": 2}
 MAX_TRACE = 64
 
 
@@ -28,7 +29,8 @@ class Options(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("pivot", ctypes.c_int32),
                 ("quantile", ctypes.c_float), ("sample_size", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("sparse_degree", ctypes.c_int32),
-                ("min_split_edges", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("min_split_edges", ctypes.c_int32), ("round0", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 class Stats(ctypes.Structure):
@@ -137,8 +139,9 @@ def library():
 
 
 def make_options(algo="boruvka", pivot="median", quantile=0.5, seed=1, sample_size=0,
-                 sparse_degree=0, min_split_edges=0):
+                 sparse_degree=0, min_split_edges=0, round0="auto"):
     o = Options()
+    o.round0 = ROUND0[round0] if isinstance(round0, str) else int(round0)
     o.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
     o.pivot = PIVOTS[pivot] if isinstance(pivot, str) else int(pivot)
     o.quantile = float(quantile)

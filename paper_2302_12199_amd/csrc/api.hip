@@ -29,7 +29,7 @@ namespace {
 const char* const kKernelNames[K_COUNT] = {
     "minedge_r0", "hook", "jump", "scan_roots", "label", "pass", "compact", "compose",
     "fill", "scan_prep", "sample", "partition", "filter", "rep_maint", "mlp", "batch", "tail",
-    "pass_r0"};
+    "pass_r0", "bucket_index", "bucket_scatter", "bucket_min", "bucket_label", "bucket_pass"};
 
 struct Profiler {
     std::mutex mu;
@@ -125,13 +125,15 @@ int check_args(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
         if (!(opt->quantile >= 0.0f && opt->quantile <= 1.0f)) return MSF_EINVAL;
         if (opt->sample_size < 0 || opt->sample_size > 8192) return MSF_EINVAL;
         if (opt->sparse_degree < 0 || opt->min_split_edges < 0) return MSF_EINVAL;
-        for (int i = 0; i < 8; ++i)
+        if (opt->round0 < MSF_ROUND0_AUTO || opt->round0 > MSF_ROUND0_BUCKETS) return MSF_EINVAL;
+        for (int i = 0; i < 7; ++i)
             if (opt->reserved[i]) return MSF_EINVAL;
     }
     return MSF_OK;
 }
 
 bool use_filter(const msf_options* opt) { return opt && opt->algo == MSF_ALGO_FILTER; }
+bool round0_buckets(const msf_options* opt) { return !opt || opt->round0 != MSF_ROUND0_EDGES; }
 
 int solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,
           uint8_t* mask, uint64_t* total_out, char* ws, hipStream_t s, const msf_options* opt,
@@ -147,7 +149,8 @@ int solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int6
         rc = filter_solve(u, v, w, m, n, mask, ws, s, *opt, st);
     } else {
         EngineBuffers B;
-        engine_carve(ws, m, n, &B);
+        engine_carve(ws, m, n, &B, round0_buckets(opt));
+        B.round0 = opt ? opt->round0 : MSF_ROUND0_AUTO;
         HIP_TRY(hipMemsetAsync(B.ctrl, 0, sizeof(Ctrl), s));
         int h = prof_begin(K_FILL, s);
         launch_zero_bytes(mask, m, s);
@@ -171,7 +174,7 @@ extern "C" {
 
 size_t msf_workspace_bytes(int64_t m, int64_t n, const msf_options* opt) {
     if (m < 0 || n < 0) return 0;
-    return use_filter(opt) ? filter_bytes(m, n, *opt) : engine_bytes(m, n);
+    return use_filter(opt) ? filter_bytes(m, n, *opt) : engine_bytes(m, n, round0_buckets(opt));
 }
 
 int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,

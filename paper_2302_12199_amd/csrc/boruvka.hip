@@ -358,34 +358,6 @@ __device__ __forceinline__ void load_group(const View& g, int64_t q, int64_t m, 
     }
 }
 
-template <int OUT>
-__device__ __forceinline__ void store_group(int64_t q, int64_t m, const int32_t (&ra)[4],
-                                            const int32_t (&rb)[4], int32_t* __restrict__ ou,
-                                            int32_t* __restrict__ ov,
-                                            uint32_t* __restrict__ op16) {
-    const int64_t e0 = q * 4;
-    const bool full = e0 + 3 < m;
-    if constexpr (OUT == kOut32) {
-        if (full) {
-            reinterpret_cast<int4*>(ou)[q] = make_int4(ra[0], ra[1], ra[2], ra[3]);
-            reinterpret_cast<int4*>(ov)[q] = make_int4(rb[0], rb[1], rb[2], rb[3]);
-        } else {
-            for (int k = 0; k < 4; ++k)
-                if (e0 + k < m) { ou[e0 + k] = ra[k]; ov[e0 + k] = rb[k]; }
-        }
-    } else if constexpr (OUT == kOut16) {
-        uint32_t pk[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) pk[k] = (uint32_t)ra[k] | ((uint32_t)rb[k] << 16);
-        if (full) {
-            reinterpret_cast<uint4*>(op16)[q] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-        } else {
-            for (int k = 0; k < 4; ++k)
-                if (e0 + k < m) op16[e0 + k] = pk[k];
-        }
-    }
-}
-
 // Relabel + next-round minedge over every position of the view, keeping the
 // positions.  Each lane handles kPassGroups groups of 4 consecutive positions
 // per step (16-byte vector loads, all issued before any is consumed).  The
@@ -417,9 +389,31 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
     const int64_t m = g.len;
     const int64_t groups = (m + 3) / 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // Skewed graphs leave a few huge components whose entries every lane
+    // would update: the label most frequent among 64 sampled edges of this
+    // workgroup's first positions (if it holds at least 1/8 of them) has its
+    // minimum taken in LDS and merged once.  (PAIR has no per-vertex minimum.)
+    __shared__ int32_t s_hot[kHot];
+    __shared__ unsigned long long s_hotmin[kHot];
+    if (!PAIR && threadIdx.x < kWave) {
+        const int64_t p = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x * (blockDim.x / kWave)) * 4;
+        int32_t lab = -1;
+        if (p < m) {
+            int32_t a0, b0;
+            load_ends<IN>(g, p, a0, b0);
+            if (a0 != b0) lab = map[a0];
+        }
+        hot_labels(lab, s_hot, s_hotmin);
+    }
+    __syncthreads();
+    int32_t hot[kHot];
+#pragma unroll
+    for (int h = 0; h < kHot; ++h) hot[h] = PAIR ? -1 : s_hot[h];
     uint32_t kept = 0;
-    for (int64_t q0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q0 < groups;
-         q0 += stride * G) {
+    // the loop bound is uniform per wave (wave_min_update needs whole waves)
+    for (int64_t qw = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1));
+         qw < groups; qw += stride * G) {
+        const int64_t q0 = qw + (threadIdx.x & (kWave - 1));
         int32_t a[G][4], b[G][4];
         uint32_t w[G][4];
 #pragma unroll
@@ -439,28 +433,44 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 ra[k] = rb[k] = 0;
-                if (a[j][k] != b[j][k]) {     // equal stored labels stay a self-loop
+                bool act = false;
+                uint64_t key = kKeyMax;
+                if (q < groups && a[j][k] != b[j][k]) {   // equal stored labels stay a self-loop
                     const int32_t x = map[a[j][k]], y = map[b[j][k]];
                     if (x != y) {
                         ra[k] = x;
                         rb[k] = y;
                         ++kept;
-                        const uint64_t key = ((uint64_t)w[j][k] << 32) | (uint64_t)(q * 4 + k);
+                        act = true;
+                        key = ((uint64_t)w[j][k] << 32) | (uint64_t)(q * 4 + k);
                         if constexpr (PAIR) {   // lightest edge per vertex pair, for the tail
                             const int64_t lo = x < y ? x : y, hi = x < y ? y : x;
                             atomic_min_key(&pairs[hi * (hi - 1) / 2 + lo], key);
-                        } else {
-                            atomic_min_key(&bst[x], key);
-                            atomic_min_key(&bst[y], key);
                         }
                     }
+                }
+                if constexpr (!PAIR) {
+                    const bool hx = act && hot_min(hot, s_hotmin, ra[k], key);
+                    const bool hy = act && hot_min(hot, s_hotmin, rb[k], key);
+                    wave_min_update(bst, ra[k], key, act && !hx);
+                    wave_min_update(bst, rb[k], key, act && !hy);
                 }
             }
             if (q < groups) store_group<OUT>(q, m, ra, rb, ou, ov, op16);
         }
     }
-    const uint64_t wk = wave_sum_u64(kept);
-    if (lane_id() == 0 && wk) atomicAdd((unsigned long long*)&ctrl->m_next, (unsigned long long)wk);
+    {   // one counter atomic per workgroup (same-address atomics queue)
+        __shared__ uint64_t s_kept[kPassBlock / kWave];
+        uint64_t tot;
+        (void)block_excl_scan(kept, s_kept, &tot);
+        if (threadIdx.x == 0 && tot)
+            atomicAdd((unsigned long long*)&ctrl->m_next, (unsigned long long)tot);
+    }
+    if constexpr (!PAIR) {
+        __syncthreads();
+        if (threadIdx.x < kHot && hot[threadIdx.x] >= 0 && s_hotmin[threadIdx.x] != kKeyMax)
+            atomic_min_key(&bst[hot[threadIdx.x]], s_hotmin[threadIdx.x]);
+    }
     if constexpr (LDS_B) {
         __syncthreads();
         for (int64_t i = threadIdx.x; i < nn; i += blockDim.x) {

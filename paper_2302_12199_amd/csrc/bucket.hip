@@ -1,0 +1,569 @@
+// Round 0 of Borůvka by vertex buckets (paper Sec. II-C: the lightest
+// incident edge of every vertex, then the relabelling of every edge).
+//
+// Done directly on the caller's edge list, both steps touch an n-sized table
+// at two random places per edge.  With no locality in the vertex ids (RMAT
+// with permuted ids) every touch is a separate 128-byte line request to HBM,
+// and the min updates are device-scope atomics that do not stay in the XCD's
+// L2.  Here every random access goes to LDS instead, and global memory is
+// only streamed or read in runs:
+//
+//   scatter  one workgroup per tile of 2^13 edges: the tile's arcs (one per
+//            endpoint) are sorted by vertex bucket (2^14 vertices) in LDS and
+//            written as one contiguous block; meta[t][b] = (run start, length)
+//   index    meta transposed to bucket-major; bucket totals; their scan
+//   min      one workgroup per bucket: its runs (one per tile) are read 1024
+//            runs at a time, each arc's lane found by a binary search over the
+//            batch's run prefix; the minimum key per vertex is kept in LDS.
+//            It also writes the arcs' vertex indices as one bucket-major
+//            stream and where each run starts in it
+//   label    (after hook / jump / root scan) one workgroup per bucket: the
+//            bucket's labels in LDS, the index stream in, the labels out
+//   pass     one workgroup per tile: its runs of labels are gathered into LDS
+//            in tile-block order; each edge reads its two labels there, and
+//            the pass writes the relabelled layout and runs the next round's
+//            lightest-edge search
+#include <algorithm>
+
+#include "bucket.h"
+#include "host.h"
+#include "prim.h"
+
+namespace msf {
+
+size_t scan_levels_bytes(int64_t n);
+void launch_scan_u64(uint64_t* cnt, int64_t n, uint64_t* tmp, uint64_t* total, hipStream_t s);
+
+namespace {
+
+constexpr size_t kAl = 256;
+size_t al(size_t x) { return (x + kAl - 1) / kAl * kAl; }
+int64_t nbuckets(int64_t n) { return (n + kBucketWidth - 1) >> kBucketShift; }
+int64_t ntiles(int64_t m) { return (m + kBucketTile - 1) >> kBucketTileShift; }
+constexpr int kGroups = (int)(kBucketTile / 4 / kBucketThreads);   // 4-edge groups per thread
+constexpr uint32_t kArcMask = (uint32_t)kTileArcs - 1;
+constexpr int kInFlight = 16;                                       // gathers per lane in flight
+constexpr uint32_t kPassGrid = 1024;                                // workgroups of the pass
+
+template <typename T, typename V>
+__device__ __forceinline__ void load4(const T* __restrict__ p, int64_t q, int64_t e1, T (&x)[4]) {
+    const int64_t e = q * 4;
+    if (e + 3 < e1) {
+        const V t = reinterpret_cast<const V*>(p)[q];
+        x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = e + k < e1 ? p[e + k] : 0;
+    }
+}
+
+__device__ __forceinline__ bool in_range(int32_t a, int32_t b, int64_t n) {
+    return (uint32_t)a < (uint64_t)n && (uint32_t)b < (uint64_t)n;
+}
+
+// Largest k in [0, 1024) with a[k] <= x (a non-decreasing, a[0] <= x): ten
+// fixed steps, so a lane's searches interleave.  With empty runs (equal
+// starts) it lands on the one run that holds slot x.
+__device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t x) {
+    uint32_t lo = 0;
+#pragma unroll
+    for (uint32_t step = kBucketThreads / 2; step > 0; step >>= 1)
+        lo = a[lo + step] <= x ? lo + step : lo;
+    return lo;
+}
+static_assert(kBucketMax == kBucketThreads, "run tables are searched over kBucketThreads entries");
+
+}  // namespace
+
+bool bucket_eligible(int64_t m, int64_t n) {
+    return n >= (1ll << 21) && nbuckets(n) <= kBucketMax && m >= (1ll << 22) && m < (1ll << 31);
+}
+
+size_t bucket_carve(char* ws, int64_t m, int64_t n, BucketBuffers* B) {
+    BucketBuffers b{};
+    if (!bucket_eligible(m, n)) {
+        if (B) *B = b;
+        return 0;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += al(bytes);
+        return ws ? ws + o : nullptr;
+    };
+    const int64_t nb = nbuckets(n), nt = ntiles(m), cells = nb * nt;
+    b.arcs = (uint64_t*)take((size_t)(nt * kTileArcs) * 8);
+    b.meta = (uint32_t*)take((size_t)cells * 4);
+    b.metat = (uint32_t*)take((size_t)cells * 4);
+    b.offb = (uint32_t*)take((size_t)cells * 4);
+    b.offt = (uint32_t*)take((size_t)cells * 4);
+    b.base = (uint64_t*)take((size_t)(nb + 1) * 8);
+    b.tmp = (uint64_t*)take(scan_levels_bytes(nb));
+    b.xs = (uint16_t*)take((size_t)(2 * m + 64) * 2);   // 8-index groups may read past the end
+    b.rank = (uint32_t*)take((size_t)m * 4 + 16);
+    b.hot = (int32_t*)take(kHot * 4);
+    b.mcap = m;
+    b.ncap = n;
+    if (B) *B = b;
+    return off;
+}
+
+bool bucket_usable(const BucketBuffers& B, int64_t m, int64_t n) {
+    return B.arcs && bucket_eligible(m, n) && m <= B.mcap && n <= B.ncap;
+}
+
+// ---------------------------------------------------------------- scatter
+
+// Arc of endpoint x of edge e (in tile block order): w << 32 | (e - e0) << 14
+// | x mod 2^14.  An edge whose ids are out of range raises kErrRange and, like a
+// self-loop, has no arcs.  rank[e] = places of its two arcs in the block.
+__global__ __launch_bounds__(kBucketThreads) void k_bk_scatter(
+    const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
+    int64_t m, int64_t n, uint32_t nb, uint64_t* __restrict__ arcs, uint32_t* __restrict__ meta,
+    uint32_t* __restrict__ rank, Ctrl* ctrl) {
+    __shared__ uint64_t s_stage[kTileArcs];
+    __shared__ uint32_t s_cnt[kBucketMax];
+    __shared__ uint32_t s_cur[kBucketMax];
+    __shared__ uint64_t s_w[kBucketThreads / kWave];
+    const uint32_t t = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid < (int)nb) s_cnt[tid] = 0;
+    const int64_t e0 = (int64_t)t << kBucketTileShift;
+    const int64_t e1 = e0 + kBucketTile < m ? e0 + kBucketTile : m;
+    int32_t a[kGroups][4], b[kGroups][4];
+    uint32_t ww[kGroups][4];
+#pragma unroll
+    for (int j = 0; j < kGroups; ++j) {
+        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
+        load4<int32_t, int4>(u, q, e1, a[j]);
+        load4<int32_t, int4>(v, q, e1, b[j]);
+        load4<uint32_t, uint4>(w, q, e1, ww[j]);
+    }
+    __syncthreads();
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < kGroups; ++j) {
+        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (q * 4 + k >= e1) continue;
+            const int32_t x = a[j][k], y = b[j][k];
+            if (!in_range(x, y, n)) { bad = true; continue; }
+            if (x == y) continue;
+            atomicAdd(&s_cnt[(uint32_t)x >> kBucketShift], 1u);
+            atomicAdd(&s_cnt[(uint32_t)y >> kBucketShift], 1u);
+        }
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrRange);
+    __syncthreads();
+    const uint32_t c = tid < (int)nb ? s_cnt[tid] : 0u;
+    uint64_t tot;
+    const uint32_t ex = (uint32_t)block_excl_scan(c, s_w, &tot);
+    if (tid < (int)nb) {
+        s_cur[tid] = ex;
+        meta[(int64_t)t * nb + tid] = ex | (c << 16);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kGroups; ++j) {
+        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
+        uint32_t rk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            rk[k] = 0;
+            const int64_t e = q * 4 + k;
+            const int32_t x = a[j][k], y = b[j][k];
+            if (e >= e1 || !in_range(x, y, n) || x == y) continue;
+            const uint64_t hi = ((uint64_t)ww[j][k] << 32) | ((uint64_t)(e - e0) << kBucketShift);
+            const uint32_t px = atomicAdd(&s_cur[(uint32_t)x >> kBucketShift], 1u) & kArcMask;
+            const uint32_t py = atomicAdd(&s_cur[(uint32_t)y >> kBucketShift], 1u) & kArcMask;
+            s_stage[px] = hi | (uint64_t)(x & (kBucketWidth - 1));
+            s_stage[py] = hi | (uint64_t)(y & (kBucketWidth - 1));
+            rk[k] = px | (py << 16);
+        }
+        if (q * 4 + 3 < e1) {
+            reinterpret_cast<uint4*>(rank)[q] = make_uint4(rk[0], rk[1], rk[2], rk[3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (q * 4 + k < e1) rank[q * 4 + k] = rk[k];
+        }
+    }
+    __syncthreads();
+    const uint32_t na = (uint32_t)(tot < (uint64_t)kTileArcs ? tot : (uint64_t)kTileArcs);
+    uint64_t* dst = arcs + (int64_t)t * kTileArcs;
+    for (uint32_t i = tid; i < na; i += blockDim.x) dst[i] = s_stage[i];
+}
+
+// ------------------------------------------------------------------ index
+
+// out[c * R + r] = in[r * C + c] for an R x C matrix, 32 x 32 tiles.
+__global__ __launch_bounds__(256) void k_transpose_u32(const uint32_t* __restrict__ in,
+                                                       uint32_t* __restrict__ out, int64_t R,
+                                                       int64_t C) {
+    __shared__ uint32_t tile[32][33];
+    const int64_t tiles_c = (C + 31) / 32;
+    const int64_t tc = blockIdx.x % tiles_c, tr = blockIdx.x / tiles_c;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t r = tr * 32 + k, c = tc * 32 + tx;
+        if (r < R && c < C) tile[k][tx] = in[r * C + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int64_t c = tc * 32 + k, r = tr * 32 + tx;
+        if (r < R && c < C) out[c * R + r] = tile[tx][k];
+    }
+}
+
+// base[b] = arcs of bucket b (scanned afterwards).
+__global__ __launch_bounds__(256) void k_bk_totals(const uint32_t* __restrict__ metat, uint32_t nt,
+                                                   uint64_t* __restrict__ base) {
+    __shared__ uint64_t s_w[256 / kWave];
+    const uint32_t* row = metat + (int64_t)blockIdx.x * nt;
+    uint64_t sum = 0;
+    for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) sum += row[t] >> 16;
+    uint64_t tot;
+    (void)block_excl_scan(sum, s_w, &tot);
+    if (threadIdx.x == 0) base[blockIdx.x] = tot;
+}
+
+// -------------------------------------------------------------------- min
+
+__global__ __launch_bounds__(kBucketThreads) void k_bk_min(
+    const uint64_t* __restrict__ arcs, const uint32_t* __restrict__ metat, uint32_t nt,
+    int64_t n, int64_t narcs, const uint64_t* __restrict__ base, uint64_t* __restrict__ best,
+    uint16_t* __restrict__ xs, uint32_t* __restrict__ offb) {
+    __shared__ unsigned long long s_best[kBucketWidth];
+    __shared__ uint32_t s_pre[kBucketThreads];   // batch run r0 + k starts at arc s_pre[k] of the batch
+    __shared__ uint32_t s_rs[kBucketThreads];    // and at slot s_rs[k] of its tile block
+    __shared__ uint64_t s_w[kBucketThreads / kWave];
+    const uint32_t bk = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kBucketWidth; i += blockDim.x) s_best[i] = kKeyMax;
+    const uint64_t xs0 = base[bk];
+    const uint32_t* row = metat + (int64_t)bk * nt;
+    uint32_t pre = 0;   // arcs of the bucket in earlier batches
+    for (uint32_t r0 = 0; r0 < nt; r0 += kBucketThreads) {
+        const uint32_t r = r0 + tid;
+        const uint32_t mt = r < nt ? row[r] : 0u;
+        uint64_t btot;
+        const uint32_t ex = (uint32_t)block_excl_scan(mt >> 16, s_w, &btot);
+        s_pre[tid] = ex;
+        s_rs[tid] = mt & 0xffff;
+        if (r < nt) offb[(int64_t)bk * nt + r] = pre + ex;
+        __syncthreads();
+        const uint32_t bt = (uint32_t)btot;
+        for (uint32_t v0 = tid; v0 < bt; v0 += kInFlight * kBucketThreads) {
+            uint64_t arc[kInFlight];
+            uint32_t run[kInFlight];
+#pragma unroll
+            for (int k = 0; k < kInFlight; ++k) {
+                const uint32_t x = v0 + k * kBucketThreads;
+                arc[k] = 0;
+                run[k] = 0;
+                if (x < bt) {
+                    const uint32_t j = last_le(s_pre, x);
+                    run[k] = j;
+                    const uint32_t slot = (s_rs[j] + (x - s_pre[j])) & kArcMask;
+                    arc[k] = arcs[(int64_t)(r0 + j) * kTileArcs + slot];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kInFlight; ++k) {
+                const uint32_t x = v0 + k * kBucketThreads;
+                if (x >= bt) continue;
+                const uint32_t xl = (uint32_t)arc[k] & (uint32_t)(kBucketWidth - 1);
+                const uint64_t e = ((uint64_t)(r0 + run[k]) << kBucketTileShift) +
+                                   (((uint32_t)arc[k] >> kBucketShift) & (uint32_t)(kBucketTile - 1));
+                const uint64_t key = (arc[k] & 0xffffffff00000000ull) | e;
+                if (key < s_best[xl]) atomicMin(&s_best[xl], (unsigned long long)key);
+                const uint64_t o = xs0 + pre + x;
+                if (o < (uint64_t)narcs) xs[o] = (uint16_t)xl;
+            }
+        }
+        pre += bt;
+        __syncthreads();
+    }
+    const int64_t v0 = (int64_t)bk << kBucketShift;
+    for (int i = tid; i < kBucketWidth && v0 + i < n; i += blockDim.x) best[v0 + i] = s_best[i];
+}
+
+// ------------------------------------------------------------------ label
+
+// relab[i] = M[vertex of arc i] over the bucket's part of the bucket-major
+// streams, 8 indices (16 B) per group; relab shares memory with the arcs.
+__global__ __launch_bounds__(kBucketThreads) void k_bk_label(
+    const uint16_t* __restrict__ xs, const uint64_t* __restrict__ base, int64_t n, int64_t narcs,
+    const int32_t* __restrict__ M, uint32_t* __restrict__ relab) {
+    __shared__ uint32_t s_lab[kBucketWidth];
+    const uint32_t bk = blockIdx.x;
+    const int64_t v0 = (int64_t)bk << kBucketShift;
+    for (int i = threadIdx.x; i < kBucketWidth; i += blockDim.x)
+        s_lab[i] = v0 + i < n ? (uint32_t)M[v0 + i] : 0u;
+    __syncthreads();
+    const int64_t i1 = std::min((int64_t)base[bk + 1], narcs);
+    const int64_t i0 = std::min((int64_t)base[bk], i1);
+    const int64_t g0 = i0 / 8, g1 = (i1 + 7) / 8;
+    const int64_t stride = blockDim.x;
+    for (int64_t gb = g0 + threadIdx.x; gb < g1; gb += 2 * stride) {
+        uint4 xv[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t g = gb + j * stride;
+            if (g < g1) xv[j] = reinterpret_cast<const uint4*>(xs)[g];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t g = gb + j * stride;
+            if (g >= g1) continue;
+            const uint32_t wd[4] = {xv[j].x, xv[j].y, xv[j].z, xv[j].w};
+            uint32_t r[8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+                r[a] = s_lab[((a & 1) ? (wd[a >> 1] >> 16) : wd[a >> 1]) & (uint32_t)(kBucketWidth - 1)];
+            const int64_t i = g * 8;
+            if (i >= i0 && i + 8 <= i1) {
+                reinterpret_cast<uint4*>(relab)[2 * g] = make_uint4(r[0], r[1], r[2], r[3]);
+                reinterpret_cast<uint4*>(relab)[2 * g + 1] = make_uint4(r[4], r[5], r[6], r[7]);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 8; ++a)
+                    if (i + a >= i0 && i + a < i1) relab[i + a] = r[a];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------- pass
+
+// One workgroup per tile: slot x of the tile block holds the arc whose label
+// is relab[base[b] + offt[t][b] + (x - run start of b)], b the bucket whose run
+// holds x.  The labels are gathered into LDS in block order; an edge finds
+// its two at the places recorded in rank[].  Then, as the plain relabelling
+// pass does: dead edges (self-loops, equal labels) are written as (0, 0),
+// live ones as label pairs, and take part in the next round's lightest-edge
+// search with key (w << 32 | position).
+template <int OUT>
+__global__ __launch_bounds__(kBucketThreads) void k_bk_pass(
+    const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
+    int64_t m, int64_t n, uint32_t nb, uint32_t nt, const uint32_t* __restrict__ meta,
+    const uint32_t* __restrict__ offt, const uint64_t* __restrict__ base,
+    const uint32_t* __restrict__ relab, const uint32_t* __restrict__ rank,
+    int32_t* __restrict__ ou, int32_t* __restrict__ ov, uint32_t* __restrict__ op16,
+    uint64_t* __restrict__ best_next, int64_t nn, const int32_t* __restrict__ hot_in, Ctrl* ctrl) {
+    __shared__ uint32_t s_lab[kTileArcs];
+    __shared__ uint32_t s_rs[kBucketMax];
+    __shared__ uint64_t s_src[kBucketMax];
+    __shared__ uint32_t s_na;
+    __shared__ unsigned long long s_hotmin[kHot];  // lightest edges of the hot labels in the tile
+    __shared__ uint64_t s_w[kBucketThreads / kWave];
+    const int tid = threadIdx.x;
+    const uint64_t narcs = 2 * (uint64_t)m;
+    uint32_t kept = 0;
+    bool bad = false;
+    // After round 0 of a skewed graph most edges touch a few huge
+    // components: the hot labels (found once, by k_bk_hot) have their minima
+    // taken in LDS and merged once per tile.
+    int32_t hot[kHot];
+#pragma unroll
+    for (int h = 0; h < kHot; ++h) hot[h] = hot_in[h];
+    // tiles are taken grid-stride, so the live-edge count costs one atomic
+    // per workgroup (same-address atomics queue at ~13 ns each)
+    for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    if (tid < (int)nb) {
+        const int64_t j = (int64_t)t * nb + tid;
+        const uint32_t mt = meta[j];
+        s_rs[tid] = mt & 0xffff;
+        s_src[tid] = base[tid] + offt[j];
+        if (tid == (int)nb - 1) s_na = std::min((mt & 0xffff) + (mt >> 16), (uint32_t)kTileArcs);
+    } else {
+        s_rs[tid] = 0xffffffffu;   // past the last bucket: never <= a slot
+        s_src[tid] = 0;
+    }
+    __syncthreads();
+    const uint32_t na = s_na;
+    for (uint32_t x0 = tid; x0 < na; x0 += kInFlight * kBucketThreads) {
+        uint32_t val[kInFlight];
+#pragma unroll
+        for (int k = 0; k < kInFlight; ++k) {
+            const uint32_t x = x0 + k * kBucketThreads;
+            val[k] = 0;
+            if (x < na) {
+                const uint32_t b = last_le(s_rs, x);
+                const uint64_t i = s_src[b] + (x - s_rs[b]);
+                if (i < narcs) val[k] = relab[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kInFlight; ++k) {
+            const uint32_t x = x0 + k * kBucketThreads;
+            if (x < na) s_lab[x] = val[k];
+        }
+    }
+    __syncthreads();
+    if (tid < kHot) s_hotmin[tid] = kKeyMax;
+    __syncthreads();
+    const int64_t e0 = (int64_t)t << kBucketTileShift;
+    const int64_t e1 = e0 + kBucketTile < m ? e0 + kBucketTile : m;
+    int32_t a[kGroups][4], b[kGroups][4];
+    uint32_t ww[kGroups][4], rk[kGroups][4];
+#pragma unroll
+    for (int j = 0; j < kGroups; ++j) {
+        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
+        load4<int32_t, int4>(u, q, e1, a[j]);
+        load4<int32_t, int4>(v, q, e1, b[j]);
+        load4<uint32_t, uint4>(w, q, e1, ww[j]);
+        load4<uint32_t, uint4>(rank, q, e1, rk[j]);
+    }
+    // The lane's 2 x kGroups x 4 reads of best_next are issued together,
+    // then the atomics of the keys that beat them (every lane runs every step:
+    // wave_min_commit needs whole waves).
+    constexpr int kE = kGroups * 4;
+    int32_t ra[kE], rb[kE];
+    uint64_t key[kE];
+    bool ax[kE], ay[kE];
+#pragma unroll
+    for (int j = 0; j < kGroups; ++j) {
+        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = j * 4 + k;
+            ra[i] = rb[i] = 0;
+            key[i] = kKeyMax;
+            ax[i] = ay[i] = false;
+            const int64_t e = q * 4 + k;
+            const int32_t x = a[j][k], y = b[j][k];
+            if (e < e1 && in_range(x, y, n) && x != y) {
+                const uint32_t lx = s_lab[rk[j][k] & kArcMask];
+                const uint32_t ly = s_lab[(rk[j][k] >> 16) & kArcMask];
+                if (lx != ly) {
+                    if (lx >= (uint64_t)nn || ly >= (uint64_t)nn) {
+                        bad = true;
+                    } else {
+                        ra[i] = (int32_t)lx;
+                        rb[i] = (int32_t)ly;
+                        ++kept;
+                        key[i] = ((uint64_t)ww[j][k] << 32) | (uint64_t)e;
+                        ax[i] = !hot_min(hot, s_hotmin, ra[i], key[i]);
+                        ay[i] = !hot_min(hot, s_hotmin, rb[i], key[i]);
+                    }
+                }
+            }
+        }
+        if (q * 4 < e1) store_group<OUT>(q, m, *reinterpret_cast<int32_t(*)[4]>(&ra[j * 4]),
+                                         *reinterpret_cast<int32_t(*)[4]>(&rb[j * 4]), ou, ov, op16);
+    }
+    uint64_t cx[kE], cy[kE];
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+        cx[i] = ax[i] ? best_next[ra[i]] : 0;
+        cy[i] = ay[i] ? best_next[rb[i]] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+        wave_min_commit(best_next, ra[i], key[i], ax[i] && key[i] < cx[i]);
+        wave_min_commit(best_next, rb[i], key[i], ay[i] && key[i] < cy[i]);
+    }
+    __syncthreads();
+    if (tid < kHot && hot[tid] >= 0 && s_hotmin[tid] != kKeyMax)
+        atomic_min_key(&best_next[hot[tid]], s_hotmin[tid]);
+    __syncthreads();   // the next tile reuses the LDS tables
+    }
+    uint64_t tot;
+    (void)block_excl_scan(kept, s_w, &tot);
+    if (tid == 0 && tot) atomicAdd((unsigned long long*)&ctrl->m_next, (unsigned long long)tot);
+    if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrInternal);
+}
+
+// The kHot labels most frequent among 64 arcs sampled evenly over the
+// bucket-major label stream (each at least kHotMinCount of them), or -1.
+__global__ __launch_bounds__(kWave) void k_bk_hot(const uint32_t* __restrict__ relab,
+                                                  uint64_t narcs, int32_t* __restrict__ hot) {
+    __shared__ int32_t s_hot[kHot];
+    __shared__ unsigned long long s_min[kHot];
+    const uint64_t i = ((uint64_t)threadIdx.x * narcs + narcs / 2) / kWave;
+    hot_labels(i < narcs ? (int32_t)relab[i] : -1, s_hot, s_min);
+    __syncthreads();
+    if (threadIdx.x < kHot) hot[threadIdx.x] = s_hot[threadIdx.x];
+}
+
+// ctrl->aux[0] = how many of 4096 edges sampled evenly have |u - v| below the
+// bucket width (ids with locality: the edge-list round 0 then hits in L2).
+__global__ __launch_bounds__(kBucketThreads) void k_bk_locality(const int32_t* __restrict__ u,
+                                                                const int32_t* __restrict__ v,
+                                                                int64_t m, Ctrl* ctrl) {
+    __shared__ uint64_t s_w[kBucketThreads / kWave];
+    uint64_t local = 0;
+    for (int k = threadIdx.x; k < kLocalitySample; k += blockDim.x) {
+        const int64_t e = (int64_t)(((uint64_t)k * (uint64_t)m) / kLocalitySample);
+        const int64_t d = (int64_t)u[e] - (int64_t)v[e];
+        local += (d < kBucketWidth && -d < kBucketWidth) ? 1 : 0;
+    }
+    uint64_t tot;
+    (void)block_excl_scan(local, s_w, &tot);
+    if (threadIdx.x == 0) ctrl->aux[0] = tot;
+}
+
+// -------------------------------------------------------------- launchers
+
+void bucket_sample_locality(const int32_t* u, const int32_t* v, int64_t m, Ctrl* ctrl,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_bk_locality, dim3(1), dim3(kBucketThreads), 0, s, u, v, m, ctrl);
+}
+
+static unsigned transpose_grid(int64_t R, int64_t C) {
+    return (unsigned)(((R + 31) / 32) * ((C + 31) / 32));
+}
+
+void bucket_minedge(const BucketBuffers& B, const int32_t* u, const int32_t* v,
+                    const uint32_t* w, int64_t m, int64_t n, uint64_t* best, Ctrl* ctrl,
+                    hipStream_t s) {
+    const uint32_t nb = (uint32_t)nbuckets(n), nt = (uint32_t)ntiles(m);
+    const double cells = (double)nb * nt, arcs = 2.0 * (double)m;
+    const dim3 bl(kBucketThreads);
+    int h = prof_begin(K_BK_SCATTER, s);
+    hipLaunchKernelGGL(k_bk_scatter, dim3(nt), bl, 0, s, u, v, w, m, n, nb, B.arcs, B.meta,
+                       B.rank, ctrl);
+    prof_end(h, s, 12.0 * m + 8.0 * arcs + 4.0 * m + 4.0 * cells);
+    h = prof_begin(K_BK_INDEX, s);
+    hipLaunchKernelGGL(k_transpose_u32, dim3(transpose_grid(nt, nb)), dim3(256), 0, s, B.meta,
+                       B.metat, (int64_t)nt, (int64_t)nb);
+    hipLaunchKernelGGL(k_bk_totals, dim3(nb), dim3(256), 0, s, B.metat, nt, B.base);
+    launch_scan_u64(B.base, nb, B.tmp, B.base + nb, s);
+    prof_end(h, s, 12.0 * cells + 24.0 * nb);
+    h = prof_begin(K_BK_MIN, s);
+    hipLaunchKernelGGL(k_bk_min, dim3(nb), bl, 0, s, B.arcs, B.metat, nt, n, 2 * m, B.base, best,
+                       B.xs, B.offb);
+    prof_end(h, s, 8.0 * arcs + 2.0 * arcs + 8.0 * cells + 8.0 * n);
+    h = prof_begin(K_BK_INDEX, s);
+    hipLaunchKernelGGL(k_transpose_u32, dim3(transpose_grid(nb, nt)), dim3(256), 0, s, B.offb,
+                       B.offt, (int64_t)nb, (int64_t)nt);
+    prof_end(h, s, 8.0 * cells);
+}
+
+void bucket_relabel(const BucketBuffers& B, const int32_t* u, const int32_t* v,
+                    const uint32_t* w, int64_t m, int64_t n, const int32_t* M, int out,
+                    int32_t* ou, int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn,
+                    Ctrl* ctrl, hipStream_t s) {
+    const uint32_t nb = (uint32_t)nbuckets(n), nt = (uint32_t)ntiles(m);
+    const double cells = (double)nb * nt, arcs = 2.0 * (double)m;
+    uint32_t* relab = reinterpret_cast<uint32_t*>(B.arcs);
+    const dim3 bl(kBucketThreads);
+    int h = prof_begin(K_BK_LABEL, s);
+    hipLaunchKernelGGL(k_bk_label, dim3(nb), bl, 0, s, B.xs, B.base, n, 2 * m, M, relab);
+    hipLaunchKernelGGL(k_bk_hot, dim3(1), dim3(kWave), 0, s, relab, (uint64_t)(2 * m), B.hot);
+    prof_end(h, s, 6.0 * arcs + 4.0 * n);
+    h = prof_begin(K_BK_PASS, s);
+    const dim3 grid(std::min<uint32_t>(nt, kPassGrid));
+    if (out == kOut16)
+        hipLaunchKernelGGL(k_bk_pass<kOut16>, grid, bl, 0, s, u, v, w, m, n, nb, nt, B.meta,
+                           B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, B.hot, ctrl);
+    else
+        hipLaunchKernelGGL(k_bk_pass<kOut32>, grid, bl, 0, s, u, v, w, m, n, nb, nt, B.meta,
+                           B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, B.hot, ctrl);
+    prof_end(h, s, 16.0 * m + 4.0 * arcs + (out == kOut16 ? 4.0 : 8.0) * m + 8.0 * cells +
+                       8.0 * nn);
+}
+
+}  // namespace msf

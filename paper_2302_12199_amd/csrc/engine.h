@@ -1,5 +1,6 @@
 // Borůvka round driver (paper Sec. II-C, Alg. 1's round loop) on one GPU.
 #pragma once
+#include "bucket.h"
 #include "host.h"
 #include "launch.h"
 
@@ -21,12 +22,15 @@ struct EngineBuffers {
     uint64_t* pairs;      // tail: lightest edge per vertex pair (triangular table)
     uint32_t* list_xy[2];  // tail: pair list (ping-pong, compacted every round)
     uint64_t* list_key[2];
+    BucketBuffers bk;     // bucketed round 0 (large graphs only)
+    int round0;           // msf_round0: when round 0 runs by buckets
     int64_t ncap, mcap;
 };
 
-size_t engine_bytes(int64_t m, int64_t n);
+// buckets: also carve the bucketed round 0's buffers (for graphs it applies to).
+size_t engine_bytes(int64_t m, int64_t n, bool buckets);
 // Carves buffers starting at ws; returns the bytes used.
-size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B);
+size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool buckets);
 
 // Runs Borůvka rounds until no edge is left.
 //   view/mode   the current graph: kOrig (the caller's arrays; round 0 runs

@@ -32,7 +32,7 @@ constexpr double kCompactBelow = 0.5;   // compact when live / positions drops b
 constexpr int64_t kMax16 = 65535;       // label count that still fits the packed layout
 }  // namespace
 
-size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B) {
+size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool buckets) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -65,13 +65,18 @@ size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B) {
         b.list_xy[i] = (uint32_t*)take(slots * 4);
         b.list_key[i] = (uint64_t*)take(slots * 8);
     }
+    if (buckets) off += bucket_carve(ws ? ws + off : nullptr, m, n, &b.bk);
+    else b.bk = BucketBuffers{};
+    b.round0 = MSF_ROUND0_AUTO;
     b.ncap = n;
     b.mcap = m;
     if (B) *B = b;
     return off;
 }
 
-size_t engine_bytes(int64_t m, int64_t n) { return engine_carve(nullptr, m, n, nullptr); }
+size_t engine_bytes(int64_t m, int64_t n, bool buckets) {
+    return engine_carve(nullptr, m, n, nullptr, buckets);
+}
 
 // MSF_ALWAYS_COMPACT=1 compacts after every round (a tuning and diagnosis knob).
 static bool always_compact() {
@@ -81,6 +86,22 @@ static bool always_compact() {
         on = (e && e[0] == '1') ? 1 : 0;
     }
     return on == 1;
+}
+
+// MSF_BUCKET_R0=0 runs round 0 on the caller's edge list directly even where
+// the bucketed round 0 applies (a tuning and diagnosis knob).
+static bool bucket_r0_enabled() {
+    static int on = -1;
+    if (on < 0) {
+        const char* e = getenv("MSF_BUCKET_R0");
+        on = (e && e[0] == '0') ? 0 : 1;
+    }
+    return on == 1;
+}
+
+static bool aligned16(const View& g) {
+    return ((((uintptr_t)g.u | (uintptr_t)g.v | (uintptr_t)g.w | (uintptr_t)g.p16 |
+              (uintptr_t)g.id) & 15) == 0);
 }
 
 // MSF_DUMP_DIR=<dir> writes each round's parent, label, map and next-best
@@ -122,12 +143,27 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
 
     // Round 0 lightest edges (on the caller's arrays, or on a compact view
     // whose positions are already in id order).
-    int h = prof_begin(K_FILL, s);
-    launch_fill_u64(B.best[cur], nr, kKeyMax, s);
-    prof_end(h, s, 8.0 * nr);
-    h = prof_begin(K_MINEDGE_R0, s);
-    launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, hot, s);
-    prof_end(h, s, 12.0 * view.len + 8.0 * nv);
+    // Large graphs on the caller's arrays without id locality: round 0 by
+    // vertex buckets (with locality the edge-list round 0 mostly hits in L2).
+    bool bucketed = mode == kOrig && bucket_r0_enabled() && aligned16(view) &&
+                    bucket_usable(B.bk, view.len, nv);
+    if (bucketed && B.round0 == MSF_ROUND0_AUTO) {
+        bucket_sample_locality(view.u, view.v, view.len, dc, s);
+        HIP_TRY(hipGetLastError());
+        if ((st = read_ctrl(dc, hc, s))) return st;
+        bucketed = hc->aux[0] * 2 < (uint64_t)kLocalitySample;
+    }
+    int h = -1;
+    if (bucketed) {
+        bucket_minedge(B.bk, view.u, view.v, view.w, view.len, nv, B.best[cur], dc, s);
+    } else {
+        h = prof_begin(K_FILL, s);
+        launch_fill_u64(B.best[cur], nr, kKeyMax, s);
+        prof_end(h, s, 8.0 * nr);
+        h = prof_begin(K_MINEDGE_R0, s);
+        launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, hot, s);
+        prof_end(h, s, 12.0 * view.len + 8.0 * nv);
+    }
     HIP_TRY(hipGetLastError());
     if ((st = read_ctrl(dc, hc, s))) return st;
     if (hc->err & kErrRange) return MSF_ERANGE;
@@ -257,15 +293,20 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             int out = kOutNone;
             if (mode == kOrig) out = nn <= kMax16 ? kOut16 : kOut32;
             else if (mode == kFull32 && nn <= kMax16) out = kOut16;
-            h = prof_begin(mode == kOrig ? K_PASS_R0 : K_PASS, s);
-            if (!launch_pass(mode, out, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1], nn,
-                             nullptr, dc, s)) {
-                set_err_text("unsupported pass layout");
-                return MSF_EINTERNAL;
+            if (bucketed && mode == kOrig) {
+                bucket_relabel(B.bk, view.u, view.v, view.w, view.len, nv, M, out, B.f32u,
+                               B.f32v, B.p16, B.best[cur ^ 1], nn, dc, s);
+            } else {
+                h = prof_begin(mode == kOrig ? K_PASS_R0 : K_PASS, s);
+                if (!launch_pass(mode, out, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1],
+                                 nn, nullptr, dc, s)) {
+                    set_err_text("unsupported pass layout");
+                    return MSF_EINTERNAL;
+                }
+                prof_end(h, s, view_read_bytes(mode) * view.len + 8.0 * m_live +
+                                   (out == kOut32 ? 8.0 : out == kOut16 ? 4.0 : 0.0) * view.len +
+                                   8.0 * nn);
             }
-            prof_end(h, s, view_read_bytes(mode) * view.len + 8.0 * m_live +
-                               (out == kOut32 ? 8.0 : out == kOut16 ? 4.0 : 0.0) * view.len +
-                               8.0 * nn);
             if (out == kOut32) {
                 next.u = B.f32u; next.v = B.f32v; next.p16 = nullptr; next_mode = kFull32;
             } else if (out == kOut16) {

@@ -250,27 +250,6 @@ constexpr unsigned kTileGrid = 4096;
 constexpr int kScanChunk = kBlock * 8;
 constexpr int kScanTop = 1024;     // chunk sums: nt <= 2^21 tiles covers m < 2^32
 
-__device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t* s_w, uint64_t* total) {
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    uint64_t inc = x;
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint64_t y = __shfl_up(inc, off, kWave);
-        if (lane >= off) inc += y;
-    }
-    if (lane == kWave - 1) s_w[wave] = inc;
-    __syncthreads();
-    uint64_t pre = 0, tot = 0;
-    const int nw = blockDim.x / kWave;
-    for (int i = 0; i < nw; ++i) {
-        const uint64_t v = s_w[i];
-        if (i < wave) pre += v;
-        tot += v;
-    }
-    __syncthreads();
-    *total = tot;
-    return pre + inc - x;
-}
-
 __global__ __launch_bounds__(kBlock) void k_scan_up(const uint64_t* __restrict__ cnt, uint32_t nt,
                                                     uint64_t* __restrict__ bsum) {
     __shared__ uint64_t s_w[kBlock / kWave];
@@ -320,6 +299,28 @@ void launch_scan_tiles(uint64_t* cnt, uint32_t nt, uint64_t* bsum, uint64_t* tot
     hipLaunchKernelGGL(k_scan_up, dim3(nb), dim3(kBlock), 0, s, cnt, nt, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTop), 0, s, bsum, nb, total);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, s, cnt, nt, bsum);
+}
+
+// Exclusive scan of cnt[0, n) in place for any n < 2^32: the chunk sums are
+// scanned by one workgroup when there are at most kScanTop of them, else by
+// the same three steps one level up (tmp holds every level's chunk sums:
+// scan_levels_bytes(n) bytes).
+size_t scan_levels_bytes(int64_t n) {
+    size_t words = 0;
+    for (int64_t k = n; k > 1;) {
+        k = (k + kScanChunk - 1) / kScanChunk;
+        words += (size_t)k;
+    }
+    return (words + 1) * 8;
+}
+void launch_scan_u64(uint64_t* cnt, int64_t n, uint64_t* tmp, uint64_t* total, hipStream_t s) {
+    const uint32_t nb = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(k_scan_up, dim3(nb), dim3(kBlock), 0, s, cnt, (uint32_t)n, tmp);
+    if (nb <= (uint32_t)kScanTop)
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTop), 0, s, tmp, nb, total);
+    else
+        launch_scan_u64(tmp, nb, tmp + nb, total, s);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, s, cnt, (uint32_t)n, tmp);
 }
 
 // Stable two-way split by key <= pivot: tile t writes its light edges from
@@ -871,8 +872,7 @@ size_t flags_bytes(int64_t m) {
 }
 
 size_t filter_bytes(int64_t m, int64_t n, const msf_options& opt) {
-    (void)opt;
-    return engine_bytes(m, n) + align_up((size_t)(n > 0 ? n : 1) * 4) + 2 * buffer_bytes(m) +
+    return engine_bytes(m, n, opt.round0 != MSF_ROUND0_EDGES) + align_up((size_t)(n > 0 ? n : 1) * 4) + 2 * buffer_bytes(m) +
            codes_bytes(n) + flags_bytes(m) + align_up(kScanTop * 8);
 }
 
@@ -880,7 +880,8 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
                  uint8_t* mask, char* ws, hipStream_t s, const msf_options& opt,
                  msf_stats* stats) {
     Ctx C;
-    size_t off = engine_carve(ws, m, n, &C.B);
+    size_t off = engine_carve(ws, m, n, &C.B, opt.round0 != MSF_ROUND0_EDGES);
+    C.B.round0 = opt.round0;
     C.P = (int32_t*)(ws + off);
     off += align_up((size_t)(n > 0 ? n : 1) * 4);
     C.buf[0] = carve_buffer(ws + off, m);

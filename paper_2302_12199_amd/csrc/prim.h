@@ -60,6 +60,59 @@ __device__ __forceinline__ void wave_min_update(uint64_t* best, int32_t t, uint6
     if (act) atomic_min_key(&best[t], key);
 }
 
+// As wave_min_update, for lanes whose key already beat the entry's value as
+// read earlier (a caller that issues all its reads first keeps them in
+// flight together): the atomics go out without reading the entry again.
+__device__ __forceinline__ void wave_min_commit(uint64_t* best, int32_t t, uint64_t key,
+                                                bool act) {
+    const uint64_t am = __ballot(act);
+    if (am == 0) return;
+    const int leader = __builtin_ctzll(am);
+    const int32_t tl = __shfl(t, leader, 64);
+    const bool same = act && t == tl;
+    if (__popcll(__ballot(same)) > 1) {
+        const uint64_t k = wave_min_u64(same ? key : kKeyMax);
+        if (lane_id() == leader) atomicMin((unsigned long long*)&best[tl], (unsigned long long)k);
+        act = act && !same;
+    }
+    if (act) atomicMin((unsigned long long*)&best[t], (unsigned long long)key);
+}
+
+// Hot labels of a workgroup: called by one wave with one sampled label per
+// lane (-1 = none); writes the kHot most frequent sampled labels that occur
+// at least kHotMinCount times (else -1) and clears their minima.
+constexpr int kHot = 4;
+constexpr int kHotMinCount = 4;
+__device__ __forceinline__ void hot_labels(int32_t lab, int32_t* s_hot,
+                                           unsigned long long* s_hotmin) {
+    for (int h = 0; h < kHot; ++h) {
+        int best_cnt = 0;
+        int32_t best_lab = -1;
+        for (int i = 0; i < kWave; ++i) {
+            const int32_t li = __shfl(lab, i, kWave);
+            const int c = __popcll(__ballot(lab == li && li >= 0));
+            if (c > best_cnt) { best_cnt = c; best_lab = li; }
+        }
+        if (lane_id() == 0) {
+            s_hot[h] = best_cnt >= kHotMinCount ? best_lab : -1;
+            s_hotmin[h] = kKeyMax;
+        }
+        if (best_lab >= 0 && lab == best_lab) lab = -1;   // next pass finds the next label
+    }
+}
+// If t is one of the hot labels, min-updates its LDS entry and returns true.
+__device__ __forceinline__ bool hot_min(const int32_t (&hot)[kHot], unsigned long long* s_hotmin,
+                                        int32_t t, uint64_t key) {
+#pragma unroll
+    for (int h = 0; h < kHot; ++h) {
+        if (t == hot[h]) {
+            if (key < s_hotmin[h]) atomicMin(&s_hotmin[h], (unsigned long long)key);
+            return true;
+        }
+    }
+    return false;
+}
+
 // Dynamic tile id: tiles are numbered in the order workgroups start, so a tile
 // only ever waits on tiles that are already running (no deadlock).
 __device__ __forceinline__ uint32_t take_tile(Ctrl* ctrl, uint32_t* s_tile) {
@@ -113,6 +166,59 @@ __device__ __forceinline__ uint64_t tile_prefix(uint64_t* status, uint32_t tile,
     }
     __syncthreads();
     return *s_prefix;
+}
+
+// Exclusive scan of one value per thread over the workgroup; *total gets the
+// sum.  Every thread of the workgroup must call it (two barriers inside).
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t* s_w, uint64_t* total) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    uint64_t inc = x;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
+    }
+    if (lane == kWave - 1) s_w[wave] = inc;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+    const int nw = blockDim.x / kWave;
+    for (int i = 0; i < nw; ++i) {
+        const uint64_t v = s_w[i];
+        if (i < wave) pre += v;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - x;
+}
+
+// Stores 4 consecutive relabelled positions of a pass (q = position / 4) in
+// the layout OUT selects: int32 label pairs or 16-bit packed pairs.
+template <int OUT>
+__device__ __forceinline__ void store_group(int64_t q, int64_t m, const int32_t (&ra)[4],
+                                            const int32_t (&rb)[4], int32_t* __restrict__ ou,
+                                            int32_t* __restrict__ ov,
+                                            uint32_t* __restrict__ op16) {
+    const int64_t e0 = q * 4;
+    const bool full = e0 + 3 < m;
+    if constexpr (OUT == kOut32) {
+        if (full) {
+            reinterpret_cast<int4*>(ou)[q] = make_int4(ra[0], ra[1], ra[2], ra[3]);
+            reinterpret_cast<int4*>(ov)[q] = make_int4(rb[0], rb[1], rb[2], rb[3]);
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (e0 + k < m) { ou[e0 + k] = ra[k]; ov[e0 + k] = rb[k]; }
+        }
+    } else if constexpr (OUT == kOut16) {
+        uint32_t pk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pk[k] = (uint32_t)ra[k] | ((uint32_t)rb[k] << 16);
+        if (full) {
+            reinterpret_cast<uint4*>(op16)[q] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (e0 + k < m) op16[e0 + k] = pk[k];
+        }
+    }
 }
 
 }  // namespace msf
