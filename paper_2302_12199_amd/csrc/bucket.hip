@@ -19,9 +19,9 @@
 //            stream and where each run starts in it
 //   label    (after hook / jump / root scan) one workgroup per bucket: the
 //            bucket's labels in LDS, the index stream in, the labels out
-//   pass     one workgroup per tile: its runs of labels are gathered into LDS
-//            in tile-block order; each edge reads its two labels there, and
-//            the pass writes the relabelled layout and runs the next round's
+//   pass     per tile: its runs of labels are gathered into LDS in
+//            tile-block order; each edge reads its two labels there, and the
+//            pass writes the relabelled layout and runs the next round's
 //            lightest-edge search
 #include <algorithm>
 
@@ -43,7 +43,9 @@ int64_t ntiles(int64_t m) { return (m + kBucketTile - 1) >> kBucketTileShift; }
 constexpr int kGroups = (int)(kBucketTile / 4 / kBucketThreads);   // 4-edge groups per thread
 constexpr uint32_t kArcMask = (uint32_t)kTileArcs - 1;
 constexpr int kInFlight = 16;                                       // gathers per lane in flight
-constexpr uint32_t kPassGrid = 1024;                                // workgroups of the pass
+constexpr uint32_t kPassGrid = 2048;                                // workgroups of the pass
+constexpr int kPassThreads = 512;     // two pass workgroups fit a CU (LDS, registers)
+constexpr int kPassParts = (int)(kBucketTile / 4 / kPassThreads / kGroups);   // edge parts per tile
 
 template <typename T, typename V>
 __device__ __forceinline__ void load4(const T* __restrict__ p, int64_t q, int64_t e1, T (&x)[4]) {
@@ -61,13 +63,13 @@ __device__ __forceinline__ bool in_range(int32_t a, int32_t b, int64_t n) {
     return (uint32_t)a < (uint64_t)n && (uint32_t)b < (uint64_t)n;
 }
 
-// Largest k in [0, 1024) with a[k] <= x (a non-decreasing, a[0] <= x): ten
+// Largest k in [0, kBucketMax) with a[k] <= x (a non-decreasing, a[0] <= x): ten
 // fixed steps, so a lane's searches interleave.  With empty runs (equal
 // starts) it lands on the one run that holds slot x.
 __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t x) {
     uint32_t lo = 0;
 #pragma unroll
-    for (uint32_t step = kBucketThreads / 2; step > 0; step >>= 1)
+    for (uint32_t step = kBucketMax / 2; step > 0; step >>= 1)
         lo = a[lo + step] <= x ? lo + step : lo;
     return lo;
 }
@@ -337,15 +339,16 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_label(
 
 // ------------------------------------------------------------------- pass
 
-// One workgroup per tile: slot x of the tile block holds the arc whose label
-// is relab[base[b] + offt[t][b] + (x - run start of b)], b the bucket whose run
+// Workgroups of 512 threads (two fit a CU) take tiles grid-stride.  Slot x
+// of a tile block holds the arc whose label is
+// relab[base[b] + offt[t][b] + (x - run start of b)], b the bucket whose run
 // holds x.  The labels are gathered into LDS in block order; an edge finds
 // its two at the places recorded in rank[].  Then, as the plain relabelling
 // pass does: dead edges (self-loops, equal labels) are written as (0, 0),
 // live ones as label pairs, and take part in the next round's lightest-edge
 // search with key (w << 32 | position).
 template <int OUT>
-__global__ __launch_bounds__(kBucketThreads) void k_bk_pass(
+__global__ __launch_bounds__(kPassThreads) void k_bk_pass(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
     int64_t m, int64_t n, uint32_t nb, uint32_t nt, const uint32_t* __restrict__ meta,
     const uint32_t* __restrict__ offt, const uint64_t* __restrict__ base,
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_pass(
     __shared__ uint64_t s_src[kBucketMax];
     __shared__ uint32_t s_na;
     __shared__ unsigned long long s_hotmin[kHot];  // lightest edges of the hot labels in the tile
-    __shared__ uint64_t s_w[kBucketThreads / kWave];
+    __shared__ uint64_t s_w[kPassThreads / kWave];
     const int tid = threadIdx.x;
     const uint64_t narcs = 2 * (uint64_t)m;
     uint32_t kept = 0;
@@ -371,104 +374,110 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_pass(
     // tiles are taken grid-stride, so the live-edge count costs one atomic
     // per workgroup (same-address atomics queue at ~13 ns each)
     for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
-    if (tid < (int)nb) {
-        const int64_t j = (int64_t)t * nb + tid;
-        const uint32_t mt = meta[j];
-        s_rs[tid] = mt & 0xffff;
-        s_src[tid] = base[tid] + offt[j];
-        if (tid == (int)nb - 1) s_na = std::min((mt & 0xffff) + (mt >> 16), (uint32_t)kTileArcs);
-    } else {
-        s_rs[tid] = 0xffffffffu;   // past the last bucket: never <= a slot
-        s_src[tid] = 0;
-    }
-    __syncthreads();
-    const uint32_t na = s_na;
-    for (uint32_t x0 = tid; x0 < na; x0 += kInFlight * kBucketThreads) {
-        uint32_t val[kInFlight];
-#pragma unroll
-        for (int k = 0; k < kInFlight; ++k) {
-            const uint32_t x = x0 + k * kBucketThreads;
-            val[k] = 0;
-            if (x < na) {
-                const uint32_t b = last_le(s_rs, x);
-                const uint64_t i = s_src[b] + (x - s_rs[b]);
-                if (i < narcs) val[k] = relab[i];
+        const int64_t e0 = (int64_t)t << kBucketTileShift;
+        const int64_t e1 = e0 + kBucketTile < m ? e0 + kBucketTile : m;
+        for (int bk = tid; bk < kBucketMax; bk += kPassThreads) {
+            if (bk < (int)nb) {
+                const int64_t j = (int64_t)t * nb + bk;
+                const uint32_t mt = meta[j];
+                s_rs[bk] = mt & 0xffff;
+                s_src[bk] = base[bk] + offt[j];
+                if (bk == (int)nb - 1) s_na = std::min((mt & 0xffff) + (mt >> 16), (uint32_t)kTileArcs);
+            } else {
+                s_rs[bk] = 0xffffffffu;   // past the last bucket: never <= a slot
+                s_src[bk] = 0;
             }
         }
+        __syncthreads();
+        const uint32_t na = s_na;
+        for (uint32_t x0 = tid; x0 < na; x0 += kInFlight * kPassThreads) {
+            uint32_t val[kInFlight];
 #pragma unroll
-        for (int k = 0; k < kInFlight; ++k) {
-            const uint32_t x = x0 + k * kBucketThreads;
-            if (x < na) s_lab[x] = val[k];
-        }
-    }
-    __syncthreads();
-    if (tid < kHot) s_hotmin[tid] = kKeyMax;
-    __syncthreads();
-    const int64_t e0 = (int64_t)t << kBucketTileShift;
-    const int64_t e1 = e0 + kBucketTile < m ? e0 + kBucketTile : m;
-    int32_t a[kGroups][4], b[kGroups][4];
-    uint32_t ww[kGroups][4], rk[kGroups][4];
-#pragma unroll
-    for (int j = 0; j < kGroups; ++j) {
-        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
-        load4<int32_t, int4>(u, q, e1, a[j]);
-        load4<int32_t, int4>(v, q, e1, b[j]);
-        load4<uint32_t, uint4>(w, q, e1, ww[j]);
-        load4<uint32_t, uint4>(rank, q, e1, rk[j]);
-    }
-    // The lane's 2 x kGroups x 4 reads of best_next are issued together,
-    // then the atomics of the keys that beat them (every lane runs every step:
-    // wave_min_commit needs whole waves).
-    constexpr int kE = kGroups * 4;
-    int32_t ra[kE], rb[kE];
-    uint64_t key[kE];
-    bool ax[kE], ay[kE];
-#pragma unroll
-    for (int j = 0; j < kGroups; ++j) {
-        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int i = j * 4 + k;
-            ra[i] = rb[i] = 0;
-            key[i] = kKeyMax;
-            ax[i] = ay[i] = false;
-            const int64_t e = q * 4 + k;
-            const int32_t x = a[j][k], y = b[j][k];
-            if (e < e1 && in_range(x, y, n) && x != y) {
-                const uint32_t lx = s_lab[rk[j][k] & kArcMask];
-                const uint32_t ly = s_lab[(rk[j][k] >> 16) & kArcMask];
-                if (lx != ly) {
-                    if (lx >= (uint64_t)nn || ly >= (uint64_t)nn) {
-                        bad = true;
-                    } else {
-                        ra[i] = (int32_t)lx;
-                        rb[i] = (int32_t)ly;
-                        ++kept;
-                        key[i] = ((uint64_t)ww[j][k] << 32) | (uint64_t)e;
-                        ax[i] = !hot_min(hot, s_hotmin, ra[i], key[i]);
-                        ay[i] = !hot_min(hot, s_hotmin, rb[i], key[i]);
-                    }
+            for (int k = 0; k < kInFlight; ++k) {
+                const uint32_t x = x0 + k * kPassThreads;
+                val[k] = 0;
+                if (x < na) {
+                    const uint32_t b = last_le(s_rs, x);
+                    const uint64_t i = s_src[b] + (x - s_rs[b]);
+                    if (i < narcs) val[k] = relab[i];
                 }
             }
+#pragma unroll
+            for (int k = 0; k < kInFlight; ++k) {
+                const uint32_t x = x0 + k * kPassThreads;
+                if (x < na) s_lab[x] = val[k];
+            }
         }
-        if (q * 4 < e1) store_group<OUT>(q, m, *reinterpret_cast<int32_t(*)[4]>(&ra[j * 4]),
-                                         *reinterpret_cast<int32_t(*)[4]>(&rb[j * 4]), ou, ov, op16);
-    }
-    uint64_t cx[kE], cy[kE];
+        __syncthreads();
+        if (tid < kHot) s_hotmin[tid] = kKeyMax;
+        __syncthreads();
+        // the tile's edges in two parts of kGroups x 4 per lane (register budget)
+        for (int part = 0; part < kPassParts; ++part) {
+            const int64_t qbase = e0 / 4 + (int64_t)part * kGroups * kPassThreads + tid;
+            int32_t a[kGroups][4], b[kGroups][4];
+            uint32_t ww[kGroups][4], rk[kGroups][4];
 #pragma unroll
-    for (int i = 0; i < kE; ++i) {
-        cx[i] = ax[i] ? best_next[ra[i]] : 0;
-        cy[i] = ay[i] ? best_next[rb[i]] : 0;
-    }
+            for (int j = 0; j < kGroups; ++j) {
+                const int64_t q = qbase + (int64_t)j * kPassThreads;
+                load4<int32_t, int4>(u, q, e1, a[j]);
+                load4<int32_t, int4>(v, q, e1, b[j]);
+                load4<uint32_t, uint4>(w, q, e1, ww[j]);
+                load4<uint32_t, uint4>(rank, q, e1, rk[j]);
+            }
+            // The lane's 2 x kGroups x 4 reads of best_next are issued together,
+            // then the atomics of the keys that beat them (every lane runs every step:
+            // wave_min_commit needs whole waves).
+            constexpr int kE = kGroups * 4;
+            int32_t ra[kE], rb[kE];
+            uint64_t key[kE];
+            bool ax[kE], ay[kE];
 #pragma unroll
-    for (int i = 0; i < kE; ++i) {
-        wave_min_commit(best_next, ra[i], key[i], ax[i] && key[i] < cx[i]);
-        wave_min_commit(best_next, rb[i], key[i], ay[i] && key[i] < cy[i]);
-    }
-    __syncthreads();
-    if (tid < kHot && hot[tid] >= 0 && s_hotmin[tid] != kKeyMax)
-        atomic_min_key(&best_next[hot[tid]], s_hotmin[tid]);
-    __syncthreads();   // the next tile reuses the LDS tables
+            for (int j = 0; j < kGroups; ++j) {
+                const int64_t q = qbase + (int64_t)j * kPassThreads;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int i = j * 4 + k;
+                    ra[i] = rb[i] = 0;
+                    key[i] = kKeyMax;
+                    ax[i] = ay[i] = false;
+                    const int64_t e = q * 4 + k;
+                    const int32_t x = a[j][k], y = b[j][k];
+                    if (e < e1 && in_range(x, y, n) && x != y) {
+                        const uint32_t lx = s_lab[rk[j][k] & kArcMask];
+                        const uint32_t ly = s_lab[(rk[j][k] >> 16) & kArcMask];
+                        if (lx != ly) {
+                            if (lx >= (uint64_t)nn || ly >= (uint64_t)nn) {
+                                bad = true;
+                            } else {
+                                ra[i] = (int32_t)lx;
+                                rb[i] = (int32_t)ly;
+                                ++kept;
+                                key[i] = ((uint64_t)ww[j][k] << 32) | (uint64_t)e;
+                                ax[i] = !hot_min(hot, s_hotmin, ra[i], key[i]);
+                                ay[i] = !hot_min(hot, s_hotmin, rb[i], key[i]);
+                            }
+                        }
+                    }
+                }
+                if (q * 4 < e1) store_group<OUT>(q, m, *reinterpret_cast<int32_t(*)[4]>(&ra[j * 4]),
+                                                 *reinterpret_cast<int32_t(*)[4]>(&rb[j * 4]), ou, ov, op16);
+            }
+            uint64_t cx[kE], cy[kE];
+#pragma unroll
+            for (int i = 0; i < kE; ++i) {
+                cx[i] = ax[i] ? best_next[ra[i]] : 0;
+                cy[i] = ay[i] ? best_next[rb[i]] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < kE; ++i) {
+                wave_min_commit(best_next, ra[i], key[i], ax[i] && key[i] < cx[i]);
+                wave_min_commit(best_next, rb[i], key[i], ay[i] && key[i] < cy[i]);
+            }
+        }
+        __syncthreads();
+        if (tid < kHot && hot[tid] >= 0 && s_hotmin[tid] != kKeyMax)
+            atomic_min_key(&best_next[hot[tid]], s_hotmin[tid]);
+        __syncthreads();   // the next tile reuses the LDS tables
     }
     uint64_t tot;
     (void)block_excl_scan(kept, s_w, &tot);
@@ -555,12 +564,12 @@ void bucket_relabel(const BucketBuffers& B, const int32_t* u, const int32_t* v,
     hipLaunchKernelGGL(k_bk_hot, dim3(1), dim3(kWave), 0, s, relab, (uint64_t)(2 * m), B.hot);
     prof_end(h, s, 6.0 * arcs + 4.0 * n);
     h = prof_begin(K_BK_PASS, s);
-    const dim3 grid(std::min<uint32_t>(nt, kPassGrid));
+    const dim3 grid(std::min<uint32_t>(nt, kPassGrid)), pbl(kPassThreads);
     if (out == kOut16)
-        hipLaunchKernelGGL(k_bk_pass<kOut16>, grid, bl, 0, s, u, v, w, m, n, nb, nt, B.meta,
+        hipLaunchKernelGGL(k_bk_pass<kOut16>, grid, pbl, 0, s, u, v, w, m, n, nb, nt, B.meta,
                            B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, B.hot, ctrl);
     else
-        hipLaunchKernelGGL(k_bk_pass<kOut32>, grid, bl, 0, s, u, v, w, m, n, nb, nt, B.meta,
+        hipLaunchKernelGGL(k_bk_pass<kOut32>, grid, pbl, 0, s, u, v, w, m, n, nb, nt, B.meta,
                            B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, B.hot, ctrl);
     prof_end(h, s, 16.0 * m + 4.0 * arcs + (out == kOut16 ? 4.0 : 8.0) * m + 8.0 * cells +
                        8.0 * nn);
