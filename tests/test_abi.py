@@ -68,12 +68,26 @@ def test_rejects_null_pointers(msf):
 
 def test_rejects_bad_options(msf):
     for kw in [dict(algo=7), dict(pivot=9), dict(quantile=1.5), dict(quantile=float("nan")),
-               dict(sample_size=-1)]:
+               dict(sample_size=-1), dict(round0=3), dict(round0=-1)]:
         rc, _ = msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE, options=msf.make_options(**kw))
         assert rc == msf.EINVAL, kw
     o = msf.make_options()
     o.reserved[3] = 1
     assert msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE, options=o)[0] == msf.EINVAL
+
+
+def test_workspace_sizes_of_the_round0_choices(msf):
+    # the bucketed round 0 needs about 24 B per edge more, only where it applies
+    m, n = 1 << 22, 1 << 21
+    auto, edges = msf.workspace_bytes(m, n), msf.workspace_bytes(m, n, round0="edges")
+    assert auto == msf.workspace_bytes(m, n, round0="buckets")
+    assert 24 * m <= auto - edges <= 26 * m + (1 << 20)
+    for m, n in [(1 << 20, 1 << 16), ((1 << 22) - 1, 1 << 21), (1 << 22, (1 << 21) - 1),
+                 (1 << 22, (1 << 24) + 1)]:   # too small or too many vertices
+        assert msf.workspace_bytes(m, n) == msf.workspace_bytes(m, n, round0="edges")
+    for algo in ["boruvka", "filter"]:
+        assert msf.workspace_bytes(1 << 28, 1 << 24, algo=algo) > \
+            msf.workspace_bytes(1 << 28, 1 << 24, algo=algo, round0="edges")
 
 
 def test_workspace_too_small(msf):
