@@ -308,15 +308,16 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_label(
     const int64_t i0 = std::min((int64_t)base[bk], i1);
     const int64_t g0 = i0 / 8, g1 = (i1 + 7) / 8;
     const int64_t stride = blockDim.x;
-    for (int64_t gb = g0 + threadIdx.x; gb < g1; gb += 2 * stride) {
-        uint4 xv[2];
+    constexpr int kLabGroups = 8;   // 16-byte index groups per lane in flight
+    for (int64_t gb = g0 + threadIdx.x; gb < g1; gb += kLabGroups * stride) {
+        uint4 xv[kLabGroups];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < kLabGroups; ++j) {
             const int64_t g = gb + j * stride;
             if (g < g1) xv[j] = reinterpret_cast<const uint4*>(xs)[g];
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < kLabGroups; ++j) {
             const int64_t g = gb + j * stride;
             if (g >= g1) continue;
             const uint32_t wd[4] = {xv[j].x, xv[j].y, xv[j].z, xv[j].w};
