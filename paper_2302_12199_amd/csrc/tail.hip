@@ -11,6 +11,9 @@
 
 namespace msf {
 
+// Component pairs of the in-LDS dedup (64 KiB of keys: up to 128 components).
+constexpr uint32_t kTailPairSlots = 8192;
+
 __global__ __launch_bounds__(kTailThreads) void k_tail(
     const uint64_t* __restrict__ pairs, int64_t nn, uint32_t* list_xy0, uint64_t* list_key0,
     uint32_t* list_xy1, uint64_t* list_key1, const uint32_t* __restrict__ view_id,
@@ -25,6 +28,10 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(
     __shared__ int32_t arg[kTailMax];    // list index of best[]
     __shared__ int32_t par[kTailMax];
     __shared__ uint32_t s_cnt, s_live, s_found;
+    __shared__ uint64_t s_scan[kTailThreads / kWave];
+    __shared__ int16_t s_dense[kTailMax];        // next-round component id of a root
+    __shared__ int16_t s_inv[kTailMax];          // root of a next-round component id
+    __shared__ unsigned long long s_pairs[kTailPairSlots];   // lightest entry per component pair
     const int tid = threadIdx.x;
     if (tid == 0) s_cnt = 0;
     __syncthreads();
@@ -120,10 +127,55 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(
             }
         }
         if (tid == 0) s_cnt = 0;
+        // Dense ids of the next round's components (roots that have an edge).
+        const bool root = tid < nn && par[tid] == tid && best[tid] != kKeyMax;
+        uint64_t nd64;
+        const uint32_t d = (uint32_t)block_excl_scan(root ? 1 : 0, s_scan, &nd64);
+        const uint32_t nd = (uint32_t)nd64;
+        if (root) { s_dense[tid] = (int16_t)d; s_inv[d] = (int16_t)tid; }
+        const bool dedup = nd >= 2 && (uint64_t)nd * (nd - 1) / 2 <= kTailPairSlots;
+        if (dedup)
+            for (uint32_t i = tid; i < nd * (nd - 1) / 2; i += kTailThreads) s_pairs[i] = kKeyMax;
         __syncthreads();
-        // Next round's list, in the other buffer: both ends mapped to their
-        // new roots, pairs inside one component dropped.
-        {
+        if (dedup) {
+            // Few components left: keep only the lightest entry per component
+            // pair (parallel edges are dropped, as the paper allows).
+            for (uint32_t i = tid; i < L; i += kTailThreads) {
+                const uint32_t xy = list_xy[i];
+                const int32_t x = par[xy & 0xffff], y = par[xy >> 16];
+                if (x == y) continue;
+                const uint32_t dx = (uint32_t)s_dense[x], dy = (uint32_t)s_dense[y];
+                const uint32_t lo = dx < dy ? dx : dy, hi = dx < dy ? dy : dx;
+                const uint64_t k = list_key[i];
+                unsigned long long* slot = &s_pairs[(hi * (hi - 1) / 2 + lo) & (kTailPairSlots - 1)];
+                if (k < *slot) atomicMin(slot, (unsigned long long)k);
+            }
+            __syncthreads();
+            uint32_t* xy_out = list_xy == list_xy0 ? list_xy1 : list_xy0;
+            uint64_t* key_out = list_key == list_key0 ? list_key1 : list_key0;
+            const int wave = tid / kWave, lane = tid % kWave;
+            for (uint32_t y = 1 + wave; y < nd; y += kTailThreads / kWave) {
+                const uint32_t row = y * (y - 1) / 2;
+                for (uint32_t x0 = 0; x0 < y; x0 += kWave) {
+                    const uint32_t x = x0 + lane;
+                    const uint64_t k = x < y ? s_pairs[row + x] : kKeyMax;
+                    const uint64_t occ = __ballot(k != kKeyMax);
+                    if (occ == 0) continue;
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(occ));
+                    base = __shfl(base, 0, kWave);
+                    if (k != kKeyMax) {
+                        const uint32_t j = base + lanes_below(occ);
+                        xy_out[j] = (uint32_t)(uint16_t)s_inv[x] | ((uint32_t)(uint16_t)s_inv[y] << 16);
+                        key_out[j] = k;
+                    }
+                }
+            }
+            list_xy = xy_out;
+            list_key = key_out;
+        } else {
+            // Next round's list, in the other buffer: both ends mapped to
+            // their new roots, pairs inside one component dropped.
             uint32_t* xy_out = list_xy == list_xy0 ? list_xy1 : list_xy0;
             uint64_t* key_out = list_key == list_key0 ? list_key1 : list_key0;
             const int wave = tid / kWave, lane = tid % kWave;
