@@ -44,6 +44,7 @@ constexpr int kGroups = (int)(kBucketTile / 4 / kBucketThreads);   // 4-edge gro
 constexpr uint32_t kArcMask = (uint32_t)kTileArcs - 1;
 constexpr int kInFlight = 16;                                       // gathers per lane in flight
 constexpr uint32_t kPassGrid = 2048;                                // workgroups of the pass
+constexpr uint32_t kScatterGrid = 512;                              // workgroups of the scatter
 constexpr int kPassThreads = 512;     // two pass workgroups fit a CU (LDS, registers)
 constexpr int kPassParts = (int)(kBucketTile / 4 / kPassThreads / kGroups);   // edge parts per tile
 
@@ -119,82 +120,106 @@ bool bucket_usable(const BucketBuffers& B, int64_t m, int64_t n) {
 // Arc of endpoint x of edge e (in tile block order): w << 32 | (e - e0) << 14
 // | x mod 2^14.  An edge whose ids are out of range raises kErrRange and, like a
 // self-loop, has no arcs.  rank[e] = places of its two arcs in the block.
+__device__ __forceinline__ void load_ends_of_tile(const int32_t* __restrict__ u,
+                                                  const int32_t* __restrict__ v, int64_t m,
+                                                  uint32_t t, int32_t (&a)[kGroups][4],
+                                                  int32_t (&b)[kGroups][4]) {
+    const int64_t e0 = (int64_t)t << kBucketTileShift;
+    const int64_t e1 = e0 + kBucketTile < m ? e0 + kBucketTile : m;
+#pragma unroll
+    for (int j = 0; j < kGroups; ++j) {
+        const int64_t q = e0 / 4 + threadIdx.x + (int64_t)j * blockDim.x;
+        load4<int32_t, int4>(u, q, e1, a[j]);
+        load4<int32_t, int4>(v, q, e1, b[j]);
+    }
+}
+
+// Tiles are taken grid-stride; the next tile's endpoints are loaded while
+// the current tile's arcs are placed and written, a tile's weights while its
+// arcs are counted.
 __global__ __launch_bounds__(kBucketThreads) void k_bk_scatter(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
-    int64_t m, int64_t n, uint32_t nb, uint64_t* __restrict__ arcs, uint32_t* __restrict__ meta,
-    uint32_t* __restrict__ rank, Ctrl* ctrl) {
+    int64_t m, int64_t n, uint32_t nb, uint32_t nt, uint64_t* __restrict__ arcs,
+    uint32_t* __restrict__ meta, uint32_t* __restrict__ rank, Ctrl* ctrl) {
     __shared__ uint64_t s_stage[kTileArcs];
     __shared__ uint32_t s_cnt[kBucketMax];
     __shared__ uint32_t s_cur[kBucketMax];
     __shared__ uint64_t s_w[kBucketThreads / kWave];
-    const uint32_t t = blockIdx.x;
     const int tid = threadIdx.x;
-    if (tid < (int)nb) s_cnt[tid] = 0;
-    const int64_t e0 = (int64_t)t << kBucketTileShift;
-    const int64_t e1 = e0 + kBucketTile < m ? e0 + kBucketTile : m;
-    int32_t a[kGroups][4], b[kGroups][4];
-    uint32_t ww[kGroups][4];
-#pragma unroll
-    for (int j = 0; j < kGroups; ++j) {
-        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
-        load4<int32_t, int4>(u, q, e1, a[j]);
-        load4<int32_t, int4>(v, q, e1, b[j]);
-        load4<uint32_t, uint4>(w, q, e1, ww[j]);
-    }
-    __syncthreads();
     bool bad = false;
+    int32_t a[kGroups][4], b[kGroups][4];
+    if (blockIdx.x < nt) load_ends_of_tile(u, v, m, blockIdx.x, a, b);
+    for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int64_t e0 = (int64_t)t << kBucketTileShift;
+        const int64_t e1 = e0 + kBucketTile < m ? e0 + kBucketTile : m;
+        uint32_t ww[kGroups][4];
 #pragma unroll
-    for (int j = 0; j < kGroups; ++j) {
-        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
+        for (int j = 0; j < kGroups; ++j)
+            load4<uint32_t, uint4>(w, e0 / 4 + tid + (int64_t)j * blockDim.x, e1, ww[j]);
+        if (tid < (int)nb) s_cnt[tid] = 0;
+        __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (q * 4 + k >= e1) continue;
-            const int32_t x = a[j][k], y = b[j][k];
-            if (!in_range(x, y, n)) { bad = true; continue; }
-            if (x == y) continue;
-            atomicAdd(&s_cnt[(uint32_t)x >> kBucketShift], 1u);
-            atomicAdd(&s_cnt[(uint32_t)y >> kBucketShift], 1u);
+        for (int j = 0; j < kGroups; ++j) {
+            const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (q * 4 + k >= e1) continue;
+                const int32_t x = a[j][k], y = b[j][k];
+                if (!in_range(x, y, n)) { bad = true; continue; }
+                if (x == y) continue;
+                atomicAdd(&s_cnt[(uint32_t)x >> kBucketShift], 1u);
+                atomicAdd(&s_cnt[(uint32_t)y >> kBucketShift], 1u);
+            }
+        }
+        __syncthreads();
+        const uint32_t c = tid < (int)nb ? s_cnt[tid] : 0u;
+        uint64_t tot;
+        const uint32_t ex = (uint32_t)block_excl_scan(c, s_w, &tot);
+        if (tid < (int)nb) {
+            s_cur[tid] = ex;
+            meta[(int64_t)t * nb + tid] = ex | (c << 16);
+        }
+        __syncthreads();
+        int32_t a2[kGroups][4], b2[kGroups][4];
+        const uint32_t tn = t + gridDim.x;
+        if (tn < nt) load_ends_of_tile(u, v, m, tn, a2, b2);
+#pragma unroll
+        for (int j = 0; j < kGroups; ++j) {
+            const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
+            uint32_t rk[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                rk[k] = 0;
+                const int64_t e = q * 4 + k;
+                const int32_t x = a[j][k], y = b[j][k];
+                if (e >= e1 || !in_range(x, y, n) || x == y) continue;
+                const uint64_t hi = ((uint64_t)ww[j][k] << 32) | ((uint64_t)(e - e0) << kBucketShift);
+                const uint32_t px = atomicAdd(&s_cur[(uint32_t)x >> kBucketShift], 1u) & kArcMask;
+                const uint32_t py = atomicAdd(&s_cur[(uint32_t)y >> kBucketShift], 1u) & kArcMask;
+                s_stage[px] = hi | (uint64_t)(x & (kBucketWidth - 1));
+                s_stage[py] = hi | (uint64_t)(y & (kBucketWidth - 1));
+                rk[k] = px | (py << 16);
+            }
+            if (q * 4 + 3 < e1) {
+                reinterpret_cast<uint4*>(rank)[q] = make_uint4(rk[0], rk[1], rk[2], rk[3]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (q * 4 + k < e1) rank[q * 4 + k] = rk[k];
+            }
+        }
+        __syncthreads();
+        const uint32_t na = (uint32_t)(tot < (uint64_t)kTileArcs ? tot : (uint64_t)kTileArcs);
+        uint64_t* dst = arcs + (int64_t)t * kTileArcs;
+        for (uint32_t i = tid; i < na; i += blockDim.x) dst[i] = s_stage[i];
+        if (tn < nt) {
+#pragma unroll
+            for (int j = 0; j < kGroups; ++j)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { a[j][k] = a2[j][k]; b[j][k] = b2[j][k]; }
         }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrRange);
-    __syncthreads();
-    const uint32_t c = tid < (int)nb ? s_cnt[tid] : 0u;
-    uint64_t tot;
-    const uint32_t ex = (uint32_t)block_excl_scan(c, s_w, &tot);
-    if (tid < (int)nb) {
-        s_cur[tid] = ex;
-        meta[(int64_t)t * nb + tid] = ex | (c << 16);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kGroups; ++j) {
-        const int64_t q = e0 / 4 + tid + (int64_t)j * blockDim.x;
-        uint32_t rk[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            rk[k] = 0;
-            const int64_t e = q * 4 + k;
-            const int32_t x = a[j][k], y = b[j][k];
-            if (e >= e1 || !in_range(x, y, n) || x == y) continue;
-            const uint64_t hi = ((uint64_t)ww[j][k] << 32) | ((uint64_t)(e - e0) << kBucketShift);
-            const uint32_t px = atomicAdd(&s_cur[(uint32_t)x >> kBucketShift], 1u) & kArcMask;
-            const uint32_t py = atomicAdd(&s_cur[(uint32_t)y >> kBucketShift], 1u) & kArcMask;
-            s_stage[px] = hi | (uint64_t)(x & (kBucketWidth - 1));
-            s_stage[py] = hi | (uint64_t)(y & (kBucketWidth - 1));
-            rk[k] = px | (py << 16);
-        }
-        if (q * 4 + 3 < e1) {
-            reinterpret_cast<uint4*>(rank)[q] = make_uint4(rk[0], rk[1], rk[2], rk[3]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (q * 4 + k < e1) rank[q * 4 + k] = rk[k];
-        }
-    }
-    __syncthreads();
-    const uint32_t na = (uint32_t)(tot < (uint64_t)kTileArcs ? tot : (uint64_t)kTileArcs);
-    uint64_t* dst = arcs + (int64_t)t * kTileArcs;
-    for (uint32_t i = tid; i < na; i += blockDim.x) dst[i] = s_stage[i];
 }
 
 // ------------------------------------------------------------------ index
@@ -533,8 +558,8 @@ void bucket_minedge(const BucketBuffers& B, const int32_t* u, const int32_t* v,
     const double cells = (double)nb * nt, arcs = 2.0 * (double)m;
     const dim3 bl(kBucketThreads);
     int h = prof_begin(K_BK_SCATTER, s);
-    hipLaunchKernelGGL(k_bk_scatter, dim3(nt), bl, 0, s, u, v, w, m, n, nb, B.arcs, B.meta,
-                       B.rank, ctrl);
+    hipLaunchKernelGGL(k_bk_scatter, dim3(std::min<uint32_t>(nt, kScatterGrid)), bl, 0, s, u, v,
+                       w, m, n, nb, nt, B.arcs, B.meta, B.rank, ctrl);
     prof_end(h, s, 12.0 * m + 8.0 * arcs + 4.0 * m + 4.0 * cells);
     h = prof_begin(K_BK_INDEX, s);
     hipLaunchKernelGGL(k_transpose_u32, dim3(transpose_grid(nt, nb)), dim3(256), 0, s, B.meta,
