@@ -26,7 +26,9 @@ struct BucketBuffers {
     uint64_t* tmp;       // scan partial sums
     uint16_t* xs;        // [2m] bucket-major: vertex in bucket of every arc
     uint32_t* rank;      // [m] places of the edge's two arcs in its tile block (u | v << 16)
-    int32_t* hot;        // [4] labels on very many arcs after round 0 (-1: none)
+    uint64_t* hotpre;    // [n + 2] hot flags of the round-1 labels, then their exclusive scan
+    uint64_t* hottmp;    // scan partial sums
+    mutable int64_t hotn;  // labels of the last hot-first renumbering (hotpre[hotn] = hot count)
     int64_t mcap, ncap;  // the largest graph the buffers were carved for
 };
 
@@ -46,6 +48,11 @@ void bucket_sample_locality(const int32_t* u, const int32_t* v, int64_t m, Ctrl*
 void bucket_minedge(const BucketBuffers& B, const int32_t* u, const int32_t* v,
                     const uint32_t* w, int64_t m, int64_t n, uint64_t* best, Ctrl* ctrl,
                     hipStream_t s);
+// Renumbers the round-1 labels lab[0, nr) (values in [0, nn), -1 = none) so
+// that the labels on many sampled edge ends come first.
+void bucket_hot_first(const BucketBuffers& B, const int32_t* u, const int32_t* v, int64_t m,
+                      int32_t* lab, int64_t nr, int64_t nn, hipStream_t s);
+
 // Relabel every edge through M (round-0 vertex -> next label), write the
 // OUT layout (kOut32 or kOut16; dead edges as (0, 0)), count the live edges
 // into ctrl->m_next and run the next round's lightest-edge search into

@@ -8,13 +8,13 @@
 // L2.  Here every random access goes to LDS instead, and global memory is
 // only streamed or read in runs:
 //
-//   scatter  one workgroup per tile of 2^13 edges: the tile's arcs (one per
-//            endpoint) are sorted by vertex bucket (2^14 vertices) in LDS and
-//            written as one contiguous block; meta[t][b] = (run start, length)
+//   scatter  per tile of 2^13 edges: the tile's arcs (one per endpoint) are
+//            sorted by vertex bucket (2^14 vertices) in LDS and written as one
+//            contiguous block; meta[t][b] = (run start, length)
 //   index    meta transposed to bucket-major; bucket totals; their scan
 //   min      one workgroup per bucket: its runs (one per tile) are read 1024
-//            runs at a time, each arc's lane found by a binary search over the
-//            batch's run prefix; the minimum key per vertex is kept in LDS.
+//            runs at a time, each arc's lane found by a branchless search over
+//            the batch's run prefix; the minimum key per vertex is kept in LDS.
 //            It also writes the arcs' vertex indices as one bucket-major
 //            stream and where each run starts in it
 //   label    (after hook / jump / root scan) one workgroup per bucket: the
@@ -27,6 +27,7 @@
 
 #include "bucket.h"
 #include "host.h"
+#include "launch.h"
 #include "prim.h"
 
 namespace msf {
@@ -43,9 +44,11 @@ int64_t ntiles(int64_t m) { return (m + kBucketTile - 1) >> kBucketTileShift; }
 constexpr int kGroups = (int)(kBucketTile / 4 / kBucketThreads);   // 4-edge groups per thread
 constexpr uint32_t kArcMask = (uint32_t)kTileArcs - 1;
 constexpr int kInFlight = 16;                                       // gathers per lane in flight
+constexpr int kHotSample = 8192;                                    // edge ends sampled for hot labels
+constexpr uint32_t kHotIds = 4096;                                  // labels whose minima stay in LDS
 constexpr uint32_t kPassGrid = 2048;                                // workgroups of the pass
 constexpr uint32_t kScatterGrid = 512;                              // workgroups of the scatter
-constexpr int kPassThreads = 512;     // two pass workgroups fit a CU (LDS, registers)
+constexpr int kPassThreads = 1024;    // one pass workgroup per CU (LDS)
 constexpr int kPassParts = (int)(kBucketTile / 4 / kPassThreads / kGroups);   // edge parts per tile
 
 template <typename T, typename V>
@@ -74,7 +77,7 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t* a, uint32_t x) {
         lo = a[lo + step] <= x ? lo + step : lo;
     return lo;
 }
-static_assert(kBucketMax == kBucketThreads, "run tables are searched over kBucketThreads entries");
+static_assert(kBucketMax == kBucketThreads, "a batch of runs has one entry per thread");
 
 }  // namespace
 
@@ -104,7 +107,9 @@ size_t bucket_carve(char* ws, int64_t m, int64_t n, BucketBuffers* B) {
     b.tmp = (uint64_t*)take(scan_levels_bytes(nb));
     b.xs = (uint16_t*)take((size_t)(2 * m + 64) * 2);   // 8-index groups may read past the end
     b.rank = (uint32_t*)take((size_t)m * 4 + 16);
-    b.hot = (int32_t*)take(kHot * 4);
+    b.hotpre = (uint64_t*)take((size_t)(n + 2) * 8);
+    b.hottmp = (uint64_t*)take(scan_levels_bytes(n + 1));
+    b.hotn = -1;
     b.mcap = m;
     b.ncap = n;
     if (B) *B = b;
@@ -365,7 +370,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_label(
 
 // ------------------------------------------------------------------- pass
 
-// Workgroups of 512 threads (two fit a CU) take tiles grid-stride.  Slot x
+// Workgroups of 1024 threads take tiles grid-stride.  Slot x
 // of a tile block holds the arc whose label is
 // relab[base[b] + offt[t][b] + (x - run start of b)], b the bucket whose run
 // holds x.  The labels are gathered into LDS in block order; an edge finds
@@ -380,23 +385,22 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
     const uint32_t* __restrict__ offt, const uint64_t* __restrict__ base,
     const uint32_t* __restrict__ relab, const uint32_t* __restrict__ rank,
     int32_t* __restrict__ ou, int32_t* __restrict__ ov, uint32_t* __restrict__ op16,
-    uint64_t* __restrict__ best_next, int64_t nn, const int32_t* __restrict__ hot_in, Ctrl* ctrl) {
+    uint64_t* __restrict__ best_next, int64_t nn, const uint64_t* __restrict__ hot_count,
+    Ctrl* ctrl) {
     __shared__ uint32_t s_lab[kTileArcs];
     __shared__ uint32_t s_rs[kBucketMax];
     __shared__ uint64_t s_src[kBucketMax];
     __shared__ uint32_t s_na;
-    __shared__ unsigned long long s_hotmin[kHot];  // lightest edges of the hot labels in the tile
+    __shared__ unsigned long long s_hmin[kHotIds];   // minima of the labels below kh
     __shared__ uint64_t s_w[kPassThreads / kWave];
     const int tid = threadIdx.x;
     const uint64_t narcs = 2 * (uint64_t)m;
     uint32_t kept = 0;
     bool bad = false;
-    // After round 0 of a skewed graph most edges touch a few huge
-    // components: the hot labels (found once, by k_bk_hot) have their minima
-    // taken in LDS and merged once per tile.
-    int32_t hot[kHot];
-#pragma unroll
-    for (int h = 0; h < kHot; ++h) hot[h] = hot_in[h];
+    // The hot labels were renumbered first (k_hot_*): the minima of labels
+    // below kh are taken in LDS and merged once per workgroup.
+    const uint32_t kh = hot_count ? (uint32_t)std::min<uint64_t>(*hot_count, (uint64_t)kHotIds) : 0u;
+    for (uint32_t i = tid; i < kh; i += kPassThreads) s_hmin[i] = kKeyMax;
     // tiles are taken grid-stride, so the live-edge count costs one atomic
     // per workgroup (same-address atomics queue at ~13 ns each)
     for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
@@ -435,7 +439,6 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
             }
         }
         __syncthreads();
-        if (tid < kHot) s_hotmin[tid] = kKeyMax;
         __syncthreads();
         // the tile's edges in two parts of kGroups x 4 per lane (register budget)
         for (int part = 0; part < kPassParts; ++part) {
@@ -479,8 +482,12 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
                                 rb[i] = (int32_t)ly;
                                 ++kept;
                                 key[i] = ((uint64_t)ww[j][k] << 32) | (uint64_t)e;
-                                ax[i] = !hot_min(hot, s_hotmin, ra[i], key[i]);
-                                ay[i] = !hot_min(hot, s_hotmin, rb[i], key[i]);
+                                ax[i] = lx >= kh;
+                                ay[i] = ly >= kh;
+                                if (!ax[i] && key[i] < s_hmin[lx])
+                                    atomicMin(&s_hmin[lx], (unsigned long long)key[i]);
+                                if (!ay[i] && key[i] < s_hmin[ly])
+                                    atomicMin(&s_hmin[ly], (unsigned long long)key[i]);
                             }
                         }
                     }
@@ -500,27 +507,71 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
                 wave_min_commit(best_next, rb[i], key[i], ay[i] && key[i] < cy[i]);
             }
         }
-        __syncthreads();
-        if (tid < kHot && hot[tid] >= 0 && s_hotmin[tid] != kKeyMax)
-            atomic_min_key(&best_next[hot[tid]], s_hotmin[tid]);
         __syncthreads();   // the next tile reuses the LDS tables
     }
+    for (uint32_t i = tid; i < kh; i += kPassThreads)
+        if (s_hmin[i] != kKeyMax) atomic_min_key(&best_next[i], s_hmin[i]);
     uint64_t tot;
     (void)block_excl_scan(kept, s_w, &tot);
     if (tid == 0 && tot) atomicAdd((unsigned long long*)&ctrl->m_next, (unsigned long long)tot);
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrInternal);
 }
 
-// The kHot labels most frequent among 64 arcs sampled evenly over the
-// bucket-major label stream (each at least kHotMinCount of them), or -1.
-__global__ __launch_bounds__(kWave) void k_bk_hot(const uint32_t* __restrict__ relab,
-                                                  uint64_t narcs, int32_t* __restrict__ hot) {
-    __shared__ int32_t s_hot[kHot];
-    __shared__ unsigned long long s_min[kHot];
-    const uint64_t i = ((uint64_t)threadIdx.x * narcs + narcs / 2) / kWave;
-    hot_labels(i < narcs ? (int32_t)relab[i] : -1, s_hot, s_min);
+// Hot-first renumbering of the round-1 labels.  After round 0 of a skewed
+// graph a few thousand components carry a large share of the edge ends; the
+// relabelling pass keeps the minima of the smallest kHotIds labels in LDS, so
+// those components get the smallest labels.  A label is hot when it appears
+// at least twice among kHotSample edge ends sampled by a counter-based hash
+// (SplitMix64 output function of the sample index).  The new labels are a
+// permutation of [0, nn): hot labels first, in label order, then the others.
+
+// hot[l] = 1 for the hot labels (hot zeroed before).
+__global__ __launch_bounds__(kBucketThreads) void k_hot_sample(
+    const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m,
+    const int32_t* __restrict__ lab, uint64_t* __restrict__ hot) {
+    __shared__ uint32_t s[kHotSample];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kHotSample; i += kBucketThreads) {
+        uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x243F6A8885A308D3ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const int64_t e = (int64_t)__umul64hi(z, (uint64_t)m);
+        const int32_t x = (i & 1) ? v[e] : u[e], y = (i & 1) ? u[e] : v[e];
+        const int32_t l = x != y ? lab[x] : -1;
+        s[i] = l >= 0 ? (uint32_t)l : 0xffffffffu;
+    }
     __syncthreads();
-    if (threadIdx.x < kHot) hot[threadIdx.x] = s_hot[threadIdx.x];
+    for (int k = 2; k <= kHotSample; k <<= 1) {              // bitonic sort, ascending
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = tid; i < kHotSample; i += kBucketThreads) {
+                const int p = i ^ jj;
+                if (p > i) {
+                    const uint32_t a = s[i], b = s[p];
+                    if (((i & k) == 0) == (a > b)) { s[i] = b; s[p] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = 1 + tid; i < kHotSample; i += kBucketThreads) {
+        const uint32_t l = s[i];
+        if (l != 0xffffffffu && l == s[i - 1] && (i == 1 || s[i - 2] != l)) hot[l] = 1;
+    }
+}
+
+// lab[x] <- new label of lab[x]; pre = exclusive scan of hot[] (pre[nn] = H).
+__global__ __launch_bounds__(kBlock) void k_hot_relabel(int32_t* __restrict__ lab, int64_t nr,
+                                                        const uint64_t* __restrict__ pre,
+                                                        int64_t nn) {
+    const uint64_t H = pre[nn];
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nr;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t l = lab[x];
+        if (l < 0 || l >= nn) continue;
+        const uint64_t r = pre[l], hot = pre[l + 1] - r;
+        lab[x] = (int32_t)(hot ? r : H + ((uint64_t)l - r));
+    }
 }
 
 // ctrl->aux[0] = how many of 4096 edges sampled evenly have |u - v| below the
@@ -542,6 +593,18 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_locality(const int32_t* _
 
 // -------------------------------------------------------------- launchers
 
+void bucket_hot_first(const BucketBuffers& B, const int32_t* u, const int32_t* v, int64_t m,
+                      int32_t* lab, int64_t nr, int64_t nn, hipStream_t s) {
+    const int h = prof_begin(K_BK_INDEX, s);
+    B.hotn = nn;
+    launch_fill_u64(B.hotpre, nn + 1, 0, s);
+    hipLaunchKernelGGL(k_hot_sample, dim3(1), dim3(kBucketThreads), 0, s, u, v, m, lab, B.hotpre);
+    launch_scan_u64(B.hotpre, nn, B.hottmp, B.hotpre + nn, s);
+    const int64_t g = std::min<int64_t>((nr + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(k_hot_relabel, dim3((unsigned)g), dim3(kBlock), 0, s, lab, nr, B.hotpre, nn);
+    prof_end(h, s, 8.0 * nr + 24.0 * nn);
+}
+
 void bucket_sample_locality(const int32_t* u, const int32_t* v, int64_t m, Ctrl* ctrl,
                             hipStream_t s) {
     hipLaunchKernelGGL(k_bk_locality, dim3(1), dim3(kBucketThreads), 0, s, u, v, m, ctrl);
@@ -557,6 +620,7 @@ void bucket_minedge(const BucketBuffers& B, const int32_t* u, const int32_t* v,
     const uint32_t nb = (uint32_t)nbuckets(n), nt = (uint32_t)ntiles(m);
     const double cells = (double)nb * nt, arcs = 2.0 * (double)m;
     const dim3 bl(kBucketThreads);
+    B.hotn = -1;   // no hot-first renumbering yet in this solve
     int h = prof_begin(K_BK_SCATTER, s);
     hipLaunchKernelGGL(k_bk_scatter, dim3(std::min<uint32_t>(nt, kScatterGrid)), bl, 0, s, u, v,
                        w, m, n, nb, nt, B.arcs, B.meta, B.rank, ctrl);
@@ -587,16 +651,17 @@ void bucket_relabel(const BucketBuffers& B, const int32_t* u, const int32_t* v,
     const dim3 bl(kBucketThreads);
     int h = prof_begin(K_BK_LABEL, s);
     hipLaunchKernelGGL(k_bk_label, dim3(nb), bl, 0, s, B.xs, B.base, n, 2 * m, M, relab);
-    hipLaunchKernelGGL(k_bk_hot, dim3(1), dim3(kWave), 0, s, relab, (uint64_t)(2 * m), B.hot);
     prof_end(h, s, 6.0 * arcs + 4.0 * n);
+    // the count of renumbered hot labels, if this solve renumbered them
+    const uint64_t* hot_count = B.hotn >= 0 && B.hotn <= nn ? B.hotpre + B.hotn : nullptr;
     h = prof_begin(K_BK_PASS, s);
     const dim3 grid(std::min<uint32_t>(nt, kPassGrid)), pbl(kPassThreads);
     if (out == kOut16)
         hipLaunchKernelGGL(k_bk_pass<kOut16>, grid, pbl, 0, s, u, v, w, m, n, nb, nt, B.meta,
-                           B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, B.hot, ctrl);
+                           B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, hot_count, ctrl);
     else
         hipLaunchKernelGGL(k_bk_pass<kOut32>, grid, pbl, 0, s, u, v, w, m, n, nb, nt, B.meta,
-                           B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, B.hot, ctrl);
+                           B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, hot_count, ctrl);
     prof_end(h, s, 16.0 * m + 4.0 * arcs + (out == kOut16 ? 4.0 : 8.0) * m + 8.0 * cells +
                        8.0 * nn);
 }

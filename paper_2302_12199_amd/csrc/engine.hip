@@ -206,6 +206,10 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         }
         const uint64_t live = hc->live, found = hc->found;
         const int64_t nn = (int64_t)hc->n_next;
+        // Before the bucketed relabelling pass: the round-1 labels on many
+        // edge ends are renumbered first (their minima then stay in LDS).
+        if (bucketed && mode == kOrig && nn > kTailMax && !always_compact())
+            bucket_hot_first(B.bk, view.u, view.v, view.len, lab, nr, nn, s);
         prof_add(K_HOOK, 17.0 * live);
         prof_add(K_SCAN_ROOTS, 4.0 * nn);
         prof_add(K_LABEL, 8.0 * nn);
