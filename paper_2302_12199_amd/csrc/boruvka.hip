@@ -362,7 +362,9 @@ __device__ __forceinline__ void load_group(const View& g, int64_t q, int64_t m, 
 // positions.  Each lane handles kPassGroups groups of 4 consecutive positions
 // per step (16-byte vector loads, all issued before any is consumed).  The
 // map M (view labels -> next-round labels, nc entries) and the next round's
-// best[] can be staged in LDS when small.  OUT selects what is written:
+// best[] can be staged in LDS when small; LDS_M stages the first km entries of
+// M (all of it, or the prefix that fits: after a hot-first renumbering the
+// most used labels come first).  OUT selects what is written:
 // nothing (the caller composes maps instead), int32 label pairs, or packed
 // 16-bit label pairs.  Dead edges are written as (0, 0).  PAIR (last pass
 // before the tail): instead of the next minedge, keep the lightest edge of
@@ -373,16 +375,20 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
                                                      int32_t* __restrict__ ov,
                                                      uint32_t* __restrict__ op16,
                                                      uint64_t* __restrict__ best_next, int64_t nn,
-                                                     uint64_t* __restrict__ pairs, Ctrl* ctrl) {
+                                                     uint64_t* __restrict__ pairs, int64_t km,
+                                                     Ctrl* ctrl) {
     extern __shared__ uint64_t lds[];
     uint64_t* s_best = lds;                                        // nn entries (LDS_B)
-    int32_t* s_map = reinterpret_cast<int32_t*>(lds + (LDS_B ? nn : 0));  // nc entries (LDS_M)
+    int32_t* s_map = reinterpret_cast<int32_t*>(lds + (LDS_B ? nn : 0));  // km entries (LDS_M)
     if constexpr (LDS_B)
         for (int64_t i = threadIdx.x; i < nn; i += blockDim.x) s_best[i] = kKeyMax;
     if constexpr (LDS_M)
-        for (int64_t i = threadIdx.x; i < nc; i += blockDim.x) s_map[i] = M[i];
+        for (int64_t i = threadIdx.x; i < km; i += blockDim.x) s_map[i] = M[i];
     if constexpr (LDS_B || LDS_M) __syncthreads();
-    const int32_t* map = LDS_M ? s_map : M;
+    auto map = [&](int32_t a) -> int32_t {
+        if constexpr (LDS_M) return a < km ? s_map[a] : M[a];
+        else return M[a];
+    };
     uint64_t* bst = LDS_B ? s_best : best_next;
 
     constexpr int G = kPassGroups;
@@ -401,7 +407,7 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
         if (p < m) {
             int32_t a0, b0;
             load_ends<IN>(g, p, a0, b0);
-            if (a0 != b0) lab = map[a0];
+            if (a0 != b0) lab = map(a0);
         }
         hot_labels(lab, s_hot, s_hotmin);
     }
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
                 bool act = false;
                 uint64_t key = kKeyMax;
                 if (q < groups && a[j][k] != b[j][k]) {   // equal stored labels stay a self-loop
-                    const int32_t x = map[a[j][k]], y = map[b[j][k]];
+                    const int32_t x = map(a[j][k]), y = map(b[j][k]);
                     if (x != y) {
                         ra[k] = x;
                         rb[k] = y;
@@ -631,7 +637,9 @@ void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_
 }
 
 // LDS budget of one pass workgroup (two fit in a CU's 160 KiB).
-constexpr int64_t kPassLds = 72 * 1024;
+constexpr int64_t kPassLds = 78 * 1024;
+// Smallest map prefix worth staging when the whole map does not fit.
+constexpr int64_t kMapPrefixMin = 1024;
 
 // Raises the dynamic-LDS limit of one pass instantiation once (needed above
 // 64 KiB); returns false when the runtime refuses.
@@ -664,31 +672,33 @@ static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* 
                           uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
                           Ctrl* ctrl, hipStream_t s) {
     const bool lds_on = lds_enabled();
-    bool ldsb = lds_on && !PAIR && nn * 8 <= kPassLds;
-    bool ldsm = lds_on && nc * 4 + (ldsb ? nn * 8 : 0) <= kPassLds;
-    size_t lds = (ldsb ? nn * 8 : 0) + (ldsm ? nc * 4 : 0);
-    bool ok = true;
-    if (ldsb && ldsm) ok = allow_lds<IN, OUT, true, true, PAIR>(lds);
-    else if (ldsb) ok = allow_lds<IN, OUT, false, true, PAIR>(lds);
-    else if (ldsm) ok = allow_lds<IN, OUT, true, false, PAIR>(lds);
-    if (!ok) {   // stay within 64 KiB
-        ldsb = lds_on && !PAIR && nn * 8 <= 64 * 1024;
-        ldsm = lds_on && nc * 4 + (ldsb ? nn * 8 : 0) <= 64 * 1024;
-        lds = (ldsb ? nn * 8 : 0) + (ldsm ? nc * 4 : 0);
+    bool ldsb = false;
+    int64_t km = 0;
+    size_t lds = 0;
+    for (int64_t budget : {kPassLds, (int64_t)64 * 1024}) {   // the second if the runtime refuses
+        ldsb = lds_on && !PAIR && nn * 8 <= budget;
+        const int64_t left = budget - (ldsb ? nn * 8 : 0);
+        km = !lds_on ? 0 : nc * 4 <= left ? nc : (left / 4 >= kMapPrefixMin ? left / 4 : 0);
+        lds = (ldsb ? nn * 8 : 0) + km * 4;
+        bool ok = true;
+        if (ldsb && km) ok = allow_lds<IN, OUT, true, true, PAIR>(lds);
+        else if (ldsb) ok = allow_lds<IN, OUT, false, true, PAIR>(lds);
+        else if (km) ok = allow_lds<IN, OUT, true, false, PAIR>(lds);
+        if (ok) break;
     }
     const int64_t groups = (g.len + 3) / 4;
     int64_t want = (groups + (int64_t)kPassBlock * kPassGroups - 1) / ((int64_t)kPassBlock * kPassGroups);
     const int64_t cap = lds ? 512 : 1024;   // LDS variants: two workgroups per CU
     const unsigned grid = (unsigned)(want < 1 ? 1 : (want > cap ? cap : want));
     const dim3 bl(kPassBlock);
-    if (ldsb && ldsm)
-        hipLaunchKernelGGL((k_pass<IN, OUT, true, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl);
+    if (ldsb && km)
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, ctrl);
     else if (ldsb)
-        hipLaunchKernelGGL((k_pass<IN, OUT, false, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl);
-    else if (ldsm)
-        hipLaunchKernelGGL((k_pass<IN, OUT, true, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, ctrl);
+    else if (km)
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, ctrl);
     else
-        hipLaunchKernelGGL((k_pass<IN, OUT, false, false, PAIR>), dim3(grid), bl, 0, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, false, PAIR>), dim3(grid), bl, 0, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, ctrl);
 }
 
 // Streaming pass; returns false for a layout/output pair it does not support.
