@@ -69,7 +69,7 @@ typedef enum {
  *   MSF_ROUND0_BUCKETS  by vertex buckets wherever the graph qualifies.
  * By buckets, the edges are split once into per-endpoint arcs grouped by 2^14-vertex
  * buckets; the minimum and the relabelling then work on one bucket's vertices in LDS.
- * It costs msf_workspace_bytes about 24 extra bytes per edge. */
+ * It costs msf_workspace_bytes about 24 extra bytes per edge and 8 per vertex. */
 typedef enum { MSF_ROUND0_AUTO = 0, MSF_ROUND0_EDGES = 1, MSF_ROUND0_BUCKETS = 2 } msf_round0;
 
 /* Options; a NULL pointer means {MSF_ALGO_BORUVKA, MSF_PIVOT_MEDIAN, 0.5, seed 1,

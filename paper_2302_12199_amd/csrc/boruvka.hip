@@ -376,6 +376,7 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
                                                      uint32_t* __restrict__ op16,
                                                      uint64_t* __restrict__ best_next, int64_t nn,
                                                      uint64_t* __restrict__ pairs, int64_t km,
+                                                     const uint64_t* __restrict__ pair_hot,
                                                      Ctrl* ctrl) {
     extern __shared__ uint64_t lds[];
     uint64_t* s_best = lds;                                        // nn entries (LDS_B)
@@ -384,7 +385,14 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
         for (int64_t i = threadIdx.x; i < nn; i += blockDim.x) s_best[i] = kKeyMax;
     if constexpr (LDS_M)
         for (int64_t i = threadIdx.x; i < km; i += blockDim.x) s_map[i] = M[i];
-    if constexpr (LDS_B || LDS_M) __syncthreads();
+    // PAIR with pair_hot: the lightest edge of each pair among the first kp
+    // labels (hot first after a renumbering) is kept in LDS, after the map,
+    // and merged into the table once per workgroup.
+    unsigned long long* s_pair =
+        reinterpret_cast<unsigned long long*>(lds + (LDS_B ? nn : 0) + (LDS_M ? (km + 1) / 2 : 0));
+    const int64_t kp = PAIR && pair_hot ? (*pair_hot < kPairHot ? (int64_t)*pair_hot : kPairHot) : 0;
+    for (int64_t i = threadIdx.x; i < kp * (kp - 1) / 2; i += blockDim.x) s_pair[i] = kKeyMax;
+    if constexpr (LDS_B || LDS_M || PAIR) __syncthreads();
     auto map = [&](int32_t a) -> int32_t {
         if constexpr (LDS_M) return a < km ? s_map[a] : M[a];
         else return M[a];
@@ -451,7 +459,12 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
                         key = ((uint64_t)w[j][k] << 32) | (uint64_t)(q * 4 + k);
                         if constexpr (PAIR) {   // lightest edge per vertex pair, for the tail
                             const int64_t lo = x < y ? x : y, hi = x < y ? y : x;
-                            atomic_min_key(&pairs[hi * (hi - 1) / 2 + lo], key);
+                            const int64_t slot = hi * (hi - 1) / 2 + lo;
+                            if (hi < kp) {
+                                if (key < s_pair[slot]) atomicMin(&s_pair[slot], (unsigned long long)key);
+                            } else {
+                                atomic_min_key(&pairs[slot], key);
+                            }
                         }
                     }
                 }
@@ -476,6 +489,10 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
         __syncthreads();
         if (threadIdx.x < kHot && hot[threadIdx.x] >= 0 && s_hotmin[threadIdx.x] != kKeyMax)
             atomic_min_key(&bst[hot[threadIdx.x]], s_hotmin[threadIdx.x]);
+    } else {
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < kp * (kp - 1) / 2; i += blockDim.x)
+            if (s_pair[i] != kKeyMax) atomic_min_key(&pairs[i], s_pair[i]);
     }
     if constexpr (LDS_B) {
         __syncthreads();
@@ -629,6 +646,90 @@ void launch_compose(const int32_t* cmap, int64_t nc, const int32_t* label, int32
         hipLaunchKernelGGL(k_compose, dim3(grid_for(nc)), dim3(kBlock), 0, s, cmap, nc, label, out);
 }
 
+// Hot-first renumbering before the tail (nn <= kTailMax labels): one
+// workgroup samples kPreTailSample edge ends of the view (positions from the
+// SplitMix64 output function of the sample index), takes each end's label
+// lab[c] (c = the end's current vertex, through cmap when maps are composed),
+// sorts the samples in LDS, marks the labels seen at least twice as hot, and
+// writes the permutation hot labels first (perm[nn]) and their count (*hot).
+constexpr int kPreTailSample = 8192;
+
+template <int MODE>
+__global__ __launch_bounds__(kTailThreads) void k_hot_first_small(
+    View g, const int32_t* __restrict__ cmap, const int32_t* __restrict__ lab, int64_t nr,
+    int64_t nn, int32_t* __restrict__ perm, uint64_t* __restrict__ hot) {
+    __shared__ uint32_t s[kPreTailSample];
+    __shared__ uint32_t s_flag[kTailMax];
+    __shared__ uint64_t s_w[kTailThreads / kWave];
+    const int tid = threadIdx.x;
+    if (tid < kTailMax) s_flag[tid] = 0;
+    for (int i = tid; i < kPreTailSample; i += blockDim.x) {
+        uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x13198A2E03707344ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const int64_t e = (int64_t)__umul64hi(z, (uint64_t)g.len);
+        int32_t a, b;
+        load_ends<MODE>(g, e, a, b);
+        uint32_t sample = 0xffffffffu;
+        if (a != b) {
+            const int32_t ca = cmap ? cmap[a] : a, cb = cmap ? cmap[b] : b;
+            if (ca >= 0 && cb >= 0 && ca < nr && cb < nr) {
+                const int32_t la = lab[ca], lb = lab[cb];
+                const int32_t l = (i & 1) ? lb : la;
+                if (la != lb && l >= 0 && l < nn) sample = (uint32_t)l;
+            }
+        }
+        s[i] = sample;
+    }
+    __syncthreads();
+    for (int k = 2; k <= kPreTailSample; k <<= 1) {          // bitonic sort, ascending
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = tid; i < kPreTailSample; i += blockDim.x) {
+                const int p = i ^ jj;
+                if (p > i) {
+                    const uint32_t x = s[i], y = s[p];
+                    if (((i & k) == 0) == (x > y)) { s[i] = y; s[p] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = 1 + tid; i < kPreTailSample; i += blockDim.x) {
+        const uint32_t l = s[i];
+        if (l != 0xffffffffu && l == s[i - 1]) s_flag[l] = 1;
+    }
+    __syncthreads();
+    const uint32_t f = tid < nn ? s_flag[tid] : 0u;
+    uint64_t H;
+    const uint64_t r = block_excl_scan(f, s_w, &H);
+    if (tid < nn) perm[tid] = (int32_t)(f ? r : H + ((uint64_t)tid - r));
+    if (tid == 0) *hot = H;
+}
+
+__global__ __launch_bounds__(kBlock) void k_apply_perm(int32_t* __restrict__ lab, int64_t nr,
+                                                       const int32_t* __restrict__ perm,
+                                                       int64_t nn) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nr;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t l = lab[x];
+        if (l >= 0 && l < nn) lab[x] = perm[l];
+    }
+}
+
+void launch_hot_first_small(int mode, const View& g, const int32_t* cmap, int32_t* lab, int64_t nr,
+                            int64_t nn, int32_t* perm, uint64_t* hot, hipStream_t s) {
+    if (g.len <= 0 || nn > kTailMax) return;
+    const dim3 one(1), tb(kTailThreads);
+    switch (mode) {
+        case kOrig: hipLaunchKernelGGL(k_hot_first_small<kOrig>, one, tb, 0, s, g, cmap, lab, nr, nn, perm, hot); break;
+        case kFull32: hipLaunchKernelGGL(k_hot_first_small<kFull32>, one, tb, 0, s, g, cmap, lab, nr, nn, perm, hot); break;
+        case kFull16: hipLaunchKernelGGL(k_hot_first_small<kFull16>, one, tb, 0, s, g, cmap, lab, nr, nn, perm, hot); break;
+        default: hipLaunchKernelGGL(k_hot_first_small<kCompact>, one, tb, 0, s, g, cmap, lab, nr, nn, perm, hot); break;
+    }
+    hipLaunchKernelGGL(k_apply_perm, dim3(grid_for(nr)), dim3(kBlock), 0, s, lab, nr, perm, nn);
+}
+
 void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_t* label,
                        int64_t nr, const int32_t* orig_cur, int32_t* orig_next, int32_t* rep,
                        hipStream_t s) {
@@ -670,16 +771,18 @@ static bool lds_enabled() {
 template <int IN, int OUT, bool PAIR>
 static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* ou, int32_t* ov,
                           uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
-                          Ctrl* ctrl, hipStream_t s) {
+                          const uint64_t* pair_hot, Ctrl* ctrl, hipStream_t s) {
     const bool lds_on = lds_enabled();
     bool ldsb = false;
     int64_t km = 0;
     size_t lds = 0;
+    const int64_t ptab = PAIR && pair_hot && lds_on ? kPairHot * (kPairHot - 1) / 2 * 8 : 0;
+    if (!ptab) pair_hot = nullptr;
     for (int64_t budget : {kPassLds, (int64_t)64 * 1024}) {   // the second if the runtime refuses
         ldsb = lds_on && !PAIR && nn * 8 <= budget;
-        const int64_t left = budget - (ldsb ? nn * 8 : 0);
+        const int64_t left = budget - (ldsb ? nn * 8 : 0) - ptab - 8;
         km = !lds_on ? 0 : nc * 4 <= left ? nc : (left / 4 >= kMapPrefixMin ? left / 4 : 0);
-        lds = (ldsb ? nn * 8 : 0) + km * 4;
+        lds = (ldsb ? nn * 8 : 0) + (km + 1) / 2 * 8 + ptab;
         bool ok = true;
         if (ldsb && km) ok = allow_lds<IN, OUT, true, true, PAIR>(lds);
         else if (ldsb) ok = allow_lds<IN, OUT, false, true, PAIR>(lds);
@@ -692,37 +795,37 @@ static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* 
     const unsigned grid = (unsigned)(want < 1 ? 1 : (want > cap ? cap : want));
     const dim3 bl(kPassBlock);
     if (ldsb && km)
-        hipLaunchKernelGGL((k_pass<IN, OUT, true, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl);
     else if (ldsb)
-        hipLaunchKernelGGL((k_pass<IN, OUT, false, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl);
     else if (km)
-        hipLaunchKernelGGL((k_pass<IN, OUT, true, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl);
     else
-        hipLaunchKernelGGL((k_pass<IN, OUT, false, false, PAIR>), dim3(grid), bl, 0, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl);
 }
 
 // Streaming pass; returns false for a layout/output pair it does not support.
 // pairs != null: last pass before the tail (output kOutNone only).
 bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t nc, int32_t* ou,
                  int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
-                 Ctrl* ctrl, hipStream_t s) {
+                 const uint64_t* pair_hot, Ctrl* ctrl, hipStream_t s) {
     if (g.len <= 0) return true;
     if (pairs) {
         if (out != kOutNone) return false;
         switch (in_mode) {
-            case kOrig: pass_dispatch<kOrig, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl, s); return true;
-            case kFull32: pass_dispatch<kFull32, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl, s); return true;
-            case kFull16: pass_dispatch<kFull16, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl, s); return true;
-            default: pass_dispatch<kCompact, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, ctrl, s); return true;
+            case kOrig: pass_dispatch<kOrig, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, s); return true;
+            case kFull32: pass_dispatch<kFull32, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, s); return true;
+            case kFull16: pass_dispatch<kFull16, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, s); return true;
+            default: pass_dispatch<kCompact, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, s); return true;
         }
     }
     switch (in_mode * 3 + out) {
-        case kOrig * 3 + kOut32: pass_dispatch<kOrig, kOut32, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
-        case kOrig * 3 + kOut16: pass_dispatch<kOrig, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
-        case kFull32 * 3 + kOutNone: pass_dispatch<kFull32, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
-        case kFull32 * 3 + kOut16: pass_dispatch<kFull32, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
-        case kFull16 * 3 + kOutNone: pass_dispatch<kFull16, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
-        case kCompact * 3 + kOutNone: pass_dispatch<kCompact, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, ctrl, s); return true;
+        case kOrig * 3 + kOut32: pass_dispatch<kOrig, kOut32, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
+        case kOrig * 3 + kOut16: pass_dispatch<kOrig, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
+        case kFull32 * 3 + kOutNone: pass_dispatch<kFull32, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
+        case kFull32 * 3 + kOut16: pass_dispatch<kFull32, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
+        case kFull16 * 3 + kOutNone: pass_dispatch<kFull16, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
+        case kCompact * 3 + kOutNone: pass_dispatch<kCompact, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
         default: return false;
     }
 }

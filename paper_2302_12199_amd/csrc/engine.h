@@ -20,6 +20,7 @@ struct EngineBuffers {
     uint32_t* p16;        // kFull16 layout
     EdgeSoA cbuf[2];      // kCompact layouts (alternating)
     uint64_t* pairs;      // tail: lightest edge per vertex pair (triangular table)
+    int32_t* perm;        // tail: hot-first permutation of its vertices' labels
     uint32_t* list_xy[2];  // tail: pair list (ping-pong, compacted every round)
     uint64_t* list_key[2];
     BucketBuffers bk;     // bucketed round 0 (large graphs only)

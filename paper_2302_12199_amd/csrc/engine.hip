@@ -30,6 +30,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr double kCompactBelow = 0.5;   // compact when live / positions drops below this
 constexpr int64_t kMax16 = 65535;       // label count that still fits the packed layout
+constexpr int64_t kPreTailMinEdges = 1 << 23;   // smaller views are not worth renumbering
 }  // namespace
 
 size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool buckets) {
@@ -61,6 +62,7 @@ size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool bucke
     }
     const size_t slots = (size_t)kTailMax * (kTailMax - 1) / 2;
     b.pairs = (uint64_t*)take(slots * 8);
+    b.perm = (int32_t*)take((size_t)kTailMax * 4);
     for (int i = 0; i < 2; ++i) {
         b.list_xy[i] = (uint32_t*)take(slots * 4);
         b.list_key[i] = (uint64_t*)take(slots * 8);
@@ -210,6 +212,13 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         // edge ends are renumbered first (their minima then stay in LDS).
         if (bucketed && mode == kOrig && nn > kTailMax && !always_compact())
             bucket_hot_first(B.bk, view.u, view.v, view.len, lab, nr, nn, s);
+        // Before the tail: the labels of its vertices are renumbered hot first
+        // (the pair pass keeps the pairs among the first ones in LDS).
+        const bool pre_tail_hot = nn <= kTailMax && view.len >= kPreTailMinEdges;
+        if (pre_tail_hot && nn > kPairHot)
+            launch_hot_first_small(mode, view, cmap, lab, nr, nn, B.perm, &dc->aux[2], s);
+        else if (pre_tail_hot)   // every pair fits the LDS table
+            launch_fill_u64(&dc->aux[2], 1, (uint64_t)nn, s);
         prof_add(K_HOOK, 17.0 * live);
         prof_add(K_SCAN_ROOTS, 4.0 * nn);
         prof_add(K_LABEL, 8.0 * nn);
@@ -251,7 +260,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             h = prof_begin(K_PASS, s);
             launch_fill_u64(B.pairs, slots, kKeyMax, s);
             if (!launch_pass(mode, kOutNone, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1],
-                             nn, B.pairs, dc, s)) {
+                             nn, B.pairs, pre_tail_hot ? &dc->aux[2] : nullptr, dc, s)) {
                 set_err_text("unsupported pass layout");
                 return MSF_EINTERNAL;
             }
@@ -303,7 +312,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             } else {
                 h = prof_begin(mode == kOrig ? K_PASS_R0 : K_PASS, s);
                 if (!launch_pass(mode, out, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1],
-                                 nn, nullptr, dc, s)) {
+                                 nn, nullptr, nullptr, dc, s)) {
                     set_err_text("unsupported pass layout");
                     return MSF_EINTERNAL;
                 }

@@ -23,7 +23,11 @@ void launch_compose(const int32_t* cmap, int64_t nc, const int32_t* label, int32
                     hipStream_t s);
 bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t nc, int32_t* ou,
                  int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
-                 Ctrl* ctrl, hipStream_t s);
+                 const uint64_t* pair_hot, Ctrl* ctrl, hipStream_t s);
+// Before the tail: this round's labels lab[0, nr) (values in [0, nn), nn <= the
+// tail's limit) renumbered hot first; *hot = the number of hot labels.
+void launch_hot_first_small(int mode, const View& g, const int32_t* cmap, int32_t* lab, int64_t nr,
+                            int64_t nn, int32_t* perm, uint64_t* hot, hipStream_t s);
 // tail.hip
 void launch_tail(const uint64_t* pairs, int64_t nn, uint32_t* const list_xy[2],
                  uint64_t* const list_key[2], const uint32_t* view_id, uint8_t* mask,

@@ -77,11 +77,12 @@ def test_rejects_bad_options(msf):
 
 
 def test_workspace_sizes_of_the_round0_choices(msf):
-    # the bucketed round 0 needs about 24 B per edge more, only where it applies
+    # the bucketed round 0 needs about 24 B per edge and 8 B per vertex more,
+    # only where it applies
     m, n = 1 << 22, 1 << 21
     auto, edges = msf.workspace_bytes(m, n), msf.workspace_bytes(m, n, round0="edges")
     assert auto == msf.workspace_bytes(m, n, round0="buckets")
-    assert 24 * m <= auto - edges <= 26 * m + (1 << 20)
+    assert 24 * m + 8 * n <= auto - edges <= 26 * m + 9 * n + (1 << 20)
     for m, n in [(1 << 20, 1 << 16), ((1 << 22) - 1, 1 << 21), (1 << 22, (1 << 21) - 1),
                  (1 << 22, (1 << 24) + 1)]:   # too small or too many vertices
         assert msf.workspace_bytes(m, n) == msf.workspace_bytes(m, n, round0="edges")
