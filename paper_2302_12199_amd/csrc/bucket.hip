@@ -44,8 +44,8 @@ int64_t ntiles(int64_t m) { return (m + kBucketTile - 1) >> kBucketTileShift; }
 constexpr int kGroups = (int)(kBucketTile / 4 / kBucketThreads);   // 4-edge groups per thread
 constexpr uint32_t kArcMask = (uint32_t)kTileArcs - 1;
 constexpr int kInFlight = 16;                                       // gathers per lane in flight
-constexpr int kHotSample = 8192;                                    // edge ends sampled for hot labels
-constexpr uint32_t kHotIds = 4096;                                  // labels whose minima stay in LDS
+constexpr int kHotSample = 16384;                                   // edge ends sampled for hot labels
+constexpr uint32_t kHotIds = 8192;                                  // labels whose minima stay in LDS
 constexpr uint32_t kPassGrid = 2048;                                // workgroups of the pass
 constexpr uint32_t kScatterGrid = 512;                              // workgroups of the scatter
 constexpr int kPassThreads = 1024;    // one pass workgroup per CU (LDS)
@@ -522,42 +522,32 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
 // relabelling pass keeps the minima of the smallest kHotIds labels in LDS, so
 // those components get the smallest labels.  A label is hot when it appears
 // at least twice among kHotSample edge ends sampled by a counter-based hash
-// (SplitMix64 output function of the sample index).  The new labels are a
-// permutation of [0, nn): hot labels first, in label order, then the others.
+// (SplitMix64 output function of the sample index), counted with atomics.
+// The new labels are a permutation of [0, nn): hot labels first, in label
+// order, then the others.
 
-// hot[l] = 1 for the hot labels (hot zeroed before).
-__global__ __launch_bounds__(kBucketThreads) void k_hot_sample(
-    const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m,
-    const int32_t* __restrict__ lab, uint64_t* __restrict__ hot) {
-    __shared__ uint32_t s[kHotSample];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < kHotSample; i += kBucketThreads) {
-        uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x243F6A8885A308D3ull;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        z ^= z >> 31;
-        const int64_t e = (int64_t)__umul64hi(z, (uint64_t)m);
-        const int32_t x = (i & 1) ? v[e] : u[e], y = (i & 1) ? u[e] : v[e];
-        const int32_t l = x != y ? lab[x] : -1;
-        s[i] = l >= 0 ? (uint32_t)l : 0xffffffffu;
-    }
-    __syncthreads();
-    for (int k = 2; k <= kHotSample; k <<= 1) {              // bitonic sort, ascending
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < kHotSample; i += kBucketThreads) {
-                const int p = i ^ jj;
-                if (p > i) {
-                    const uint32_t a = s[i], b = s[p];
-                    if (((i & k) == 0) == (a > b)) { s[i] = b; s[p] = a; }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int i = 1 + tid; i < kHotSample; i += kBucketThreads) {
-        const uint32_t l = s[i];
-        if (l != 0xffffffffu && l == s[i - 1] && (i == 1 || s[i - 2] != l)) hot[l] = 1;
-    }
+// cnt[l] += 1 for every sampled edge end with label l (cnt zeroed before).
+__global__ __launch_bounds__(kBlock) void k_hot_count(const int32_t* __restrict__ u,
+                                                      const int32_t* __restrict__ v, int64_t m,
+                                                      const int32_t* __restrict__ lab,
+                                                      uint64_t* __restrict__ cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kHotSample) return;
+    uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x243F6A8885A308D3ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int64_t e = (int64_t)__umul64hi(z, (uint64_t)m);
+    const int32_t x = (i & 1) ? v[e] : u[e], y = (i & 1) ? u[e] : v[e];
+    const int32_t l = x != y ? lab[x] : -1;
+    if (l >= 0) atomicAdd((unsigned long long*)&cnt[l], 1ull);
+}
+
+// cnt[l] <- 1 if label l was sampled at least twice (hot), else 0.
+__global__ __launch_bounds__(kBlock) void k_hot_flags(uint64_t* __restrict__ cnt, int64_t nn) {
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < nn;
+         l += (int64_t)gridDim.x * blockDim.x)
+        cnt[l] = cnt[l] >= 2 ? 1 : 0;
 }
 
 // lab[x] <- new label of lab[x]; pre = exclusive scan of hot[] (pre[nn] = H).
@@ -598,7 +588,10 @@ void bucket_hot_first(const BucketBuffers& B, const int32_t* u, const int32_t* v
     const int h = prof_begin(K_BK_INDEX, s);
     B.hotn = nn;
     launch_fill_u64(B.hotpre, nn + 1, 0, s);
-    hipLaunchKernelGGL(k_hot_sample, dim3(1), dim3(kBucketThreads), 0, s, u, v, m, lab, B.hotpre);
+    hipLaunchKernelGGL(k_hot_count, dim3((kHotSample + kBlock - 1) / kBlock), dim3(kBlock), 0, s, u,
+                       v, m, lab, B.hotpre);
+    hipLaunchKernelGGL(k_hot_flags, dim3((unsigned)std::min<int64_t>((nn + kBlock - 1) / kBlock, 4096)),
+                       dim3(kBlock), 0, s, B.hotpre, nn);
     launch_scan_u64(B.hotpre, nn, B.hottmp, B.hotpre + nn, s);
     const int64_t g = std::min<int64_t>((nr + kBlock - 1) / kBlock, 4096);
     hipLaunchKernelGGL(k_hot_relabel, dim3((unsigned)g), dim3(kBlock), 0, s, lab, nr, B.hotpre, nn);
