@@ -26,9 +26,10 @@ struct BucketBuffers {
     uint64_t* tmp;       // scan partial sums
     uint16_t* xs;        // [2m] bucket-major: vertex in bucket of every arc
     uint32_t* rank;      // [m] places of the edge's two arcs in its tile block (u | v << 16)
-    uint64_t* hotpre;    // [n + 2] hot flags of the round-1 labels, then their exclusive scan
+    uint64_t* hotpre;    // [n + 2] sample counts of the round-1 labels, tier flags, their
+                         // exclusive scan (hotpre[hotn] = tier sizes), labels sampled
     uint64_t* hottmp;    // scan partial sums
-    mutable int64_t hotn;  // labels of the last hot-first renumbering (hotpre[hotn] = hot count)
+    mutable int64_t hotn;  // labels of the last hot-first renumbering (hotpre[hotn + 1] = sampled)
     int64_t mcap, ncap;  // the largest graph the buffers were carved for
 };
 

@@ -44,7 +44,7 @@ int64_t ntiles(int64_t m) { return (m + kBucketTile - 1) >> kBucketTileShift; }
 constexpr int kGroups = (int)(kBucketTile / 4 / kBucketThreads);   // 4-edge groups per thread
 constexpr uint32_t kArcMask = (uint32_t)kTileArcs - 1;
 constexpr int kInFlight = 16;                                       // gathers per lane in flight
-constexpr int kHotSample = 16384;                                   // edge ends sampled for hot labels
+constexpr int kHotSample = 65535;                                   // edge ends sampled for hot labels
 constexpr uint32_t kHotIds = 8192;                                  // labels whose minima stay in LDS
 constexpr uint32_t kPassGrid = 2048;                                // workgroups of the pass
 constexpr uint32_t kScatterGrid = 512;                              // workgroups of the scatter
@@ -519,12 +519,15 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
 
 // Hot-first renumbering of the round-1 labels.  After round 0 of a skewed
 // graph a few thousand components carry a large share of the edge ends; the
-// relabelling pass keeps the minima of the smallest kHotIds labels in LDS, so
-// those components get the smallest labels.  A label is hot when it appears
-// at least twice among kHotSample edge ends sampled by a counter-based hash
-// (SplitMix64 output function of the sample index), counted with atomics.
-// The new labels are a permutation of [0, nn): hot labels first, in label
-// order, then the others.
+// relabelling pass keeps the minima of the smallest kHotIds labels in LDS and
+// the next pass the prefix of its label map, so the components met most
+// often get the smallest labels.  kHotSample edge ends are sampled by a
+// counter-based hash (SplitMix64 output function of the sample index) and
+// counted per label with atomics.  The sampled labels fall into four tiers by
+// count (at least 16, 4, 2, then 1); the new labels are a permutation of
+// [0, nn): tier by tier, hottest first, each tier in label order, then the
+// labels never sampled.  One u64 scan ranks all tiers at once: tier t adds
+// 1 << 16t, and no tier holds more than kHotSample < 2^16 labels.
 
 // cnt[l] += 1 for every sampled edge end with label l (cnt zeroed before).
 __global__ __launch_bounds__(kBlock) void k_hot_count(const int32_t* __restrict__ u,
@@ -543,24 +546,43 @@ __global__ __launch_bounds__(kBlock) void k_hot_count(const int32_t* __restrict_
     if (l >= 0) atomicAdd((unsigned long long*)&cnt[l], 1ull);
 }
 
-// cnt[l] <- 1 if label l was sampled at least twice (hot), else 0.
+static_assert(kHotSample < 65536, "a tier's rank must fit in 16 bits");
+
+// cnt[l] <- 1 << 16t for a label of tier t, 0 for a label never sampled.
 __global__ __launch_bounds__(kBlock) void k_hot_flags(uint64_t* __restrict__ cnt, int64_t nn) {
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < nn;
-         l += (int64_t)gridDim.x * blockDim.x)
-        cnt[l] = cnt[l] >= 2 ? 1 : 0;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t c = cnt[l];
+        const int t = c >= 16 ? 0 : c >= 4 ? 1 : c >= 2 ? 2 : 3;
+        cnt[l] = c ? 1ull << (16 * t) : 0;
+    }
 }
 
-// lab[x] <- new label of lab[x]; pre = exclusive scan of hot[] (pre[nn] = H).
+__device__ __forceinline__ uint64_t tier_sum(uint64_t p) {
+    return (p & 0xffff) + ((p >> 16) & 0xffff) + ((p >> 32) & 0xffff) + (p >> 48);
+}
+
+// lab[x] <- new label of lab[x]; pre = exclusive scan of the tier flags
+// (pre[nn] = the tiers' sizes).  Also pre[nn + 1] = labels sampled.
 __global__ __launch_bounds__(kBlock) void k_hot_relabel(int32_t* __restrict__ lab, int64_t nr,
-                                                        const uint64_t* __restrict__ pre,
-                                                        int64_t nn) {
-    const uint64_t H = pre[nn];
+                                                        uint64_t* __restrict__ pre, int64_t nn) {
+    const uint64_t T = pre[nn];
+    const uint64_t H = tier_sum(T);
+    if (blockIdx.x == 0 && threadIdx.x == 0) pre[nn + 1] = H;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nr;
          x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t l = lab[x];
         if (l < 0 || l >= nn) continue;
-        const uint64_t r = pre[l], hot = pre[l + 1] - r;
-        lab[x] = (int32_t)(hot ? r : H + ((uint64_t)l - r));
+        const uint64_t r = pre[l], d = pre[l + 1] - r;
+        uint64_t nl;
+        if (d) {
+            const int t = (int)(__builtin_ctzll(d) >> 4);
+            const uint64_t below = tier_sum(T & ((1ull << (16 * t)) - 1));   // earlier tiers
+            nl = below + ((r >> (16 * t)) & 0xffff);
+        } else {
+            nl = H + ((uint64_t)l - tier_sum(r));
+        }
+        lab[x] = (int32_t)nl;
     }
 }
 
@@ -646,7 +668,7 @@ void bucket_relabel(const BucketBuffers& B, const int32_t* u, const int32_t* v,
     hipLaunchKernelGGL(k_bk_label, dim3(nb), bl, 0, s, B.xs, B.base, n, 2 * m, M, relab);
     prof_end(h, s, 6.0 * arcs + 4.0 * n);
     // the count of renumbered hot labels, if this solve renumbered them
-    const uint64_t* hot_count = B.hotn >= 0 && B.hotn <= nn ? B.hotpre + B.hotn : nullptr;
+    const uint64_t* hot_count = B.hotn >= 0 && B.hotn <= nn ? B.hotpre + B.hotn + 1 : nullptr;
     h = prof_begin(K_BK_PASS, s);
     const dim3 grid(std::min<uint32_t>(nt, kPassGrid)), pbl(kPassThreads);
     if (out == kOut16)
