@@ -276,9 +276,13 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_min(
     const uint64_t xs0 = base[bk];
     const uint32_t* row = metat + (int64_t)bk * nt;
     uint32_t pre = 0;   // arcs of the bucket in earlier batches
+    uint32_t mt_next = (uint32_t)tid < nt ? row[tid] : 0u;
     for (uint32_t r0 = 0; r0 < nt; r0 += kBucketThreads) {
         const uint32_t r = r0 + tid;
-        const uint32_t mt = r < nt ? row[r] : 0u;
+        const uint32_t mt = mt_next;
+        // the next batch's run entry, in flight while this batch's arcs load
+        const uint32_t rn = r + kBucketThreads;
+        mt_next = rn < nt ? row[rn] : 0u;
         uint64_t btot;
         const uint32_t ex = (uint32_t)block_excl_scan(mt >> 16, s_w, &btot);
         s_pre[tid] = ex;
@@ -401,22 +405,29 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
     // below kh are taken in LDS and merged once per workgroup.
     const uint32_t kh = hot_count ? (uint32_t)std::min<uint64_t>(*hot_count, (uint64_t)kHotIds) : 0u;
     for (uint32_t i = tid; i < kh; i += kPassThreads) s_hmin[i] = kKeyMax;
+    // Thread bk holds bucket bk's run of the tile: its base once, the run
+    // entries of the next tile loaded while this tile's edges are processed.
+    static_assert(kPassThreads == kBucketMax, "one thread per bucket");
+    const int bk = tid;
+    const bool has_bk = bk < (int)nb;
+    const uint64_t bbase = has_bk ? base[bk] : 0;
+    uint32_t mt_n = 0, of_n = 0;
+    if (has_bk && blockIdx.x < nt) {
+        mt_n = meta[(int64_t)blockIdx.x * nb + bk];
+        of_n = offt[(int64_t)blockIdx.x * nb + bk];
+    }
     // tiles are taken grid-stride, so the live-edge count costs one atomic
     // per workgroup (same-address atomics queue at ~13 ns each)
     for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
         const int64_t e0 = (int64_t)t << kBucketTileShift;
         const int64_t e1 = e0 + kBucketTile < m ? e0 + kBucketTile : m;
-        for (int bk = tid; bk < kBucketMax; bk += kPassThreads) {
-            if (bk < (int)nb) {
-                const int64_t j = (int64_t)t * nb + bk;
-                const uint32_t mt = meta[j];
-                s_rs[bk] = mt & 0xffff;
-                s_src[bk] = base[bk] + offt[j];
-                if (bk == (int)nb - 1) s_na = std::min((mt & 0xffff) + (mt >> 16), (uint32_t)kTileArcs);
-            } else {
-                s_rs[bk] = 0xffffffffu;   // past the last bucket: never <= a slot
-                s_src[bk] = 0;
-            }
+        if (has_bk) {
+            s_rs[bk] = mt_n & 0xffff;
+            s_src[bk] = bbase + of_n;
+            if (bk == (int)nb - 1) s_na = std::min((mt_n & 0xffff) + (mt_n >> 16), (uint32_t)kTileArcs);
+        } else {
+            s_rs[bk] = 0xffffffffu;   // past the last bucket: never <= a slot
+            s_src[bk] = 0;
         }
         __syncthreads();
         const uint32_t na = s_na;
@@ -439,7 +450,11 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
             }
         }
         __syncthreads();
-        __syncthreads();
+        const uint32_t tn = t + gridDim.x;
+        if (has_bk && tn < nt) {
+            mt_n = meta[(int64_t)tn * nb + bk];
+            of_n = offt[(int64_t)tn * nb + bk];
+        }
         // the tile's edges in two parts of kGroups x 4 per lane (register budget)
         for (int part = 0; part < kPassParts; ++part) {
             const int64_t qbase = e0 / 4 + (int64_t)part * kGroups * kPassThreads + tid;
