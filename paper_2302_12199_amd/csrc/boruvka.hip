@@ -737,8 +737,9 @@ void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_
                        nr, orig_cur, orig_next, rep);
 }
 
-// LDS budget of one pass workgroup (two fit in a CU's 160 KiB).
-constexpr int64_t kPassLds = 78 * 1024;
+// LDS budget of one pass workgroup: one per CU (its 16 waves are all the
+// registers allow), so one copy of the minima and the map per CU.
+constexpr int64_t kPassLds = 156 * 1024;
 // Smallest map prefix worth staging when the whole map does not fit.
 constexpr int64_t kMapPrefixMin = 1024;
 
@@ -791,7 +792,7 @@ static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* 
     }
     const int64_t groups = (g.len + 3) / 4;
     int64_t want = (groups + (int64_t)kPassBlock * kPassGroups - 1) / ((int64_t)kPassBlock * kPassGroups);
-    const int64_t cap = lds ? 512 : 1024;   // LDS variants: two workgroups per CU
+    const int64_t cap = lds ? 256 : 512;   // LDS variants: one workgroup per CU
     const unsigned grid = (unsigned)(want < 1 ? 1 : (want > cap ? cap : want));
     const dim3 bl(kPassBlock);
     if (ldsb && km)

@@ -11,7 +11,7 @@ constexpr int kItems = 16;                  // items per thread in scan tiles
 constexpr int kTile = kBlock * kItems;      // items per decoupled-lookback tile
 constexpr int kRelabelItems = 8;            // edges per thread in the relabel pass
 constexpr int kRelabelTile = kBlock * kRelabelItems;
-constexpr int kPassBlock = 512;             // threads per streaming-pass workgroup
+constexpr int kPassBlock = 1024;            // threads per streaming-pass workgroup
 constexpr int kPassGroups = 2;              // 4-edge groups per lane per step in a pass
 constexpr uint64_t kKeyMax = ~0ull;         // "no edge" in best[]
 
