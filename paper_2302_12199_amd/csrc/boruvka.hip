@@ -650,19 +650,22 @@ void launch_compose(const int32_t* cmap, int64_t nc, const int32_t* label, int32
 // workgroup samples kPreTailSample edge ends of the view (positions from the
 // SplitMix64 output function of the sample index), takes each end's label
 // lab[c] (c = the end's current vertex, through cmap when maps are composed),
-// sorts the samples in LDS, marks the labels seen at least twice as hot, and
-// writes the permutation hot labels first (perm[nn]) and their count (*hot).
+// counts the samples per label in LDS, sorts the labels by count (most
+// sampled first, ties by label), and writes the permutation in that order
+// (perm[nn]) and the number of labels sampled at least once (*hot).
 constexpr int kPreTailSample = 8192;
+static_assert(kTailThreads >= kTailMax, "one thread per label");
 
 template <int MODE>
 __global__ __launch_bounds__(kTailThreads) void k_hot_first_small(
     View g, const int32_t* __restrict__ cmap, const int32_t* __restrict__ lab, int64_t nr,
     int64_t nn, int32_t* __restrict__ perm, uint64_t* __restrict__ hot) {
-    __shared__ uint32_t s[kPreTailSample];
-    __shared__ uint32_t s_flag[kTailMax];
+    __shared__ uint32_t s_cnt[kTailMax];
+    __shared__ uint64_t s_key[kTailMax];
     __shared__ uint64_t s_w[kTailThreads / kWave];
     const int tid = threadIdx.x;
-    if (tid < kTailMax) s_flag[tid] = 0;
+    if (tid < kTailMax) s_cnt[tid] = 0;
+    __syncthreads();
     for (int i = tid; i < kPreTailSample; i += blockDim.x) {
         uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x13198A2E03707344ull;
         z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -671,39 +674,37 @@ __global__ __launch_bounds__(kTailThreads) void k_hot_first_small(
         const int64_t e = (int64_t)__umul64hi(z, (uint64_t)g.len);
         int32_t a, b;
         load_ends<MODE>(g, e, a, b);
-        uint32_t sample = 0xffffffffu;
         if (a != b) {
             const int32_t ca = cmap ? cmap[a] : a, cb = cmap ? cmap[b] : b;
             if (ca >= 0 && cb >= 0 && ca < nr && cb < nr) {
                 const int32_t la = lab[ca], lb = lab[cb];
                 const int32_t l = (i & 1) ? lb : la;
-                if (la != lb && l >= 0 && l < nn) sample = (uint32_t)l;
+                if (la != lb && l >= 0 && l < nn) atomicAdd(&s_cnt[l], 1u);
             }
         }
-        s[i] = sample;
     }
     __syncthreads();
-    for (int k = 2; k <= kPreTailSample; k <<= 1) {          // bitonic sort, ascending
+    // sort key: fewer samples sort later, then the label (ascending sort)
+    if (tid < kTailMax)
+        s_key[tid] = tid < nn ? ((uint64_t)(0xffffffffu - s_cnt[tid]) << 32) | (uint64_t)tid
+                              : ~0ull;
+    const uint32_t f = tid < nn && s_cnt[tid] > 0 ? 1u : 0u;
+    __syncthreads();
+    for (int k = 2; k <= kTailMax; k <<= 1) {          // bitonic sort, ascending
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < kPreTailSample; i += blockDim.x) {
-                const int p = i ^ jj;
-                if (p > i) {
-                    const uint32_t x = s[i], y = s[p];
-                    if (((i & k) == 0) == (x > y)) { s[i] = y; s[p] = x; }
+            if (tid < kTailMax) {
+                const int p = tid ^ jj;
+                if (p > tid) {
+                    const uint64_t x = s_key[tid], y = s_key[p];
+                    if (((tid & k) == 0) == (x > y)) { s_key[tid] = y; s_key[p] = x; }
                 }
             }
             __syncthreads();
         }
     }
-    for (int i = 1 + tid; i < kPreTailSample; i += blockDim.x) {
-        const uint32_t l = s[i];
-        if (l != 0xffffffffu && l == s[i - 1]) s_flag[l] = 1;
-    }
-    __syncthreads();
-    const uint32_t f = tid < nn ? s_flag[tid] : 0u;
     uint64_t H;
-    const uint64_t r = block_excl_scan(f, s_w, &H);
-    if (tid < nn) perm[tid] = (int32_t)(f ? r : H + ((uint64_t)tid - r));
+    (void)block_excl_scan((uint64_t)f, s_w, &H);
+    if (tid < nn) perm[(uint32_t)s_key[tid]] = tid;
     if (tid == 0) *hot = H;
 }
 
@@ -777,9 +778,10 @@ static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* 
     bool ldsb = false;
     int64_t km = 0;
     size_t lds = 0;
-    const int64_t ptab = PAIR && pair_hot && lds_on ? kPairHot * (kPairHot - 1) / 2 * 8 : 0;
-    if (!ptab) pair_hot = nullptr;
+    int64_t ptab = 0;
     for (int64_t budget : {kPassLds, (int64_t)64 * 1024}) {   // the second if the runtime refuses
+        const int64_t want_ptab = kPairHot * (kPairHot - 1) / 2 * 8;
+        ptab = PAIR && pair_hot && lds_on && want_ptab + 8 <= budget ? want_ptab : 0;
         ldsb = lds_on && !PAIR && nn * 8 <= budget;
         const int64_t left = budget - (ldsb ? nn * 8 : 0) - ptab - 8;
         km = !lds_on ? 0 : nc * 4 <= left ? nc : (left / 4 >= kMapPrefixMin ? left / 4 : 0);
@@ -788,8 +790,10 @@ static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* 
         if (ldsb && km) ok = allow_lds<IN, OUT, true, true, PAIR>(lds);
         else if (ldsb) ok = allow_lds<IN, OUT, false, true, PAIR>(lds);
         else if (km) ok = allow_lds<IN, OUT, true, false, PAIR>(lds);
+        else ok = allow_lds<IN, OUT, false, false, PAIR>(lds);
         if (ok) break;
     }
+    if (!ptab) pair_hot = nullptr;   // the kernel keeps LDS pairs only when given pair_hot
     const int64_t groups = (g.len + 3) / 4;
     int64_t want = (groups + (int64_t)kPassBlock * kPassGroups - 1) / ((int64_t)kPassBlock * kPassGroups);
     const int64_t cap = lds ? 256 : 512;   // LDS variants: one workgroup per CU

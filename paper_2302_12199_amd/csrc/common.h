@@ -48,9 +48,9 @@ struct Ctrl {
 constexpr int kTailMax = 1024;              // vertices the single-workgroup tail handles
 constexpr int kTailThreads = 1024;
 constexpr int kTailRoundsMax = 24;
-// Labels whose vertex pairs the pass before the tail keeps in LDS (90 * 89 / 2
-// slots, 32 KiB), after the labels of that round were renumbered hot first.
-constexpr int64_t kPairHot = 90;
+// Labels whose vertex pairs the pass before the tail keeps in LDS (128 * 127 / 2
+// slots, 63.5 KiB), after the labels of that round were renumbered hot first.
+constexpr int64_t kPairHot = 128;
 
 // Lookback status word: 2 flag bits over a 62-bit inclusive/aggregate value.
 constexpr uint64_t kStatAgg = 1ull << 62;
