@@ -25,7 +25,8 @@ struct BucketBuffers {
     uint64_t* base;      // [nb + 1] first arc of each bucket in the bucket-major streams
     uint64_t* tmp;       // scan partial sums
     uint16_t* xs;        // [2m] bucket-major: vertex in bucket of every arc
-    uint32_t* rank;      // [m] places of the edge's two arcs in its tile block (u | v << 16)
+    uint32_t* rank;      // [m] places of the edge's two arcs in its tile block (u | v << 16);
+                         // 0 for an edge without arcs (self-loop, id out of range)
     uint64_t* hotpre;    // [n + 2] sample counts of the round-1 labels, tier flags, their
                          // exclusive scan (hotpre[hotn] = tier sizes), labels sampled
     uint64_t* hottmp;    // scan partial sums
@@ -59,8 +60,8 @@ void bucket_hot_first(const BucketBuffers& B, const int32_t* u, const int32_t* v
 // into ctrl->m_next and run the next round's lightest-edge search into
 // best_next[0, nn).  Uses the arcs of the last bucket_minedge call on the
 // same edges.
-void bucket_relabel(const BucketBuffers& B, const int32_t* u, const int32_t* v,
-                    const uint32_t* w, int64_t m, int64_t n, const int32_t* M, int out,
+void bucket_relabel(const BucketBuffers& B, const uint32_t* w, int64_t m, int64_t n,
+                    const int32_t* M, int out,
                     int32_t* ou, int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn,
                     Ctrl* ctrl, hipStream_t s);
 

@@ -384,8 +384,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_label(
 // search with key (w << 32 | position).
 template <int OUT>
 __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
-    const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
-    int64_t m, int64_t n, uint32_t nb, uint32_t nt, const uint32_t* __restrict__ meta,
+    const uint32_t* __restrict__ w, int64_t m, uint32_t nb, uint32_t nt,
+    const uint32_t* __restrict__ meta,
     const uint32_t* __restrict__ offt, const uint64_t* __restrict__ base,
     const uint32_t* __restrict__ relab, const uint32_t* __restrict__ rank,
     int32_t* __restrict__ ou, int32_t* __restrict__ ov, uint32_t* __restrict__ op16,
@@ -458,13 +458,10 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
         // the tile's edges in two parts of kGroups x 4 per lane (register budget)
         for (int part = 0; part < kPassParts; ++part) {
             const int64_t qbase = e0 / 4 + (int64_t)part * kGroups * kPassThreads + tid;
-            int32_t a[kGroups][4], b[kGroups][4];
             uint32_t ww[kGroups][4], rk[kGroups][4];
 #pragma unroll
             for (int j = 0; j < kGroups; ++j) {
                 const int64_t q = qbase + (int64_t)j * kPassThreads;
-                load4<int32_t, int4>(u, q, e1, a[j]);
-                load4<int32_t, int4>(v, q, e1, b[j]);
                 load4<uint32_t, uint4>(w, q, e1, ww[j]);
                 load4<uint32_t, uint4>(rank, q, e1, rk[j]);
             }
@@ -485,8 +482,10 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
                     key[i] = kKeyMax;
                     ax[i] = ay[i] = false;
                     const int64_t e = q * 4 + k;
-                    const int32_t x = a[j][k], y = b[j][k];
-                    if (e < e1 && in_range(x, y, n) && x != y) {
+                    // rank 0 (both arcs at slot 0) marks an edge the scatter
+                    // skipped: a self-loop or an id out of range; a real
+                    // edge's two arcs have distinct slots
+                    if (e < e1 && rk[j][k] != 0) {
                         const uint32_t lx = s_lab[rk[j][k] & kArcMask];
                         const uint32_t ly = s_lab[(rk[j][k] >> 16) & kArcMask];
                         if (lx != ly) {
@@ -671,8 +670,8 @@ void bucket_minedge(const BucketBuffers& B, const int32_t* u, const int32_t* v,
     prof_end(h, s, 8.0 * cells);
 }
 
-void bucket_relabel(const BucketBuffers& B, const int32_t* u, const int32_t* v,
-                    const uint32_t* w, int64_t m, int64_t n, const int32_t* M, int out,
+void bucket_relabel(const BucketBuffers& B, const uint32_t* w, int64_t m, int64_t n,
+                    const int32_t* M, int out,
                     int32_t* ou, int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn,
                     Ctrl* ctrl, hipStream_t s) {
     const uint32_t nb = (uint32_t)nbuckets(n), nt = (uint32_t)ntiles(m);
@@ -687,12 +686,12 @@ void bucket_relabel(const BucketBuffers& B, const int32_t* u, const int32_t* v,
     h = prof_begin(K_BK_PASS, s);
     const dim3 grid(std::min<uint32_t>(nt, kPassGrid)), pbl(kPassThreads);
     if (out == kOut16)
-        hipLaunchKernelGGL(k_bk_pass<kOut16>, grid, pbl, 0, s, u, v, w, m, n, nb, nt, B.meta,
+        hipLaunchKernelGGL(k_bk_pass<kOut16>, grid, pbl, 0, s, w, m, nb, nt, B.meta,
                            B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, hot_count, ctrl);
     else
-        hipLaunchKernelGGL(k_bk_pass<kOut32>, grid, pbl, 0, s, u, v, w, m, n, nb, nt, B.meta,
+        hipLaunchKernelGGL(k_bk_pass<kOut32>, grid, pbl, 0, s, w, m, nb, nt, B.meta,
                            B.offt, B.base, relab, B.rank, ou, ov, op16, best_next, nn, hot_count, ctrl);
-    prof_end(h, s, 16.0 * m + 4.0 * arcs + (out == kOut16 ? 4.0 : 8.0) * m + 8.0 * cells +
+    prof_end(h, s, 8.0 * m + 4.0 * arcs + (out == kOut16 ? 4.0 : 8.0) * m + 8.0 * cells +
                        8.0 * nn);
 }
 

@@ -307,7 +307,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             if (mode == kOrig) out = nn <= kMax16 ? kOut16 : kOut32;
             else if (mode == kFull32 && nn <= kMax16) out = kOut16;
             if (bucketed && mode == kOrig) {
-                bucket_relabel(B.bk, view.u, view.v, view.w, view.len, nv, M, out, B.f32u,
+                bucket_relabel(B.bk, view.w, view.len, nv, M, out, B.f32u,
                                B.f32v, B.p16, B.best[cur ^ 1], nn, dc, s);
             } else {
                 h = prof_begin(mode == kOrig ? K_PASS_R0 : K_PASS, s);
