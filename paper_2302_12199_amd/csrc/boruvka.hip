@@ -46,11 +46,10 @@ __global__ void k_scan_prep(uint64_t* __restrict__ status, int64_t ntiles, Ctrl*
         status[i] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->tile_counter = 0;
-        if (round_begin) {
+        if (round_begin) {   // m_next stays: the last pass's count is read with this round's
             ctrl->live = 0;
             ctrl->found = 0;
             ctrl->jump_more = 0;
-            ctrl->m_next = 0;
         }
     }
 }

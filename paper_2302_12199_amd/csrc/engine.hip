@@ -167,13 +167,18 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         prof_end(h, s, 12.0 * view.len + 8.0 * nv);
     }
     HIP_TRY(hipGetLastError());
-    if ((st = read_ctrl(dc, hc, s))) return st;
-    if (hc->err & kErrRange) return MSF_ERANGE;
+    // Edges with ids out of range were skipped by the lightest-edge search (no
+    // minimum holds them), so the first round runs on valid edges only; the
+    // error bit is read with that round's counters.
 
+    // The live-edge count of a relabelling pass is read with the next round's
+    // counters (one host synchronisation per round): a pass that leaves no
+    // live edge leaves every minimum empty, so that round finds nothing.
     int64_t m_live = view.len;
+    bool m_pending = false, m_compacted = false;
     uint32_t rounds = stats ? stats->rounds : 0;
     const uint32_t first_round = rounds;
-    while (m_live > 0) {
+    while (m_live > 0 || m_pending) {
         launch_scan_prep(B.status, 0, dc, 1, s);
         const int hh = prof_begin(K_HOOK, s);
         launch_hook(mode, B.best[cur], nr, view, cmap, B.parent, mask, dc, s);
@@ -200,11 +205,21 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             }
             HIP_TRY(hipMemsetAsync(&dc->jump_more, 0, sizeof(uint32_t), s));
         }
+        if (hc->err & kErrRange) return MSF_ERANGE;
         if (hc->err) {
             char buf[96];
             snprintf(buf, sizeof buf, "device error bits 0x%x in round %u", hc->err, rounds);
             set_err_text(buf);
             return MSF_EINTERNAL;
+        }
+        if (m_pending) {
+            m_pending = false;
+            m_live = (int64_t)hc->m_next;
+            if (m_compacted) {     // only a compaction changes the number of positions
+                view.len = m_live;
+                prof_add(K_COMPACT, 16.0 * m_live);
+            }
+            if (m_live == 0) break;
         }
         const uint64_t live = hc->live, found = hc->found;
         const int64_t nn = (int64_t)hc->n_next;
@@ -330,11 +345,6 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             }
         }
         HIP_TRY(hipGetLastError());
-        if ((st = read_ctrl(dc, hc, s))) return st;
-        if (hc->err) {
-            set_err_text("device error bits after the relabel pass");
-            return MSF_EINTERNAL;
-        }
         if (dump_dir()) {
             dump("parent", rounds - 1, B.parent, nr * 4, s);
             dump("label", rounds - 1, lab, nr * 4, s);
@@ -342,11 +352,8 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             dump("best_next", rounds - 1, B.best[cur ^ 1], nn * 8, s);
             dump("best_cur", rounds - 1, B.best[cur], nr * 8, s);
         }
-        m_live = (int64_t)hc->m_next;
-        if (compact) {     // only a compaction changes the number of positions
-            next.len = m_live;
-            prof_add(K_COMPACT, 16.0 * m_live);
-        }
+        m_pending = true;
+        m_compacted = compact;
         view = next;
         mode = next_mode;
         cmap = next_cmap;
