@@ -26,7 +26,7 @@ namespace msf {
 
 constexpr int kBatchMaxRounds = 64;
 constexpr int kMaxJumps = 64;
-constexpr int kEdgeIlp = 4;
+constexpr int kEdgeIlp = 8;
 constexpr uint32_t kNotReady = 0xffffffffu;       // phase id before the first set-up
 constexpr uint64_t kWaitTicks = 200000000ull;     // 2 s of the 100 MHz wall clock
 
