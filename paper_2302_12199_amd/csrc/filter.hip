@@ -508,10 +508,31 @@ __global__ __launch_bounds__(kBlock) void k_filter_flags(View g, const int32_t* 
             if (ORIG && e < m && (((uint64_t)g.w[e] << 32) | (uint64_t)e) <= pivot)
                 b[k] = a[k];                  // light: already handled, never kept
         }
+        // all code words first, then the P gathers of ends with code 0, then
+        // the ballots: the lookups of a thread's edges overlap
+        uint64_t ca[kIt], cb[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            ca[k] = cb[k] = 0;
+            if (a[k] != b[k]) {
+                ca[k] = codes[(uint32_t)a[k] >> 5];
+                cb[k] = codes[(uint32_t)b[k] >> 5];
+            }
+        }
+        int32_t ra[kIt], rb[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            ra[k] = rb[k] = 0;
+            if (a[k] == b[k]) continue;
+            const uint32_t xa = (uint32_t)(ca[k] >> (2 * ((uint32_t)a[k] & 31))) & 3u;
+            const uint32_t xb = (uint32_t)(cb[k] >> (2 * ((uint32_t)b[k] & 31))) & 3u;
+            ra[k] = (xa & 1u) ? gi : (xa ? a[k] : P[a[k]]);
+            rb[k] = (xb & 1u) ? gi : (xb ? b[k] : P[b[k]]);
+        }
         uint32_t c = 0;
 #pragma unroll
         for (int k = 0; k < kIt; ++k) {
-            const bool keep = a[k] != b[k] && rep_of(codes, P, gi, a[k]) != rep_of(codes, P, gi, b[k]);
+            const bool keep = a[k] != b[k] && ra[k] != rb[k];
             const uint64_t mk = __ballot(keep);
             if (lane == 0) flags[w0 + k] = mk;
             c += __popcll(mk);
