@@ -125,7 +125,8 @@ size_t msf_workspace_bytes(int64_t m, int64_t n, const msf_options* opt);
  *                 before returning (MSF_ENOMEM if that fails)
  *   stats         optional HOST struct, filled on MSF_OK
  * Blocking: returns once the mask and total are final.  Out-of-range ids are
- * detected on the device and reported as MSF_ERANGE after the first pass.
+ * detected on the device (such edges take no part in any minimum) and
+ * reported as MSF_ERANGE after the first round.
  */
 int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,
                 uint8_t* mask_out, uint64_t* total_weight_out, void* workspace,

@@ -17,12 +17,15 @@
 //            the batch's run prefix; the minimum key per vertex is kept in LDS.
 //            It also writes the arcs' vertex indices as one bucket-major
 //            stream and where each run starts in it
-//   label    (after hook / jump / root scan) one workgroup per bucket: the
-//            bucket's labels in LDS, the index stream in, the labels out
+//   hot      (after hook / jump / root scan) the round-1 labels renumbered by
+//            how often sampled edge ends carry them, most frequent first
+//   label    one workgroup per bucket: the bucket's labels in LDS, the index
+//            stream in, the labels out
 //   pass     per tile: its runs of labels are gathered into LDS in
-//            tile-block order; each edge reads its two labels there, and the
-//            pass writes the relabelled layout and runs the next round's
-//            lightest-edge search
+//            tile-block order; each edge reads its two labels there (found by
+//            its arc places; the endpoints are not read again), and the pass
+//            writes the relabelled layout and runs the next round's
+//            lightest-edge search, the minima of the first labels in LDS
 #include <algorithm>
 
 #include "bucket.h"

@@ -3,8 +3,9 @@
 // Each round: hook + 2-cycle break + MSF marking, pointer jumping, dense
 // relabelling of the roots, then one streaming pass over the edges that
 // relabels them, drops self-loops and runs the next round's lightest-edge
-// search.  The host reads two small counter blocks per round to size the
-// next launches; everything else stays on the device.
+// search.  The host reads one small counter block per round (after the root
+// scan, with the previous pass's live-edge count) to size the next launches;
+// everything else stays on the device.
 //
 // Edge layout policy (all layouts keep position order = edge-id order):
 //   * after round 0 the caller's arrays are rewritten once as label pairs
