@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_scatter(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
     int64_t m, int64_t n, uint32_t nb, uint32_t nt, uint64_t* __restrict__ arcs,
     uint32_t* __restrict__ meta, uint32_t* __restrict__ rank, Ctrl* ctrl) {
-    __shared__ uint64_t s_stage[kTileArcs];
+    __shared__ __align__(16) uint64_t s_stage[kTileArcs];
     __shared__ uint32_t s_cnt[kBucketMax];
     __shared__ uint32_t s_cur[kBucketMax];
     __shared__ uint64_t s_w[kBucketThreads / kWave];
@@ -218,8 +218,10 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_scatter(
         }
         __syncthreads();
         const uint32_t na = (uint32_t)(tot < (uint64_t)kTileArcs ? tot : (uint64_t)kTileArcs);
-        uint64_t* dst = arcs + (int64_t)t * kTileArcs;
-        for (uint32_t i = tid; i < na; i += blockDim.x) dst[i] = s_stage[i];
+        uint64_t* dst = arcs + (int64_t)t * kTileArcs;   // 16-byte aligned (kTileArcs even)
+        for (uint32_t i = tid; i < na / 2; i += blockDim.x)
+            reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(s_stage)[i];
+        if ((na & 1) && tid == 0) dst[na - 1] = s_stage[na - 1];
         if (tn < nt) {
 #pragma unroll
             for (int j = 0; j < kGroups; ++j)
