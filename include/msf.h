@@ -120,9 +120,11 @@ size_t msf_workspace_bytes(int64_t m, int64_t n, const msf_options* opt);
  *   mask_out      device uint8[m]; on MSF_OK mask_out[e] = 1 iff edge e is in
  *                 the MSF, else 0
  *   total_weight_out  HOST; sum of w over MSF edges (cannot overflow 64 bits)
- *   workspace     device buffer of >= msf_workspace_bytes(m, n, opt) bytes, or
- *                 NULL: the library then allocates it on `stream` and frees it
- *                 before returning (MSF_ENOMEM if that fails)
+ *   workspace     device buffer of >= msf_workspace_bytes(m, n, opt) bytes,
+ *                 256-byte aligned (hipMalloc and torch allocations are; else
+ *                 MSF_EINVAL), or NULL: the library then allocates it on
+ *                 `stream` and frees it before returning (MSF_ENOMEM if that
+ *                 fails)
  *   stats         optional HOST struct, filled on MSF_OK
  * Blocking: returns once the mask and total are final.  Out-of-range ids are
  * detected on the device (such edges take no part in any minimum) and
@@ -155,7 +157,8 @@ int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m
  *   ticks_out      device uint64[G + 1] or NULL: wall-clock tick at which each
  *                  graph finished, [G] = tick at which the batch started
  *                  (rate: msf_wall_clock_khz)
- *   workspace      device, >= msf_batched_workspace_bytes(G, max_n, opt) bytes
+ *   workspace      device, >= msf_batched_workspace_bytes(G, max_n, opt) bytes,
+ *                  256-byte aligned (else MSF_EINVAL)
  * Errors: MSF_EINVAL (bad host arguments), MSF_EWORKSPACE, MSF_EDEVICE.
  */
 typedef struct msf_batch_options {

@@ -64,6 +64,7 @@ int prepare(const int32_t* u, const int32_t* v, const uint32_t* w, const int64_t
     if (st) return st;
     if (G == 0) return MSF_OK;
     if (!u || !v || !w || !eoff || !voff || !mask || !totals || !ws) return MSF_EINVAL;
+    if ((uintptr_t)ws % 256) return MSF_EINVAL;   // its buffers take 16-byte vector accesses
     if (ws_bytes < batch_layout(G, max_n, 1).total) return MSF_EWORKSPACE;
     if ((st = fit_grid(r))) return st;
     const BatchLayout L = batch_layout(G, max_n, r->workgroups);

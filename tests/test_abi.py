@@ -98,6 +98,13 @@ def test_workspace_too_small(msf):
     assert rc == msf.EWORKSPACE
 
 
+def test_workspace_not_256_byte_aligned(msf):
+    need = msf.workspace_bytes(10, 5)
+    rc, _ = msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE, workspace_ptr=FAKE + 16,
+                            workspace_bytes=need)
+    assert rc == msf.EINVAL
+
+
 def test_forced_allocation_failure(msf, monkeypatch):
     monkeypatch.setenv("MSF_TEST_FAIL_ALLOC", "1")
     rc, _ = msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE)
@@ -131,6 +138,9 @@ def test_batched_argument_checks(msf):
     rc = lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, 3, 10, None, FAKE, FAKE, None,
                                  FAKE, 16, None, None)
     assert rc == msf.EWORKSPACE
+    rc = lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, 3, 10, None, FAKE, FAKE, None,
+                                 FAKE + 16, 1 << 30, None, None)
+    assert rc == msf.EINVAL                      # workspace not 256-byte aligned
     o = msf.make_batch_options()
     o.reserved[0] = 1
     assert lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, 3, 10, None, FAKE, FAKE, None,
