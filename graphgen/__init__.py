@@ -122,6 +122,27 @@ def rgg2d(n: int, r: float, wscale: float = 1e6, seed: int = 4):
     return _take(h, m.value)
 
 
+def star_forest(stars: int, leaves: int, copies: int, extra_isolated: int, seed: int):
+    """An edge case, not a paper family: ``stars`` disjoint stars of ``leaves``
+    leaves each, every hub-leaf edge ``copies`` times with weights in [1, 1000),
+    ``extra_isolated`` vertices without edges, ids and edge order shuffled.
+    One Borůvka round merges every star, after which no edge is live."""
+    rng = np.random.default_rng(seed)
+    hubs = np.arange(stars) * (leaves + 1)
+    hu = np.repeat(hubs, leaves)
+    lv = hu + np.tile(np.arange(1, leaves + 1), stars)
+    u = np.tile(hu, copies)
+    v = np.tile(lv, copies)
+    n = stars * (leaves + 1) + extra_isolated
+    perm = rng.permutation(n).astype(np.int32)
+    u, v = perm[u], perm[v]
+    flip = rng.random(len(u)) < 0.5
+    u, v = np.where(flip, v, u), np.where(flip, u, v)
+    order = rng.permutation(len(u))
+    w = rng.integers(1, 1000, len(u)).astype(np.uint32)
+    return u[order].astype(np.int32), v[order].astype(np.int32), w, n
+
+
 def rgg_radius(n: int, avg_deg: float) -> float:
     """Radius giving expected average degree avg_deg (boundary effects ignored)."""
     return math.sqrt(avg_deg / (math.pi * (n - 1)))

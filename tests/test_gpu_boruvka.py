@@ -198,3 +198,12 @@ def test_compose_pass_after_compaction_keeps_all_positions():
     for rows, cols in [(64, 64), (301, 277)]:
         u, v, w = graphgen.grid(rows, cols, 0.8, 1, 1, 255, seed=3)
         check_against_oracle(u, v, w, rows * cols, rounds=True)
+
+
+def test_pass_leaving_no_live_edge_ends_the_rounds():
+    # more components than the tail takes, and none of them joined by an edge:
+    # the relabel pass leaves no live edge, which the next round's counters show
+    banner("5000 disjoint stars (one round, no tail)")
+    u, v, w, n = graphgen.star_forest(5000, 3, 3, 777, seed=90)
+    st = check_against_oracle(u, v, w, n, rounds=True)
+    assert len(st["round_live"]) == 1

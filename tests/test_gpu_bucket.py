@@ -144,3 +144,13 @@ def test_auto_choice_follows_id_locality():
     mask, total, _, launches = run(u, v, w, rows * cols, "auto")
     assert launches == 0 and (mask == rm).all() and total == rt
     both(u, v, w, rows * cols)
+
+
+def test_pass_leaving_no_live_edge_ends_the_rounds():
+    # 2^19 disjoint 4-vertex stars, each edge three times: the bucketed round 0
+    # merges every star and its pass leaves no live edge
+    banner("bucketed round 0, 2^19 disjoint stars (one round)")
+    u, v, w, n = graphgen.star_forest(1 << 19, 3, 3, 12345, seed=91)
+    assert n >= 1 << 21 and len(u) >= 1 << 22
+    st = both(u, v, w, n)
+    assert len(st["round_live"]) == 1

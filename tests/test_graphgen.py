@@ -95,3 +95,13 @@ def test_rgg_shape():
     assert w.max() <= int(np.ceil(1e6 * r))
     key = u.astype(np.int64) * n + v
     assert (np.diff(key) > 0).all()                     # lexicographic (i, j)
+
+
+def test_star_forest_shape():
+    u, v, w, n = graphgen.star_forest(50, 3, 2, 7, seed=5)
+    assert n == 50 * 4 + 7 and len(u) == len(v) == len(w) == 50 * 3 * 2
+    assert (u != v).all() and u.min() >= 0 and max(u.max(), v.max()) < n
+    assert (w >= 1).all() and (w < 1000).all()
+    # every vertex of an edge has degree 2 (leaf) or 6 (hub), and there are 50 hubs
+    deg = np.bincount(np.concatenate([u, v]), minlength=n)
+    assert sorted(set(deg.tolist())) == [0, 2, 6] and (deg == 6).sum() == 50
