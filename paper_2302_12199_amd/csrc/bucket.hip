@@ -66,6 +66,21 @@ __device__ __forceinline__ void load4(const T* __restrict__ p, int64_t q, int64_
     }
 }
 
+// As load4 for data read once: non-temporal loads, which leave the L2 to the
+// tables that are read again.
+__device__ __forceinline__ void load4_nt(const uint32_t* __restrict__ p, int64_t q, int64_t e1,
+                                         uint32_t (&x)[4]) {
+    const int64_t e = q * 4;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    if (e + 3 < e1) {
+        const u32x4 t = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p) + q);
+        x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = e + k < e1 ? __builtin_nontemporal_load(p + e + k) : 0;
+    }
+}
+
 __device__ __forceinline__ bool in_range(int32_t a, int32_t b, int64_t n) {
     return (uint32_t)a < (uint64_t)n && (uint32_t)b < (uint64_t)n;
 }
@@ -445,7 +460,7 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
                 if (x < na) {
                     const uint32_t b = last_le(s_rs, x);
                     const uint64_t i = s_src[b] + (x - s_rs[b]);
-                    if (i < narcs) val[k] = relab[i];
+                    if (i < narcs) val[k] = __builtin_nontemporal_load(relab + i);
                 }
             }
 #pragma unroll
@@ -467,8 +482,8 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
 #pragma unroll
             for (int j = 0; j < kGroups; ++j) {
                 const int64_t q = qbase + (int64_t)j * kPassThreads;
-                load4<uint32_t, uint4>(w, q, e1, ww[j]);
-                load4<uint32_t, uint4>(rank, q, e1, rk[j]);
+                load4_nt(w, q, e1, ww[j]);
+                load4_nt(rank, q, e1, rk[j]);
             }
             // The lane's 2 x kGroups x 4 reads of best_next are issued together,
             // then the atomics of the keys that beat them (every lane runs every step:
