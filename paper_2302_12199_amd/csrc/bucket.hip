@@ -526,7 +526,7 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
                         }
                     }
                 }
-                if (q * 4 < e1) store_group<OUT>(q, m, *reinterpret_cast<int32_t(*)[4]>(&ra[j * 4]),
+                if (q * 4 < e1) store_group<OUT, true>(q, m, *reinterpret_cast<int32_t(*)[4]>(&ra[j * 4]),
                                                  *reinterpret_cast<int32_t(*)[4]>(&rb[j * 4]), ou, ov, op16);
             }
             uint64_t cx[kE], cy[kE];

@@ -193,7 +193,8 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t* s_w, u
 
 // Stores 4 consecutive relabelled positions of a pass (q = position / 4) in
 // the layout OUT selects: int32 label pairs or 16-bit packed pairs.
-template <int OUT>
+// NT: non-temporal stores, for output that leaves the L2 to reused tables.
+template <int OUT, bool NT = false>
 __device__ __forceinline__ void store_group(int64_t q, int64_t m, const int32_t (&ra)[4],
                                             const int32_t (&rb)[4], int32_t* __restrict__ ou,
                                             int32_t* __restrict__ ov,
@@ -201,7 +202,13 @@ __device__ __forceinline__ void store_group(int64_t q, int64_t m, const int32_t 
     const int64_t e0 = q * 4;
     const bool full = e0 + 3 < m;
     if constexpr (OUT == kOut32) {
-        if (full) {
+        if (full && NT) {
+            typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store(i32x4{ra[0], ra[1], ra[2], ra[3]},
+                                        reinterpret_cast<i32x4*>(ou) + q);
+            __builtin_nontemporal_store(i32x4{rb[0], rb[1], rb[2], rb[3]},
+                                        reinterpret_cast<i32x4*>(ov) + q);
+        } else if (full) {
             reinterpret_cast<int4*>(ou)[q] = make_int4(ra[0], ra[1], ra[2], ra[3]);
             reinterpret_cast<int4*>(ov)[q] = make_int4(rb[0], rb[1], rb[2], rb[3]);
         } else {
@@ -212,7 +219,11 @@ __device__ __forceinline__ void store_group(int64_t q, int64_t m, const int32_t 
         uint32_t pk[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) pk[k] = (uint32_t)ra[k] | ((uint32_t)rb[k] << 16);
-        if (full) {
+        if (full && NT) {
+            typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store(u32x4v{pk[0], pk[1], pk[2], pk[3]},
+                                        reinterpret_cast<u32x4v*>(op16) + q);
+        } else if (full) {
             reinterpret_cast<uint4*>(op16)[q] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
         } else {
             for (int k = 0; k < 4; ++k)
