@@ -499,13 +499,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_flags(View g, const int32_t* 
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t w0 = (int64_t)tile * (kBlock * kIt / kWave) + wave * kIt;  // first flag word
         const int64_t m = g.len;
+        // the edges are streamed once: non-temporal loads keep the codes in the L2
         int32_t a[kIt], b[kIt];
 #pragma unroll
         for (int k = 0; k < kIt; ++k) {
             const int64_t e = (w0 + k) * kWave + lane;
             a[k] = b[k] = 0;
-            if (e < m) { a[k] = g.u[e]; b[k] = g.v[e]; }
-            if (ORIG && e < m && (((uint64_t)g.w[e] << 32) | (uint64_t)e) <= pivot)
+            if (e < m) { a[k] = __builtin_nontemporal_load(g.u + e); b[k] = __builtin_nontemporal_load(g.v + e); }
+            if (ORIG && e < m &&
+                (((uint64_t)__builtin_nontemporal_load(g.w + e) << 32) | (uint64_t)e) <= pivot)
                 b[k] = a[k];                  // light: already handled, never kept
         }
         // all code words first, then the P gathers of ends with code 0, then
