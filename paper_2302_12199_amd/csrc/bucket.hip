@@ -577,7 +577,16 @@ __global__ __launch_bounds__(kBlock) void k_hot_count(const int32_t* __restrict_
     const int64_t e = (int64_t)__umul64hi(z, (uint64_t)m);
     const int32_t x = (i & 1) ? v[e] : u[e], y = (i & 1) ? u[e] : v[e];
     const int32_t l = x != y ? lab[x] : -1;
-    if (l >= 0) atomicAdd((unsigned long long*)&cnt[l], 1ull);
+    // the lanes sampling the first active lane's label add once (a giant
+    // component would otherwise queue one same-address atomic per sample)
+    const uint64_t am = __ballot(l >= 0);
+    if (am == 0) return;
+    const int leader = __builtin_ctzll(am);
+    const int32_t tl = __shfl(l, leader, kWave);
+    const bool same = l >= 0 && l == tl;
+    const uint64_t c = (uint64_t)__popcll(__ballot(same));
+    if (lane_id() == leader) atomicAdd((unsigned long long*)&cnt[tl], (unsigned long long)c);
+    if (l >= 0 && !same) atomicAdd((unsigned long long*)&cnt[l], 1ull);
 }
 
 static_assert(kHotSample < 65536, "a tier's rank must fit in 16 bits");
