@@ -162,7 +162,14 @@ __global__ __launch_bounds__(kHookBlock) void k_hook(const uint64_t* __restrict_
         ++nlive;
         const uint32_t pos = (uint32_t)b;
         int32_t eu, ev;
-        load_ends<MODE>(g, pos, eu, ev);
+        if constexpr (MODE == kOrig) {
+            // the caller's arrays are far larger than the caches: these lines
+            // are read once, so non-temporal loads leave the caches to best[]
+            eu = __builtin_nontemporal_load(g.u + pos);
+            ev = __builtin_nontemporal_load(g.v + pos);
+        } else {
+            load_ends<MODE>(g, pos, eu, ev);
+        }
         if (cmap) { eu = cmap[eu]; ev = cmap[ev]; }
         if (eu != x && ev != x) bad = true;
         const int32_t other = eu == (int32_t)x ? ev : eu;
