@@ -590,12 +590,12 @@ __global__ __launch_bounds__(kBlock) void k_filter_scatter(View g, const int32_t
         for (int k = 0; k < kIt; ++k) {
             a[k] = b[k] = 0;
             wt[k] = id[k] = 0;
-            if ((mk[k] >> lane) & 1) {
+            if ((mk[k] >> lane) & 1) {   // read once: non-temporal, the codes stay in the L2
                 const int64_t e = (w0 + k) * kWave + lane;
-                a[k] = g.u[e];
-                b[k] = g.v[e];
-                wt[k] = g.w[e];
-                id[k] = ORIG ? (uint32_t)e : g.id[e];
+                a[k] = __builtin_nontemporal_load(g.u + e);
+                b[k] = __builtin_nontemporal_load(g.v + e);
+                wt[k] = __builtin_nontemporal_load(g.w + e);
+                id[k] = ORIG ? (uint32_t)e : __builtin_nontemporal_load(g.id + e);
             }
         }
 #pragma unroll
