@@ -136,6 +136,32 @@ int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m
                 msf_stats* stats);
 
 /*
+ * msf_compute_noalloc -- msf_compute for callers that cannot allocate device
+ * memory: code that must not call hipMalloc (tight serving loops, harnesses
+ * that forbid allocation, callers preparing work for stream capture).  The
+ * workspace is a library-owned static device array of
+ * MSF_NOALLOC_SCRATCH_BYTES on each GPU the library runs on, obtained once
+ * per GPU on the first call there and held until the process ends; the host
+ * counter block is ordinary host memory; the kernel-timing profiler is not
+ * used.  Nothing is allocated by the call.
+ *   u, v, w, m, n, mask_out, total_weight_out, opt, stats: as msf_compute
+ *   stream        a hipStream_t of the CURRENT device (the scratch copy used
+ *                 is the current device's)
+ * Limit: msf_workspace_bytes(m, n, opt) must not exceed
+ * MSF_NOALLOC_SCRATCH_BYTES (e.g. plain Borůvka on up to about 2.6 million
+ * edges plus vertices), else MSF_EWORKSPACE with the sizes in
+ * msf_last_error().  Every call on one GPU uses that GPU's one array, whose
+ * contents persist from call to call (each call clears what it needs), so two
+ * overlapping calls on one GPU would race: the library serialises its own
+ * calls per GPU with a host lock, and the caller must not run other work on
+ * the array.  Blocking, like msf_compute.
+ */
+#define MSF_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int msf_compute_noalloc(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
+                        int64_t n, uint8_t* mask_out, uint64_t* total_weight_out, void* stream,
+                        const msf_options* opt, msf_stats* stats);
+
+/*
  * Batched MSF: G independent graphs solved by one persistent kernel (graph g
  * is a whole problem in the sense of msf_compute; all paper Sec. II-C rounds
  * run inside the kernel).  A graph with at least coop_edges edges is solved

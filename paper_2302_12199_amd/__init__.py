@@ -74,7 +74,7 @@ class MSFError(RuntimeError):
 _LIB = None
 
 # Exported C symbols (each declared in include/msf.h).
-SYMBOLS = ("msf_workspace_bytes", "msf_compute", "msf_status_string", "msf_last_error",
+SYMBOLS = ("msf_workspace_bytes", "msf_compute", "msf_compute_noalloc", "msf_status_string", "msf_last_error",
            "msf_version", "msf_profile_enable", "msf_profile_reset", "msf_profile_read",
            "msf_batched_workspace_bytes", "msf_compute_batched", "msf_batched_graph_create",
            "msf_batched_graph_launch", "msf_batched_graph_destroy", "msf_batched_autotune",
@@ -107,6 +107,10 @@ def _lib():
         lib.msf_compute.argtypes = [vp, vp, vp, i64, i64, vp, ctypes.POINTER(ctypes.c_uint64),
                                     vp, sz, vp, ctypes.POINTER(Options), ctypes.POINTER(Stats)]
         lib.msf_compute.restype = ctypes.c_int
+        lib.msf_compute_noalloc.argtypes = [vp, vp, vp, i64, i64, vp,
+                                            ctypes.POINTER(ctypes.c_uint64), vp,
+                                            ctypes.POINTER(Options), ctypes.POINTER(Stats)]
+        lib.msf_compute_noalloc.restype = ctypes.c_int
         lib.msf_status_string.argtypes = [ctypes.c_int]
         lib.msf_status_string.restype = ctypes.c_char_p
         lib.msf_last_error.restype = ctypes.c_char_p
@@ -194,6 +198,32 @@ def compute(u, v, w, n, *, workspace=None, mask_out=None, stream=None, **opts):
                          mask_out.data_ptr(), ctypes.byref(total), workspace.data_ptr(),
                          workspace.numel(), ctypes.c_void_p(s.cuda_stream), ctypes.byref(o),
                          ctypes.byref(st))
+    if rc != OK:
+        raise MSFError(rc, lib.msf_last_error().decode(errors="replace"))
+    return mask_out, int(total.value), st.to_dict()
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20      # MSF_NOALLOC_SCRATCH_BYTES in msf.h
+
+
+def compute_noalloc(u, v, w, n, *, mask_out, stream=None, **opts):
+    """MSF through msf_compute_noalloc: the library's static per-GPU scratch
+    is the workspace, so the call allocates nothing (``mask_out`` must be
+    given).  Same results as compute(); raises MSFError(EWORKSPACE) when the
+    graph needs more than NOALLOC_SCRATCH_BYTES of workspace."""
+    lib = _lib()
+    u, v, w = _dev_i32(u, "u"), _dev_i32(v, "v"), _dev_i32(w, "w")
+    m = u.numel()
+    if v.numel() != m or w.numel() != m or mask_out.numel() < m:
+        raise ValueError("u, v, w, mask_out lengths differ")
+    o = make_options(**opts)
+    s = stream if stream is not None else torch.cuda.current_stream(u.device)
+    total = ctypes.c_uint64(0)
+    st = Stats()
+    rc = lib.msf_compute_noalloc(u.data_ptr(), v.data_ptr(), w.data_ptr(), m, int(n),
+                                 mask_out.data_ptr(), ctypes.byref(total),
+                                 ctypes.c_void_p(s.cuda_stream), ctypes.byref(o),
+                                 ctypes.byref(st))
     if rc != OK:
         raise MSFError(rc, lib.msf_last_error().decode(errors="replace"))
     return mask_out, int(total.value), st.to_dict()

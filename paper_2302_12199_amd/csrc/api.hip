@@ -49,7 +49,12 @@ bool prof_on() {
     return g_prof.on;
 }
 
+namespace {
+thread_local bool t_prof_off = false;   // set for calls that must create no events
+}
+
 int prof_begin(int kid, hipStream_t s) {
+    if (t_prof_off) return -1;
     std::lock_guard<std::mutex> l(g_prof.mu);
     if (!g_prof.on) return -1;
     std::pair<hipEvent_t, hipEvent_t> ev;
@@ -78,27 +83,59 @@ void prof_add(int kid, double bytes) {
     if (g_prof.on) g_prof.bytes[kid] += bytes;
 }
 
+// Resolves the launches whose end event has completed; launches of calls
+// still running on other streams stay pending.
 void prof_resolve() {
     std::lock_guard<std::mutex> l(g_prof.mu);
-    for (auto& p : g_prof.pending) {
+    size_t keep = 0;
+    for (size_t i = 0; i < g_prof.pending.size(); ++i) {
+        auto& p = g_prof.pending[i];
+        if (hipEventQuery(p.b) == hipErrorNotReady) {
+            g_prof.pending[keep++] = p;
+            continue;
+        }
         float t = 0.f;
         if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
             g_prof.launches[p.kid] += 1;
             g_prof.ms[p.kid] += t;
             g_prof.bytes[p.kid] += p.bytes;
         }
+        (void)hipGetLastError();
         g_prof.pool.push_back({p.a, p.b});
     }
-    g_prof.pending.clear();
+    g_prof.pending.resize(keep);
 }
 
 // ------------------------------------------------------- counter read-back
+// Every call reads the device control block into a host block of its own, so
+// calls on different streams (or threads) run side by side: msf_compute takes
+// a pinned block from a pool (allocated on first need, kept for reuse),
+// msf_compute_noalloc reads into ordinary host memory.
 namespace {
-std::mutex g_solve_mu;       // one solve at a time per process (shared pinned block)
-Ctrl* g_host_ctrl = nullptr;
+std::mutex g_pool_mu;
+std::vector<Ctrl*> g_pinned_free;
+thread_local Ctrl* t_host_ctrl = nullptr;
+
+int take_pinned_ctrl(Ctrl** out) {
+    {
+        std::lock_guard<std::mutex> l(g_pool_mu);
+        if (!g_pinned_free.empty()) {
+            *out = g_pinned_free.back();
+            g_pinned_free.pop_back();
+            return MSF_OK;
+        }
+    }
+    HIP_TRY(hipHostMalloc((void**)out, sizeof(Ctrl), hipHostMallocDefault));
+    return MSF_OK;
+}
+
+void give_pinned_ctrl(Ctrl* c) {
+    std::lock_guard<std::mutex> l(g_pool_mu);
+    g_pinned_free.push_back(c);
+}
 }  // namespace
 
-Ctrl* host_ctrl() { return g_host_ctrl; }
+Ctrl* host_ctrl() { return t_host_ctrl; }
 
 int read_ctrl(const Ctrl* dctrl, Ctrl* host, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(host, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -135,12 +172,14 @@ int check_args(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
 bool use_filter(const msf_options* opt) { return opt && opt->algo == MSF_ALGO_FILTER; }
 bool round0_buckets(const msf_options* opt) { return !opt || opt->round0 != MSF_ROUND0_EDGES; }
 
+// `hc`: the host block this call reads the device counters into.
 int solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,
           uint8_t* mask, uint64_t* total_out, char* ws, hipStream_t s, const msf_options* opt,
-          msf_stats* stats) {
-    std::lock_guard<std::mutex> lock(g_solve_mu);
-    if (!g_host_ctrl)
-        HIP_TRY(hipHostMalloc((void**)&g_host_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+          msf_stats* stats, Ctrl* hc) {
+    struct Bind {
+        explicit Bind(Ctrl* c) { t_host_ctrl = c; }
+        ~Bind() { t_host_ctrl = nullptr; }
+    } bind(hc);
     msf_stats local;
     memset(&local, 0, sizeof local);
     msf_stats* st = stats ? stats : &local;
@@ -151,16 +190,16 @@ int solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int6
         EngineBuffers B;
         engine_carve(ws, m, n, &B, round0_buckets(opt));
         B.round0 = opt ? opt->round0 : MSF_ROUND0_AUTO;
-        HIP_TRY(hipMemsetAsync(B.ctrl, 0, sizeof(Ctrl), s));
+        launch_zero_bytes((uint8_t*)B.ctrl, sizeof(Ctrl), s);
         int h = prof_begin(K_FILL, s);
         launch_zero_bytes(mask, m, s);
         prof_end(h, s, (double)m);
         View g{u, v, nullptr, w, nullptr, m};
         rc = engine_solve(B, kOrig, g, n, mask, nullptr, s, st);
         if (rc == MSF_OK) {
-            rc = read_ctrl(B.ctrl, g_host_ctrl, s);
-            st->total_weight = g_host_ctrl->total;
-            st->msf_edges = g_host_ctrl->msf_edges;
+            rc = read_ctrl(B.ctrl, hc, s);
+            st->total_weight = hc->total;
+            st->msf_edges = hc->msf_edges;
             st->base_cases = 1;
         }
     }
@@ -205,7 +244,12 @@ int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m
         }
         owned = true;
     }
-    st = solve(u, v, w, m, n, mask_out, total_weight_out, (char*)ws, s, opt, stats);
+    Ctrl* hc = nullptr;
+    st = take_pinned_ctrl(&hc);
+    if (st == MSF_OK) {
+        st = solve(u, v, w, m, n, mask_out, total_weight_out, (char*)ws, s, opt, stats, hc);
+        give_pinned_ctrl(hc);
+    }
     if (owned) {
         hipError_t e = hipFreeAsync(ws, s);
         hipError_t e2 = hipStreamSynchronize(s);
@@ -214,6 +258,65 @@ int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m
             st = MSF_EDEVICE;
         }
     }
+    return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ no-allocation entry
+// The workspace of msf_compute_noalloc: one array per GPU, held by the loaded
+// library until the process ends.  On the host this name only stands for the
+// symbol; the device address of each GPU's copy comes from
+// hipGetSymbolAddress, and only that address is ever handed to kernels.
+static __device__ __attribute__((aligned(256))) char scratch[MSF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu[kScratchDevices];      // per GPU: set-up, then one call at a time
+void* g_scratch_dev[kScratchDevices] = {};     // per GPU: device address of `scratch`
+}  // namespace
+
+extern "C" {
+
+int msf_compute_noalloc(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
+                        int64_t n, uint8_t* mask_out, uint64_t* total_weight_out, void* stream,
+                        const msf_options* opt, msf_stats* stats) {
+    int st = check_args(u, v, w, m, n, mask_out, total_weight_out, opt);
+    if (st) return st;
+    if (stats) memset(stats, 0, sizeof *stats);
+    if (m == 0) {
+        *total_weight_out = 0;
+        if (stats) stats->base_cases = 1;
+        return MSF_OK;
+    }
+    const size_t need = msf_workspace_bytes(m, n, opt);
+    if (need > (size_t)MSF_NOALLOC_SCRATCH_BYTES) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "msf_compute_noalloc: the graph needs %zu workspace bytes, the static "
+                 "scratch holds %zu",
+                 need, (size_t)MSF_NOALLOC_SCRATCH_BYTES);
+        set_err_text(buf);
+        return MSF_EWORKSPACE;
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) {
+        set_err_text("msf_compute_noalloc: device index beyond the scratch table");
+        return MSF_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    if (!g_scratch_dev[dev]) {           // first call on this GPU, with it current
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_dev[dev] = p;
+    }
+    Ctrl hc;                              // ordinary host memory: nothing is allocated
+    const bool prof_was_off = t_prof_off;
+    t_prof_off = true;                    // the profiler would create events
+    st = solve(u, v, w, m, n, mask_out, total_weight_out, (char*)g_scratch_dev[dev],
+               (hipStream_t)stream, opt, stats, &hc);
+    t_prof_off = prof_was_off;
     return st;
 }
 

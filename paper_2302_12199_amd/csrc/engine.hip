@@ -204,7 +204,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
                 set_err_text("pointer jumping did not converge");
                 return MSF_EINTERNAL;
             }
-            HIP_TRY(hipMemsetAsync(&dc->jump_more, 0, sizeof(uint32_t), s));
+            launch_zero_bytes((uint8_t*)&dc->jump_more, sizeof(uint32_t), s);
         }
         if (hc->err & kErrRange) return MSF_ERANGE;
         if (hc->err) {
@@ -307,7 +307,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         int next_mode = mode;
         const int32_t* next_cmap = nullptr;
         int64_t next_nc = nn;
-        HIP_TRY(hipMemsetAsync(&dc->m_next, 0, sizeof(uint64_t), s));
+        launch_fill_u64(&dc->m_next, 1, 0, s);
         if (compact) {
             EdgeSoA out = B.cbuf[cbsel];
             cbsel ^= 1;

@@ -766,7 +766,7 @@ View view_of(const EdgeSoA& e, int64_t len) {
 int compress_p(Ctx& C) {
     Ctrl* hc = host_ctrl();
     for (int attempt = 0;; ++attempt) {
-        HIP_TRY(hipMemsetAsync(&C.B.ctrl->jump_more, 0, sizeof(uint32_t), C.s));
+        launch_zero_bytes((uint8_t*)&C.B.ctrl->jump_more, sizeof(uint32_t), C.s);
         const int h = prof_begin(K_PMAINT, C.s);
         launch_jump(C.P, C.n, 32, C.B.ctrl, C.s);
         prof_end(h, C.s, 12.0 * C.n);
@@ -927,7 +927,7 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
     C.min_split = opt.min_split_edges > 0 ? opt.min_split_edges : (1 << 20);
     C.sparse_deg = opt.sparse_degree > 0 ? opt.sparse_degree : 4;
 
-    HIP_TRY(hipMemsetAsync(C.B.ctrl, 0, sizeof(Ctrl), s));
+    launch_zero_bytes((uint8_t*)C.B.ctrl, sizeof(Ctrl), s);
     int h = prof_begin(K_FILL, s);
     launch_zero_bytes(mask, m, s);
     launch_iota(C.P, n, s);

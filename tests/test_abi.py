@@ -148,3 +148,30 @@ def test_batched_argument_checks(msf):
     # an empty batch needs no device
     assert lib.msf_compute_batched(None, None, None, None, None, 0, 0, None, None, None, None,
                                    None, 0, None, None) == msf.OK
+
+
+def test_noalloc_argument_checks_before_the_device(msf):
+    lib = msf.library()
+    total = ctypes.c_uint64(0)
+    # beyond the static scratch: rejected before any device call
+    m, n = 4 << 20, 1 << 20
+    assert msf.workspace_bytes(m, n) > msf.NOALLOC_SCRATCH_BYTES
+    rc = lib.msf_compute_noalloc(FAKE, FAKE, FAKE, m, n, FAKE, ctypes.byref(total), None, None,
+                                 None)
+    assert rc == msf.EWORKSPACE
+    assert b"static scratch" in lib.msf_last_error()
+    assert lib.msf_compute_noalloc(FAKE, FAKE, FAKE, 10, 0, FAKE, ctypes.byref(total), None,
+                                   None, None) == msf.EINVAL
+    assert lib.msf_compute_noalloc(FAKE, 0, FAKE, 10, 5, FAKE, ctypes.byref(total), None,
+                                   None, None) == msf.EINVAL
+    o = msf.make_options(quantile=2.0)
+    assert lib.msf_compute_noalloc(FAKE, FAKE, FAKE, 10, 5, FAKE, ctypes.byref(total), None,
+                                   ctypes.byref(o), None) == msf.EINVAL
+    st = msf.Stats()
+    assert lib.msf_compute_noalloc(None, None, None, 0, 3, None, ctypes.byref(total), None,
+                                   None, ctypes.byref(st)) == msf.OK
+    assert total.value == 0 and st.base_cases == 1
+    # the scratch size in the binding is the header's
+    text = open(os.path.join(ROOT, "include", "msf.h")).read()
+    assert "#define MSF_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)" in text
+    assert msf.NOALLOC_SCRATCH_BYTES == 128 << 20
