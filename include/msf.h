@@ -109,6 +109,7 @@ typedef struct msf_stats {
     uint64_t split_kept[MSF_MAX_TRACE];   /* heavy edges surviving the filter */
     float split_q[MSF_MAX_TRACE];         /* sample quantile used by the split */
     float top_features[16];     /* pivot-network features of the first split's sample */
+    float split_features[MSF_MAX_TRACE][16];  /* the same for every traced split */
 } msf_stats;
 
 /* Bytes of device workspace msf_compute needs for (m, n, opt); opt may be NULL. */

@@ -17,6 +17,10 @@ Contents (each restates the paper's definitions, Sec. II-B and II-C):
                    live vertex and edge counts of every round
 * ``filter_*``     the pieces of Filter-Borůvka (Sec. V, Alg. 2): pivot
                    sampling, light/heavy split and heavy-edge filtering
+                   (filter_ref.py), and the same per-split trace from set
+                   definitions (filter_def.py)
+* ``features``     the pivot network's sample statistics (features.py)
+* ``mlp_ref``      the pivot network in float64 (mlp_ref.py)
 """
 from __future__ import annotations
 

@@ -11,13 +11,17 @@
  *   (3) cycle property: every other non-self-loop edge e is heavier than
  *       every F edge on the F-path between its endpoints (otherwise swapping
  *       would give a lighter forest).
- * (1)+(2) make F a spanning forest; (3) is the optimality certificate, and it
- * makes F unique because the order is strict.  Path maxima come from binary
- * lifting on F rooted by BFS, so the check costs O((n + m) log n).
+ * (1)+(2) make F a spanning forest: an acyclic F with n - c edges has
+ * exactly c trees, none crossing a component, hence one per component, so
+ * the two ends of every edge lie in one F-tree.  (3) is the optimality
+ * certificate, and it makes F unique because the order is strict.  Path
+ * maxima come from binary lifting on F rooted by BFS, so the check costs
+ * O((n + m) log n).
  *
  * Return value: 0 = valid MSF, 1 = self-loop in F, 2 = cycle in F,
- * 3 = |F| != n - c, 4 = an edge joins two different F-trees,
- * 5 = cycle property violated, <0 = bad input / out of memory.
+ * 3 = |F| != n - c, 5 = cycle property violated, <0 = bad input / out of
+ * memory.  (Code 4 is not used: an edge joining two F-trees cannot remain
+ * once (1) and (2) hold.)
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -118,7 +122,6 @@ int oracle_msf_check(const int32_t* u, const int32_t* v, const uint32_t* w, int6
     for (int64_t e = 0; e < m && !rc; ++e) {
         if (mask[e] || u[e] == v[e]) continue;
         int64_t a = u[e], b = v[e];
-        if (find_root(tree, a) != find_root(tree, b)) { rc = 4; break; }
         uint64_t best = 0;
         if (depth[a] < depth[b]) { int64_t t = a; a = b; b = t; }
         int32_t diff = depth[a] - depth[b];

@@ -24,13 +24,16 @@ it does not matter); components are kept in a union-find, so representative
 labels differ from the GPU's, which does not change any count or pivot.
 
 Returns the MSF mask, total weight and one trace record per split, in the
-depth-first order the recursion visits them.
+depth-first order the recursion visits them; each record also holds the
+pivot-network features of its sample (features.py), computed on the split's
+edges named by their union-find representatives.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import kruskal
+from .features import sample_features
 
 GAMMA = 0x9E3779B97F4A7C15
 MASK64 = (1 << 64) - 1
@@ -112,7 +115,8 @@ def filter_boruvka(u, v, w, n, seed=1, sample=4096, q=0.5, sparse_degree=4,
         pivot = int(sk[pivot_index(qq, sample)])
         light = keys <= np.uint64(pivot)
         nl = int(light.sum())
-        rec_t = {"edges": k, "pivot": pivot, "light": nl, "kept": 0}
+        rec_t = {"edges": k, "pivot": pivot, "light": nl, "kept": 0,
+                 "features": sample_features(a, b, ww, pos, comps, depth)}
         trace.append(rec_t)
         if nl == 0 or nl == k:
             base(a, b, ww, ii)

@@ -64,6 +64,19 @@ def forward(p, x, bf=False):
     return z, (x, a1, h1, a2, h2, W2, w3)
 
 
+def magnitude(p, x):
+    """The forward pass on |parameters| and |x| (no activation): for each
+    sample, the sum of the absolute values of every product the network
+    adds up, propagated through the layers.  Rounding errors of a
+    floating-point evaluation of the network scale with it (a dot product of
+    k terms errs by at most k * u * the sum of its terms' magnitudes)."""
+    d = unpack(np.abs(np.asarray(p, np.float64)))
+    xa = np.abs(np.asarray(x, np.float64))
+    a1 = xa @ d["W1"].T + d["b1"]
+    a2 = a1 @ d["W2"].T + d["b2"]
+    return a2 @ d["w3"] + d["b3"][0]
+
+
 def loss_and_grad(p, x, t, bf=False):
     z, (xx, a1, h1, a2, h2, W2, w3) = forward(p, x, bf)
     B = len(z)

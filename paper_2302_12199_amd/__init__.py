@@ -46,7 +46,8 @@ class Stats(ctypes.Structure):
                 ("split_light", ctypes.c_uint64 * MAX_TRACE),
                 ("split_kept", ctypes.c_uint64 * MAX_TRACE),
                 ("split_q", ctypes.c_float * MAX_TRACE),
-                ("top_features", ctypes.c_float * 16)]
+                ("top_features", ctypes.c_float * 16),
+                ("split_features", (ctypes.c_float * 16) * MAX_TRACE)]
 
     def to_dict(self):
         r = min(self.rounds, MAX_TRACE)
@@ -59,7 +60,8 @@ class Stats(ctypes.Structure):
                 "filtered_in": int(self.filtered_in), "filtered_out": int(self.filtered_out),
                 "splits": [{"edges": int(self.split_edges[i]), "pivot": int(self.split_pivot[i]),
                             "light": int(self.split_light[i]), "kept": int(self.split_kept[i]),
-                            "q": float(self.split_q[i])}
+                            "q": float(self.split_q[i]),
+                            "features": [float(x) for x in self.split_features[i]]}
                            for i in range(min(self.levels, MAX_TRACE))],
                 "top_features": [float(x) for x in self.top_features]}
 

@@ -839,6 +839,7 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
         C.st->split_light[split] = (uint64_t)nl;
         C.st->split_q[split] = hc->q_used;
         C.st->split_kept[split] = 0;
+        memcpy(C.st->split_features[split], hc->feat, sizeof C.st->split_features[split]);
     }
     if (split == 0) {
         C.q_net = hc->q_used;

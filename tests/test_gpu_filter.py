@@ -15,8 +15,30 @@ from gpu_util import banner, golden_hashes, gpu_msf, sha
 pytestmark = pytest.mark.gpu
 
 
+def assert_features_close(got, ref, sample):
+    """The sampler's 16 pivot-network features (single precision on the
+    device) against the float64 oracle.  Bounds, from the arithmetic:
+    statistics of L(w) = log2(1 + w) / 32 come from one single-precision
+    log2 (about one ulp of a result below 1) of a rounded conversion, so
+    |error| <= 1e-6; the mean is a single-precision sum of up to 8192 such
+    terms (per-thread sums, then a tree), |error| <= 2e-6; the deviation is
+    sqrt(E[L^2] - mean^2) with both moments in single precision, so its
+    square is compared, |error| <= 1e-5; the tie and repeat fractions are
+    exact integer counts, compared as counts."""
+    g, r = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    idx = [0, 1, 2, 3, 4, 8, 9, 10, 11, 12, 13]
+    np.testing.assert_allclose(g[idx], r[idx], rtol=0, atol=1e-6)
+    assert abs(g[5] - r[5]) <= 2e-6, (g[5], r[5])
+    assert abs(g[6] ** 2 - r[6] ** 2) <= 1e-5, (g[6], r[6])
+    pairs = max(sample - 1, 1)
+    assert round(g[7] * pairs) == round(r[7] * pairs)
+    ends = 2 * min(sample, 2048) - 1
+    assert round(g[14] * ends) == round(r[14] * ends)
+    assert g[15] == 1.0
+
+
 def check_filter(u, v, w, n, seed=1, sample=4096, q=0.5, min_split=2000, sparse_degree=4,
-                 pivot="quantile"):
+                 pivot="quantile", definition=False):
     mask, total, st = gpu_msf(u, v, w, n, algo="filter", pivot=pivot, quantile=q, seed=seed,
                               sample_size=sample, min_split_edges=min_split,
                               sparse_degree=sparse_degree)
@@ -25,8 +47,19 @@ def check_filter(u, v, w, n, seed=1, sample=4096, q=0.5, min_split=2000, sparse_
     assert total == kt and st["msf_edges"] == kc
     _, _, trace = oracle.filter_boruvka(u, v, w, n, seed=seed, sample=sample, q=q,
                                         min_split=min_split, sparse_degree=sparse_degree)
+    if definition:      # the second, union-find-free formulation of the trace
+        from oracle.filter_def import trace_by_definition
+        td = trace_by_definition(u, v, w, n, seed=seed, sample=sample, q=q,
+                                 min_split=min_split, sparse_degree=sparse_degree)
+        assert [{k: t[k] for k in ("edges", "pivot", "light", "kept")} for t in td] == \
+            [{k: t[k] for k in ("edges", "pivot", "light", "kept")} for t in trace]
     got = [{k: s[k] for k in ("edges", "pivot", "light", "kept")} for s in st["splits"]]
-    assert got == trace[:len(got)] and len(got) == min(len(trace), 64)
+    want = [{k: t[k] for k in ("edges", "pivot", "light", "kept")} for t in trace]
+    assert got == want[:len(got)] and len(got) == min(len(trace), 64)
+    for s, t in zip(st["splits"], trace):
+        assert_features_close(s["features"], t["features"], sample)
+    if st["splits"]:
+        assert st["top_features"] == st["splits"][0]["features"]
     return st
 
 
@@ -60,6 +93,24 @@ def test_filter_sample_sizes(sample):
     n = 5000
     u, v, w = graphgen.gnm(n, 120000, 1, 2**31 - 1, seed=sample)
     check_filter(u, v, w, n, sample=sample, seed=sample + 7, min_split=3000)
+
+
+@pytest.mark.parametrize("kind", ["gnm", "rmat"])
+@pytest.mark.parametrize("sample", [1, 100, 4096, 8192])
+def test_filter_features_match_oracle(kind, sample):
+    """Every split's pivot-network features -- the top split reads the
+    caller's arrays, deeper ones the compacted buffers in label space --
+    against the float64 feature oracle on the same draws."""
+    banner(f"filter features {kind} sample={sample}")
+    if kind == "gnm":
+        n = 6000
+        u, v, w = graphgen.gnm(n, 150000, 1, 2**31 - 1, seed=50 + sample % 97)
+    else:
+        n = 1 << 13
+        u, v, w = graphgen.rmat(13, 200000, wlo=1, whi=255, seed=60 + sample % 89)
+    st = check_filter(u, v, w, n, sample=sample, seed=sample + 3, q=0.3, min_split=3000,
+                      definition=True)
+    assert len(st["splits"]) >= 2 and any(f["features"][13] > 0 for f in st["splits"])
 
 
 def test_filter_ties_and_selfloops():

@@ -34,9 +34,12 @@ def test_forward_fp32_matches_reference(B):
     rng = np.random.default_rng(B)
     p = _params(1)
     x = rng.normal(0, 1, (B, 16)).astype(np.float32)
-    z = msf.mlp_forward(_t(p), _t(x), bf16=False).cpu().numpy()
+    z = msf.mlp_forward(_t(p), _t(x), bf16=False).cpu().numpy().astype(np.float64)
     zr, _ = mlp_ref.forward(p.astype(np.float64), x.astype(np.float64))
-    np.testing.assert_allclose(z, zr, rtol=1e-4, atol=1e-4)
+    # single-precision sums: |error| <= (terms) * 2^-24 * magnitude in the worst
+    # case; demanded: one unit 2^-24 of the magnitude (measured: <= 0.07 of it)
+    M = mlp_ref.magnitude(p, x)
+    assert np.all(np.abs(z - zr) <= 2.0**-24 * M), np.max(np.abs(z - zr) / M)
 
 
 def test_forward_bf16_matches_reference():
@@ -46,12 +49,18 @@ def test_forward_bf16_matches_reference():
     rng = np.random.default_rng(5)
     p = _params(2)
     x = rng.normal(0, 1, (513, 16)).astype(np.float32)
-    z = msf.mlp_forward(_t(p), _t(x), bf16=True).cpu().numpy()
+    z = msf.mlp_forward(_t(p), _t(x), bf16=True).cpu().numpy().astype(np.float64)
     zr, _ = mlp_ref.forward(p.astype(np.float64), x.astype(np.float64), bf=True)
     z32, _ = mlp_ref.forward(p.astype(np.float64), x.astype(np.float64), bf=False)
-    # rounding of hidden activations can flip one bf16 step where the FP32 and
-    # float64 sums straddle a rounding boundary: allow a few bf16 ulps
-    np.testing.assert_allclose(z, zr, rtol=2e-2, atol=2e-2)
+    # inputs and weights round identically on both sides; the sums do not, and
+    # where a hidden activation's single- and double-precision sums straddle a
+    # bfloat16 rounding boundary that activation differs by one bfloat16 step
+    # (2^-8 of itself).  Such flips are rare: at most 1% of the outputs may
+    # differ by more than the single-precision bound, each within 1e-2 |z| + 1e-3.
+    err = np.abs(z - zr)
+    M = mlp_ref.magnitude(p, x)
+    assert np.mean(err > 2.0**-24 * M) <= 0.01
+    assert np.all(err <= 1e-2 * np.abs(zr) + 1e-3), err.max()
     # and the bf16 path really rounds: it differs from the fp32 network
     assert np.abs(z - z32).max() > 1e-5
 
@@ -69,8 +78,11 @@ def test_gradient_matches_reference(bf16):
     g, loss = msf.mlp_grad(_t(p), _t(x), _t(t), bf16=bf16)
     g = g.cpu().numpy()
     lr, gr = mlp_ref.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t, bf=bf16)
-    tol = 3e-2 if bf16 else 1e-4
-    assert abs(float(loss.item()) - lr) <= tol * max(1.0, abs(lr))
+    # FP32: single-precision sums over the batch (measured <= 1e-7 of the
+    # largest gradient); bfloat16: a rare forward rounding flip moves one
+    # sample's contribution by 2^-8 of itself (measured <= 1e-6)
+    tol = 1e-3 if bf16 else 1e-5
+    assert abs(float(loss.item()) - lr) <= 1e-5 * max(1.0, abs(lr))
     scale = np.abs(gr).max()
     err = np.abs(g - gr).max()
     assert err <= tol * scale, (err, scale)
@@ -78,7 +90,7 @@ def test_gradient_matches_reference(bf16):
     for name, sl in (("W1", slice(0, 1024)), ("W2", slice(1088, 1088 + 4096))):
         num = np.linalg.norm(g[sl] - gr[sl])
         den = np.linalg.norm(gr[sl]) + 1e-12
-        assert num / den <= (5e-2 if bf16 else 1e-4), name
+        assert num / den <= tol, name
 
 
 def test_adam_step_matches_reference():
@@ -132,6 +144,32 @@ def test_training_reduces_loss():
     assert last < 0.1 * first, (first, last)
 
 
+def check_network_quantile(p, u, v, w, n, st, min_split):
+    """The quantile the network chose at the top split against the float64
+    network on the float64 feature oracle's features of the same draws; the
+    whole split trace (every split reuses that quantile) against the
+    step-by-step reference.  Tolerances: the network alone (GPU features fed
+    to the float64 network) differs only where a hidden activation's
+    bfloat16 rounding falls the other way after single- versus
+    double-precision sums (an input of the final sum moves by 2^-8 of
+    itself), |dq| <= 5e-3; end to end, an input feature within 1e-6 of a
+    bfloat16 rounding boundary can also round the other way, |dq| <= 1e-2."""
+    import oracle
+    from oracle import mlp_ref
+    qs = [s["q"] for s in st["splits"]]
+    _, _, trace = oracle.filter_boruvka(u, v, w, n, seed=1, sample=4096, min_split=min_split,
+                                        q_of_split=lambda i: qs[i])
+    got = [{k: s[k] for k in ("edges", "pivot", "light", "kept")} for s in st["splits"]]
+    assert got == [{k: t[k] for k in ("edges", "pivot", "light", "kept")} for t in trace]
+    feats = np.array(trace[0]["features"], np.float64)[None, :]
+    q_ref = mlp_ref.quantile(mlp_ref.forward(p.astype(np.float64), feats, bf=True)[0])[0]
+    assert abs(st["pivot_q_used"] - q_ref) <= 1e-2, (st["pivot_q_used"], q_ref)
+    gfeats = np.array(st["top_features"], np.float64)[None, :]
+    q_net = mlp_ref.quantile(mlp_ref.forward(p.astype(np.float64), gfeats, bf=True)[0])[0]
+    assert abs(st["pivot_q_used"] - q_net) <= 5e-3, (st["pivot_q_used"], q_net)
+    assert all(abs(q - st["pivot_q_used"]) < 1e-7 for q in qs)
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_msf_parity_with_network_pivot(seed):
     """Any pivot gives the same MSF: the network only changes the split."""
@@ -156,12 +194,7 @@ def test_msf_parity_with_network_pivot(seed):
     assert total == ref_total
     assert np.array_equal(mask.cpu().numpy().astype(bool), ref_mask.astype(bool))
     assert st["levels"] >= 1
-    # the pivot quantile used at the top split is the network's output on the
-    # features the sampler recorded
-    feats = np.array(st["top_features"], np.float64)[None, :]
-    z, _ = mlp_ref.forward(p.astype(np.float64), feats, bf=True)
-    q = mlp_ref.quantile(z)[0]
-    assert abs(st["splits"][0]["q"] - q) <= 2e-2 * max(q, 1 - q), (st["splits"][0]["q"], q)
+    check_network_quantile(p, u, v, w, n, st, min_split=4096)
     assert abs(st["splits"][0]["q"] - 0.5) > 1e-3
 
 
@@ -213,8 +246,4 @@ def test_shipped_model_parity_and_its_quantile():
     assert np.array_equal(mask.cpu().numpy().astype(bool), ref_mask.astype(bool))
     blob = open(msf.DEFAULT_MODEL, "rb").read()
     p = np.frombuffer(blob[16:], np.float32).astype(np.float64)
-    z, _ = mlp_ref.forward(p, np.array(st["top_features"], np.float64)[None, :], bf=True)
-    q = mlp_ref.quantile(z)[0]
-    assert abs(st["pivot_q_used"] - q) <= 2e-2 * max(q, 1 - q)
-    # every split of the call uses the top split's quantile
-    assert all(abs(s["q"] - st["pivot_q_used"]) < 1e-7 for s in st["splits"])
+    check_network_quantile(p, u, v, w, n, st, min_split=1 << 16)

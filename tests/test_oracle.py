@@ -172,7 +172,13 @@ def test_certificate_checker_rejects_wrong_forests():
     m2 = mask.copy(); m2[msf[5]] = 0
     assert oracle.check(u, v, w, n, m2)[0] == 3          # too few edges
     m2 = mask.copy(); m2[non[0]] = 1
-    assert oracle.check(u, v, w, n, m2)[0] in (2, 3)      # closes a cycle
+    assert oracle.check(u, v, w, n, m2)[0] == 2           # closes a cycle
+    # a self-loop marked in F (the graph gets one appended)
+    uu, vv, ww = (np.append(u, 17).astype(np.int32), np.append(v, 17).astype(np.int32),
+                  np.append(w, 1).astype(np.uint32))
+    m3 = np.append(mask, 1).astype(np.uint8)
+    assert oracle.check(uu, vv, ww, n, m3)[0] == 1
+    assert oracle.check(uu, vv, ww, n, np.append(mask, 0).astype(np.uint8))[0] == 0
     # swap: drop an MSF edge and add a heavier edge reconnecting the two trees
     rng = np.random.default_rng(0)
     found = False
