@@ -110,6 +110,7 @@ typedef struct msf_stats {
     float split_q[MSF_MAX_TRACE];         /* sample quantile used by the split */
     float top_features[16];     /* pivot-network features of the first split's sample */
     float split_features[MSF_MAX_TRACE][16];  /* the same for every traced split */
+    uint64_t round_vertices[MSF_MAX_TRACE];   /* vertex labels of each traced round (n_r) */
 } msf_stats;
 
 /* Bytes of device workspace msf_compute needs for (m, n, opt); opt may be NULL. */
@@ -181,9 +182,10 @@ int msf_compute_noalloc(const int32_t* u, const int32_t* v, const uint32_t* w, i
  *   mask_out       device uint8[edge_off[G]]: 1 iff the edge is in its graph's MSF
  *   totals_out     device uint64[G]: MSF weight per graph; UINT64_MAX marks a graph
  *                  with an id outside [0, n_g), n_g > max_n or more than 2^32-1 edges
- *   ticks_out      device uint64[G + 1] or NULL: wall-clock tick at which each
- *                  graph finished, [G] = tick at which the batch started
- *                  (rate: msf_wall_clock_khz)
+ *   ticks_out      device uint64[2G + 1] or NULL: wall-clock ticks (rate:
+ *                  msf_wall_clock_khz): [g] = graph g finished, [G] = the batch
+ *                  started, [G + 1 + g] = graph g was taken up by a workgroup
+ *                  (its service time is [g] - [G + 1 + g])
  *   workspace      device, >= msf_batched_workspace_bytes(G, max_n, opt) bytes,
  *                  256-byte aligned (else MSF_EINVAL)
  * Errors: MSF_EINVAL (bad host arguments), MSF_EWORKSPACE, MSF_EDEVICE.

@@ -47,7 +47,8 @@ class Stats(ctypes.Structure):
                 ("split_kept", ctypes.c_uint64 * MAX_TRACE),
                 ("split_q", ctypes.c_float * MAX_TRACE),
                 ("top_features", ctypes.c_float * 16),
-                ("split_features", (ctypes.c_float * 16) * MAX_TRACE)]
+                ("split_features", (ctypes.c_float * 16) * MAX_TRACE),
+                ("round_vertices", ctypes.c_uint64 * MAX_TRACE)]
 
     def to_dict(self):
         r = min(self.rounds, MAX_TRACE)
@@ -57,6 +58,7 @@ class Stats(ctypes.Structure):
                 "round_live": [int(x) for x in self.round_live[:r]],
                 "round_edges": [int(x) for x in self.round_edges[:r]],
                 "round_found": [int(x) for x in self.round_found[:r]],
+                "round_vertices": [int(x) for x in self.round_vertices[:r]],
                 "filtered_in": int(self.filtered_in), "filtered_out": int(self.filtered_out),
                 "splits": [{"edges": int(self.split_edges[i]), "pivot": int(self.split_pivot[i]),
                             "light": int(self.split_light[i]), "kept": int(self.split_kept[i]),
@@ -286,7 +288,8 @@ class Batch:
         m = int(eo[-1]) if self.G > 0 else 0
         self.mask = torch.empty(max(m, 1), dtype=torch.uint8, device=dev)
         self.totals = torch.empty(max(self.G, 1), dtype=torch.int64, device=dev)
-        self.ticks = torch.empty(self.G + 1, dtype=torch.int64, device=dev)
+        # [g] finish, [G] batch start, [G + 1 + g] start of graph g
+        self.ticks = torch.empty(2 * self.G + 1, dtype=torch.int64, device=dev)
         need = max(int(self.lib.msf_batched_workspace_bytes(self.G, self.max_n, None)),
                    int(self.lib.msf_batched_workspace_bytes(self.G, self.max_n,
                                                            ctypes.byref(self.options))))

@@ -54,7 +54,8 @@ struct BatchArgs {
     const int32_t* order;    // [G] processing order, or null
     uint8_t* mask;           // [eoff[G]]
     uint64_t* totals;        // [G]; ~0 for a graph with invalid input
-    uint64_t* ticks;         // [G + 1] completion clock per graph, [G] = batch start; or null
+    uint64_t* ticks;         // [2G + 1]: [g] graph g finished, [G] batch start,
+                             // [G + 1 + g] graph g started; or null
     BatchQueue* q;
     XcdWork* xw;             // [kMaxXcd]
     int32_t* big;            // [G] cooperative graphs in processing order (first q->nbig)

@@ -186,6 +186,7 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
     const int32_t* V = A.v + e0;
     const uint32_t* W = A.w + e0;
     uint8_t* mask = A.mask + e0;
+    if (tid == 0 && A.ticks) A.ticks[A.G + 1 + g] = wall_clock64();
     const bool bad_shape = n < 0 || n > cap || m < 0 || m > 0xffffffffLL;
     bool bad = bad_shape;
     uint64_t wsum = 0;
@@ -293,6 +294,7 @@ __device__ void coop_next_graph(const BatchArgs& A, XcdWork* X, uint32_t p) {
         const int64_t g = A.big[gi];
         const int64_t m = A.eoff[g + 1] - A.eoff[g];
         const int64_t n = A.voff[g + 1] - A.voff[g];
+        if (A.ticks) A.ticks[A.G + 1 + g] = wall_clock64();
         if (n < 0 || n > A.nmax || m < 0 || m > 0xffffffffLL) {
             A.totals[g] = kKeyMax;
             if (A.ticks) A.ticks[g] = wall_clock64();

@@ -242,6 +242,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             stats->round_live[rounds] = live;
             stats->round_edges[rounds] = (uint64_t)m_live;
             stats->round_found[rounds] = found;
+            stats->round_vertices[rounds] = (uint64_t)nr;
         }
         ++rounds;
 
@@ -296,6 +297,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
                     stats->round_live[rounds] = hc->tail_live[t];
                     stats->round_edges[rounds] = hc->tail_scan[t];
                     stats->round_found[rounds] = hc->tail_found[t];
+                    stats->round_vertices[rounds] = t == 0 ? (uint64_t)nn : hc->tail_live[t];
                 }
                 ++rounds;
             }

@@ -99,7 +99,11 @@ def test_batch_unordered_and_ticks():
     mask, totals = results(b)
     assert (mask == rm).all() and (totals == rt).all()
     ticks = b.ticks.cpu().numpy().view(np.uint64)
-    assert (ticks[:-1] >= ticks[-1]).all()
+    G = len(rt)
+    fin, start0, start = ticks[:G], ticks[G], ticks[G + 1:]
+    assert len(start) == G
+    # every graph starts after the batch and finishes after it started
+    assert (start >= start0).all() and (fin >= start).all()
 
 
 def test_batch_graph_capture_replays_match_eager():
