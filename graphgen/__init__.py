@@ -24,6 +24,7 @@ _LIB_PATH = os.path.join(_HERE, "libgraphgen.so")
 _lib = None
 
 TAG_GNM, TAG_RMAT, TAG_PERM, TAG_RMAT_W, TAG_GRID_KEEP, TAG_GRID_W, TAG_RGG = 1, 2, 3, 4, 5, 6, 7
+TAG_RGG3, TAG_RGG3_W, TAG_RHG, TAG_RHG_W = 9, 10, 11, 12
 
 
 def build(force: bool = True) -> str:
@@ -31,7 +32,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+            ["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-Wall", "-Wextra",
              os.path.join(_HERE, "graphgen.c"), "-o", tmp, "-lpthread", "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -54,6 +55,10 @@ def _load():
         lib.gg_grid_build.restype = vp
         lib.gg_rgg2d_build.argtypes = [i64, dbl, dbl, u64, ctypes.POINTER(i64)]
         lib.gg_rgg2d_build.restype = vp
+        lib.gg_rgg3d_build.argtypes = [i64, dbl, u32, u32, u64, ctypes.POINTER(i64)]
+        lib.gg_rgg3d_build.restype = vp
+        lib.gg_rhg_build.argtypes = [i64, dbl, u32, u32, u64, ctypes.POINTER(i64)]
+        lib.gg_rhg_build.restype = vp
         lib.gg_take.argtypes = [vp, vp, vp, vp]
         lib.gg_batch_plan.argtypes = [i64, dbl, dbl, dbl, dbl, u64, vp, vp]
         lib.gg_batch_fill.argtypes = [i64, i64, i64, vp, vp, vp, u32, u32, u64, vp, vp, vp]
@@ -119,6 +124,28 @@ def rgg2d(n: int, r: float, wscale: float = 1e6, seed: int = 4):
     """2D random geometric graph in the unit square, edge iff distance < r."""
     m = ctypes.c_int64(0)
     h = _load().gg_rgg2d_build(n, r, wscale, seed, ctypes.byref(m))
+    return _take(h, m.value)
+
+
+def rgg3d(n: int, r: float, wlo: int = 1, whi: int = 254, seed: int = 7):
+    """3D random geometric graph in the unit cube, edge iff distance < r,
+    weights uniform on [wlo, whi]."""
+    m = ctypes.c_int64(0)
+    h = _load().gg_rgg3d_build(n, r, wlo, whi, seed, ctypes.byref(m))
+    return _take(h, m.value)
+
+
+def rgg3d_radius(n: int, avg_deg: float) -> float:
+    """Radius giving expected average degree avg_deg in the unit cube
+    (boundary effects ignored): (4/3) pi r^3 (n - 1) = avg_deg."""
+    return (3.0 * avg_deg / (4.0 * math.pi * (n - 1))) ** (1.0 / 3.0)
+
+
+def rhg(n: int, avg_deg: float, wlo: int = 1, whi: int = 254, seed: int = 8):
+    """Random hyperbolic graph (threshold model, power-law exponent 3) of
+    expected average degree about avg_deg, weights uniform on [wlo, whi]."""
+    m = ctypes.c_int64(0)
+    h = _load().gg_rhg_build(n, avg_deg, wlo, whi, seed, ctypes.byref(m))
     return _take(h, m.value)
 
 
@@ -206,6 +233,16 @@ def _wl_rmat22():
     return (*rmat(22, 1 << 28, wlo=1, whi=2**31 - 1, seed=5), 1 << 22)
 
 
+def _wl_rgg3d():
+    n = 1 << 24
+    return (*rgg3d(n, rgg3d_radius(n, 16.0), 1, 254, seed=7), n)
+
+
+def _wl_rhg():
+    n = 1 << 24
+    return (*rhg(n, 16.0, 1, 254, seed=8), n)
+
+
 WORKLOADS = {
     "gnm_n2^16_m2^20": _wl_gnm_small,
     "rmat_n2^24_m2^28_w255": _wl_rmat24,
@@ -213,6 +250,8 @@ WORKLOADS = {
     "grid_4096x4096_keep0.8_w255": _wl_grid_u255,
     "rgg2d_n2^24_deg8": _wl_rgg,
     "rmat_n2^22_m2^28_w2^31": _wl_rmat22,
+    "rgg3d_n2^24_deg16_w254": _wl_rgg3d,
+    "rhg_n2^24_deg16_g3_w254": _wl_rhg,
 }
 
 

@@ -133,3 +133,62 @@ def rgg2d_bruteforce(n, r, wscale, seed):
             us.append(i); vs.append(i + 1 + j)
             ws.append(int(np.floor(wscale * np.sqrt(d2[j]) + 0.5)))
     return (np.array(us, np.int32), np.array(vs, np.int32), np.array(ws, np.uint32))
+
+
+TAG_RGG3, TAG_RGG3_W, TAG_RHG, TAG_RHG_W = 9, 10, 11, 12
+
+
+def _edge_weights(seed, tag, m, wlo, whi):
+    bw = base(seed, tag)
+    return (np.uint64(wlo) + below(draw(bw, np.arange(m, dtype=np.uint64)),
+                                   whi - wlo + 1)).astype(np.uint32)
+
+
+def rgg3d_bruteforce(n, r, wlo, whi, seed):
+    """All-pairs 3D RGG in the generator's id order (for small n only)."""
+    b = base(seed, TAG_RGG3)
+    t = np.arange(n, dtype=np.uint64)
+    x = (draw(b, 3 * t) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    y = (draw(b, 3 * t + 1) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    z = (draw(b, 3 * t + 2) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    G = min(max(1, int(np.floor(1.0 / r))), 1 << 10)
+    c = [np.minimum((a * G).astype(np.int64), G - 1) for a in (x, y, z)]
+    order = np.lexsort((np.arange(n), (c[2] * G + c[1]) * G + c[0]))
+    x, y, z = x[order], y[order], z[order]
+    us, vs = [], []
+    for i in range(n):
+        dx, dy, dz = x[i + 1:] - x[i], y[i + 1:] - y[i], z[i + 1:] - z[i]
+        js = np.nonzero(dx * dx + dy * dy + dz * dz < r * r)[0]
+        us += [i] * len(js)
+        vs += (i + 1 + js).tolist()
+    return (np.array(us, np.int32), np.array(vs, np.int32),
+            _edge_weights(seed, TAG_RGG3_W, len(us), wlo, whi))
+
+
+def rhg_bruteforce(n, avg_deg, wlo, whi, seed):
+    """All-pairs random hyperbolic graph (threshold model, alpha = 1) in the
+    generator's id order (for small n only).  Per-point values use the
+    platform's libm through the math module, the adjacency test plain
+    double arithmetic in the generator's order."""
+    import math
+    R = 2.0 * math.log(8.0 * n / (math.pi * avg_deg))
+    coshR = math.cosh(R)
+    b = base(seed, TAG_RHG)
+    t = np.arange(n, dtype=np.uint64)
+    u = (draw(b, 2 * t) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    phi = (draw(b, 2 * t + 1) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    order = np.lexsort((np.arange(n), phi))
+    A = 1.0 + u[order] * (coshR - 1.0)
+    phi = phi[order]
+    B = np.sqrt(A * A - 1.0)
+    C = np.array([math.cos(2.0 * math.pi * p) for p in phi.tolist()])
+    S = np.array([math.sin(2.0 * math.pi * p) for p in phi.tolist()])
+    us, vs = [], []
+    for i in range(n):
+        j = np.arange(i + 1, n)
+        adj = A[i] * A[j] - B[i] * B[j] * (C[i] * C[j] + S[i] * S[j]) < coshR
+        js = j[adj]
+        us += [i] * len(js)
+        vs += js.tolist()
+    return (np.array(us, np.int32), np.array(vs, np.int32),
+            _edge_weights(seed, TAG_RHG_W, len(us), wlo, whi))

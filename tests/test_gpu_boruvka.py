@@ -3,6 +3,8 @@
 Bar: the MSF mask must equal the oracle's byte for byte and the 64-bit total
 must be equal (integer work: bit-exact).  Per-round live-vertex and found-edge
 counts must equal the plain round oracle (oracle.boruvka_rounds)."""
+import hashlib
+
 import numpy as np
 import pytest
 
@@ -75,7 +77,8 @@ def test_closed_forms():
 
 
 @pytest.mark.parametrize("kind,size", [("gnm", 12), ("gnm", 17), ("rmat", 14), ("rmat", 18),
-                                       ("grid", 0), ("grid255", 0), ("rgg", 0)])
+                                       ("grid", 0), ("grid255", 0), ("rgg", 0), ("rgg3d", 17),
+                                       ("rhg", 17), ("rhg", 12)])
 def test_midsize_families_with_rounds(kind, size):
     banner(f"midsize {kind} {size}")
     if kind == "gnm":
@@ -89,6 +92,12 @@ def test_midsize_families_with_rounds(kind, size):
         u, v, w = graphgen.grid(301, 277, 0.8, 1 if kind == "grid255" else 0,
                                 1 if kind == "grid255" else 10**6,
                                 255 if kind == "grid255" else 10**6, seed=3)
+    elif kind == "rgg3d":
+        n = (1 << size) + 5
+        u, v, w = graphgen.rgg3d(n, graphgen.rgg3d_radius(n, 16), 1, 254, seed=size)
+    elif kind == "rhg":
+        n = (1 << size) + 3
+        u, v, w = graphgen.rhg(n, 16.0, 1, 254, seed=size)
     else:
         n = 90001
         u, v, w = graphgen.rgg2d(n, graphgen.rgg_radius(n, 8), 1e6, seed=4)
@@ -102,7 +111,8 @@ def test_config_gnm_2p16_2p20():
 
 
 FULL = ["rmat_n2^24_m2^28_w255", "grid_4096x4096_keep0.8_w1e6", "grid_4096x4096_keep0.8_w255",
-        "rgg2d_n2^24_deg8", "rmat_n2^22_m2^28_w2^31"]
+        "rgg2d_n2^24_deg8", "rmat_n2^22_m2^28_w2^31", "rgg3d_n2^24_deg16_w254",
+        "rhg_n2^24_deg16_g3_w254"]
 
 
 @pytest.mark.parametrize("name", FULL)
@@ -111,6 +121,8 @@ def test_fullsize_matches_stored_oracle(name):
     banner(f"full size {name} (stored oracle hash)")
     u, v, w, n = graphgen.workload(name)
     assert len(u) == ref["m"] and n == ref["n"]
+    assert hashlib.sha256(u.tobytes() + v.tobytes() + w.tobytes()).hexdigest() == \
+        ref["input_sha256"], "the generator produced a different input on this machine"
     mask, total, stats = gpu_msf(u, v, w, n)
     assert total == ref["total"] and stats["msf_edges"] == ref["msf_edges"]
     assert sha(mask) == ref["mask_sha256"]

@@ -47,6 +47,46 @@ def test_rgg_matches_bruteforce():
     assert same(a, b)
 
 
+@pytest.mark.parametrize("n,seed,deg", [(2000, 7, 12.0), (3001, 1, 16.0), (257, 3, 30.0)])
+def test_rgg3d_matches_bruteforce(n, seed, deg):
+    r = graphgen.rgg3d_radius(n, deg)
+    assert same(graphgen.rgg3d(n, r, 1, 254, seed), ref.rgg3d_bruteforce(n, r, 1, 254, seed))
+
+
+@pytest.mark.parametrize("n,seed,deg", [(2000, 8, 16.0), (3001, 2, 10.0), (400, 5, 40.0)])
+def test_rhg_matches_bruteforce(n, seed, deg):
+    assert same(graphgen.rhg(n, deg, 1, 254, seed), ref.rhg_bruteforce(n, deg, 1, 254, seed))
+
+
+def test_rgg3d_shape():
+    n = 1 << 18
+    u, v, w = graphgen.rgg3d(n, graphgen.rgg3d_radius(n, 16), 1, 254, seed=7)
+    assert (u < v).all() and w.min() >= 1 and w.max() <= 254
+    assert 14.0 < 2 * len(u) / n < 16.5        # boundary effects lower the degree a little
+    # lexicographic (u, v) order and no duplicates
+    key = u.astype(np.int64) * n + v
+    assert (np.diff(key) > 0).all()
+    # locality: ids are cell-major, so endpoints are close in id
+    assert np.median(np.abs(v.astype(np.int64) - u)) < n / 100
+
+
+def test_rhg_shape():
+    n = 1 << 18
+    u, v, w = graphgen.rhg(n, 16.0, 1, 254, seed=8)
+    assert (u < v).all() and w.min() >= 1 and w.max() <= 254
+    assert 14.0 < 2 * len(u) / n < 18.0
+    key = u.astype(np.int64) * n + v
+    assert (np.diff(key) > 0).all()
+    deg = np.bincount(u, minlength=n) + np.bincount(v, minlength=n)
+    # power law with exponent 3: a heavy tail (max degree far above the mean;
+    # P(deg >= k) ~ k^-2, so about 1 % of the vertices have degree >= 10x mean / ~3)
+    assert deg.max() > 100 * deg.mean()
+    frac = (deg >= 8 * deg.mean()).mean()
+    assert 1e-4 < frac < 5e-2
+    # angular ids: most edges join vertices close in id
+    assert np.median(np.abs(v.astype(np.int64) - u)) < n / 100
+
+
 def test_determinism_and_seed_dependence():
     a = graphgen.rmat(14, 100000, seed=3)
     assert same(a, graphgen.rmat(14, 100000, seed=3))

@@ -144,7 +144,7 @@ def test_total_vs_scipy():
     assert int(round(t.sum())) - nedges == total
 
 
-@pytest.mark.parametrize("kind", ["gnm", "rmat", "grid", "rgg"])
+@pytest.mark.parametrize("kind", ["gnm", "rmat", "grid", "rgg", "rgg3d", "rhg"])
 def test_certificate_checker_agrees(kind):
     if kind == "gnm":
         u, v, w = graphgen.gnm(4096, 40000, 1, 50, seed=3)
@@ -155,6 +155,12 @@ def test_certificate_checker_agrees(kind):
     elif kind == "grid":
         u, v, w = graphgen.grid(64, 80, 0.8, 0, 7, 7, seed=5)
         n = 64 * 80
+    elif kind == "rgg3d":
+        n = 6000
+        u, v, w = graphgen.rgg3d(n, graphgen.rgg3d_radius(n, 16), 1, 254, seed=6)
+    elif kind == "rhg":
+        n = 6000
+        u, v, w = graphgen.rhg(n, 16.0, 1, 254, seed=6)
     else:
         n = 5000
         u, v, w = graphgen.rgg2d(n, graphgen.rgg_radius(n, 8), 1e6, seed=6)
