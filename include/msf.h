@@ -72,6 +72,25 @@ typedef enum {
  * It costs msf_workspace_bytes about 24 extra bytes per edge and 8 per vertex. */
 typedef enum { MSF_ROUND0_AUTO = 0, MSF_ROUND0_EDGES = 1, MSF_ROUND0_BUCKETS = 2 } msf_round0;
 
+/* Parallel-edge removal (Sec. II-C makes it optional; Sec. VI-B filters with a
+ * hash table before sorting).  Only the lightest edge of a vertex pair can be
+ * in the MSF, so removing the others never changes the result:
+ *   MSF_DEDUP_AUTO   the per-tile prefilter on graphs whose ids show locality
+ *                    (a sample of 4096 edges, at least half joining ids less
+ *                    than 2^14 apart), where contracted components share many
+ *                    edges: round 0 then compacts the relabelled edges and every
+ *                    later round compacts with the prefilter; otherwise NEVER;
+ *   MSF_DEDUP_NEVER  parallel edges stay until the last pass before the
+ *                    single-workgroup tail (which keeps one edge per pair);
+ *   MSF_DEDUP_EXACT  every compaction keeps exactly the lightest edge of each
+ *                    vertex pair, through a global hash table (needs
+ *                    msf_workspace_bytes with this option: 32 more bytes per edge);
+ *   MSF_DEDUP_LOCAL  the per-tile prefilter at every compaction (an LDS hash
+ *                    table per tile of 2048 edges keeps the lightest edge of
+ *                    each pair in the tile), whatever the ids look like. */
+typedef enum { MSF_DEDUP_AUTO = 0, MSF_DEDUP_NEVER = 1, MSF_DEDUP_EXACT = 2,
+               MSF_DEDUP_LOCAL = 3 } msf_dedup;
+
 /* Options; a NULL pointer means {MSF_ALGO_BORUVKA, MSF_PIVOT_MEDIAN, 0.5, seed 1,
  * defaults}.  Every field only changes running time, never the result. */
 typedef struct msf_options {
@@ -83,7 +102,17 @@ typedef struct msf_options {
     int32_t sparse_degree;   /* filter isSparse: stop splitting when 2m'/n' <= this; 0 = 4 */
     int32_t min_split_edges; /* filter isSparse: stop splitting below this many edges; 0 = 2^20 */
     int32_t round0;          /* msf_round0: how round 0 on the caller's arrays is organised */
-    int32_t reserved[7];     /* must be zero */
+    int32_t dedup_policy;    /* msf_dedup: parallel-edge removal in the rounds */
+    int32_t split_retries;   /* filter: balanced-split retry (proof of Thm. 1): a split
+                                whose light fraction is more than 1/6 from the target
+                                quantile (for the median: a side outside [|E|/3,
+                                2|E|/3]) is drawn again, at most this many times per
+                                split (the last draw is kept); 0 = off */
+    int32_t defer_edges;     /* filter: a recursion below the top whose filtered heavy
+                                set has fewer edges than this hands it back to its
+                                caller, which filters it again with its own heavy
+                                edges (Sec. VI-C, further remarks); 0 = off */
+    int32_t reserved[4];     /* must be zero */
 } msf_options;
 
 #define MSF_MAX_TRACE 64
@@ -111,6 +140,10 @@ typedef struct msf_stats {
     float top_features[16];     /* pivot-network features of the first split's sample */
     float split_features[MSF_MAX_TRACE][16];  /* the same for every traced split */
     uint64_t round_vertices[MSF_MAX_TRACE];   /* vertex labels of each traced round (n_r) */
+    uint32_t split_attempts[MSF_MAX_TRACE];   /* pivot draws of each split (retry) */
+    uint64_t split_deferred_in[MSF_MAX_TRACE]; /* edges handed back by the light recursion */
+    uint32_t pivot_retries;     /* redraws over the call */
+    uint32_t deferrals;         /* filtered sets handed back to a caller */
 } msf_stats;
 
 /* Bytes of device workspace msf_compute needs for (m, n, opt); opt may be NULL. */

@@ -22,7 +22,9 @@ MAXKEY = np.uint64(2**64 - 1)
 def boruvka_rounds(u, v, w, n):
     """Returns (mask, total, rounds) where rounds is a list of dicts with
     ``live`` (vertices with an incident non-self-loop edge), ``edges``
-    (non-self-loop edges entering the round) and ``found`` (MSF edges picked
+    (non-self-loop edges entering the round), ``pairs`` (distinct vertex
+    pairs among them: the edges left once parallel edges are removed),
+    ``vertices`` (vertex labels of the round) and ``found`` (MSF edges picked
     in the round)."""
     u = np.asarray(u, np.int64)
     v = np.asarray(v, np.int64)
@@ -54,7 +56,9 @@ def boruvka_rounds(u, v, w, n):
         live_comp = np.zeros(ncomp, bool)
         live_comp[comp[live]] = True
         newid = np.cumsum(live_comp) - 1
+        lo, hi = np.minimum(cu, cv), np.maximum(cu, cv)
         rounds.append({"live": int(live.sum()), "edges": int(len(cu)),
+                       "pairs": int(len(np.unique(lo * nr + hi))), "vertices": int(nr),
                        "found": int(len(picked))})
         lu, lv = newid[comp[cu]], newid[comp[cv]]
         k2 = lu != lv

@@ -22,6 +22,7 @@ OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EWORKSPACE, EINTERNAL = 0, -1, -2, -3, -4, 
 ALGOS = {"boruvka": 0, "filter": 1}
 PIVOTS = {"median": 0, "quantile": 1, "mlp": 2}
 ROUND0 = {"auto": 0, "edges": 1, "buckets": 2}
+DEDUP = {"auto": 0, "never": 1, "exact": 2, "local": 3}
 MAX_TRACE = 64
 
 
@@ -30,7 +31,8 @@ class Options(ctypes.Structure):
                 ("quantile", ctypes.c_float), ("sample_size", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("sparse_degree", ctypes.c_int32),
                 ("min_split_edges", ctypes.c_int32), ("round0", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("dedup_policy", ctypes.c_int32), ("split_retries", ctypes.c_int32),
+                ("defer_edges", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -48,7 +50,10 @@ class Stats(ctypes.Structure):
                 ("split_q", ctypes.c_float * MAX_TRACE),
                 ("top_features", ctypes.c_float * 16),
                 ("split_features", (ctypes.c_float * 16) * MAX_TRACE),
-                ("round_vertices", ctypes.c_uint64 * MAX_TRACE)]
+                ("round_vertices", ctypes.c_uint64 * MAX_TRACE),
+                ("split_attempts", ctypes.c_uint32 * MAX_TRACE),
+                ("split_deferred_in", ctypes.c_uint64 * MAX_TRACE),
+                ("pivot_retries", ctypes.c_uint32), ("deferrals", ctypes.c_uint32)]
 
     def to_dict(self):
         r = min(self.rounds, MAX_TRACE)
@@ -63,9 +68,12 @@ class Stats(ctypes.Structure):
                 "splits": [{"edges": int(self.split_edges[i]), "pivot": int(self.split_pivot[i]),
                             "light": int(self.split_light[i]), "kept": int(self.split_kept[i]),
                             "q": float(self.split_q[i]),
+                            "attempts": int(self.split_attempts[i]),
+                            "deferred_in": int(self.split_deferred_in[i]),
                             "features": [float(x) for x in self.split_features[i]]}
                            for i in range(min(self.levels, MAX_TRACE))],
-                "top_features": [float(x) for x in self.top_features]}
+                "top_features": [float(x) for x in self.top_features],
+                "pivot_retries": int(self.pivot_retries), "deferrals": int(self.deferrals)}
 
 
 class MSFError(RuntimeError):
@@ -147,9 +155,13 @@ def library():
 
 
 def make_options(algo="boruvka", pivot="median", quantile=0.5, seed=1, sample_size=0,
-                 sparse_degree=0, min_split_edges=0, round0="auto"):
+                 sparse_degree=0, min_split_edges=0, round0="auto", dedup="auto",
+                 split_retries=0, defer_edges=0):
     o = Options()
+    o.split_retries = int(split_retries)
+    o.defer_edges = int(defer_edges)
     o.round0 = ROUND0[round0] if isinstance(round0, str) else int(round0)
+    o.dedup_policy = DEDUP[dedup] if isinstance(dedup, str) else int(dedup)
     o.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
     o.pivot = PIVOTS[pivot] if isinstance(pivot, str) else int(pivot)
     o.quantile = float(quantile)

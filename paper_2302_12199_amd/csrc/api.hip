@@ -29,7 +29,8 @@ namespace {
 const char* const kKernelNames[K_COUNT] = {
     "minedge_r0", "hook", "jump", "scan_roots", "label", "pass", "compact", "compose",
     "fill", "scan_prep", "sample", "partition", "filter", "rep_maint", "mlp", "batch", "tail",
-    "pass_r0", "bucket_index", "bucket_scatter", "bucket_min", "bucket_label", "bucket_pass"};
+    "pass_r0", "bucket_index", "bucket_scatter", "bucket_min", "bucket_label", "bucket_pass",
+    "dedup"};
 
 struct Profiler {
     std::mutex mu;
@@ -163,7 +164,11 @@ int check_args(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
         if (opt->sample_size < 0 || opt->sample_size > 8192) return MSF_EINVAL;
         if (opt->sparse_degree < 0 || opt->min_split_edges < 0) return MSF_EINVAL;
         if (opt->round0 < MSF_ROUND0_AUTO || opt->round0 > MSF_ROUND0_BUCKETS) return MSF_EINVAL;
-        for (int i = 0; i < 7; ++i)
+        if (opt->dedup_policy < MSF_DEDUP_AUTO || opt->dedup_policy > MSF_DEDUP_LOCAL)
+            return MSF_EINVAL;
+        if (opt->split_retries < 0 || opt->split_retries > 64 || opt->defer_edges < 0)
+            return MSF_EINVAL;
+        for (int i = 0; i < 4; ++i)
             if (opt->reserved[i]) return MSF_EINVAL;
     }
     return MSF_OK;
@@ -171,6 +176,7 @@ int check_args(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
 
 bool use_filter(const msf_options* opt) { return opt && opt->algo == MSF_ALGO_FILTER; }
 bool round0_buckets(const msf_options* opt) { return !opt || opt->round0 != MSF_ROUND0_EDGES; }
+bool exact_dedup(const msf_options* opt) { return opt && opt->dedup_policy == MSF_DEDUP_EXACT; }
 
 // `hc`: the host block this call reads the device counters into.
 int solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,
@@ -188,8 +194,9 @@ int solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int6
         rc = filter_solve(u, v, w, m, n, mask, ws, s, *opt, st);
     } else {
         EngineBuffers B;
-        engine_carve(ws, m, n, &B, round0_buckets(opt));
+        engine_carve(ws, m, n, &B, round0_buckets(opt), exact_dedup(opt));
         B.round0 = opt ? opt->round0 : MSF_ROUND0_AUTO;
+        B.dedup = opt ? opt->dedup_policy : MSF_DEDUP_AUTO;
         launch_zero_bytes((uint8_t*)B.ctrl, sizeof(Ctrl), s);
         int h = prof_begin(K_FILL, s);
         launch_zero_bytes(mask, m, s);
@@ -213,7 +220,8 @@ extern "C" {
 
 size_t msf_workspace_bytes(int64_t m, int64_t n, const msf_options* opt) {
     if (m < 0 || n < 0) return 0;
-    return use_filter(opt) ? filter_bytes(m, n, *opt) : engine_bytes(m, n, round0_buckets(opt));
+    return use_filter(opt) ? filter_bytes(m, n, *opt)
+                           : engine_bytes(m, n, round0_buckets(opt), exact_dedup(opt));
 }
 
 int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int64_t n,

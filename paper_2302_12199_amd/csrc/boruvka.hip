@@ -511,21 +511,110 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
 
 // ----------------------------------------------------------- compaction pass
 
+// Parallel-edge prefilter of one compaction tile (the hash-table prefilter of
+// the paper's Sec. VI-B, held in LDS): every live relabelled edge enters its
+// vertex pair into an open-addressing table and min-reduces its key (w << 32 |
+// position; positions are in edge-id order) into the pair's entry; only the
+// lightest edge of each pair in the tile survives.  A dropped edge has a
+// lighter parallel edge, with which it closes a cycle on which it is the
+// heaviest, so it is in no MSF (cycle property).  The table has twice as many
+// slots as a tile has edges, so every probe sequence ends.
+constexpr int kDedupSlots = 2 * kRelabelTile;
+
+__device__ __forceinline__ uint32_t pair_slot(uint64_t pair) {
+    return (uint32_t)((pair * 0x9E3779B97F4A7C15ULL) >> 40) & (kDedupSlots - 1);
+}
+
+// Inserts `pair` (never kKeyMax) and min-reduces `key` into its entry; returns the slot.
+__device__ __forceinline__ uint32_t dedup_insert(unsigned long long* s_pair,
+                                                 unsigned long long* s_min, uint64_t pair,
+                                                 uint64_t key) {
+    uint32_t slot = pair_slot(pair);
+    for (int probe = 0; probe < kDedupSlots; ++probe) {
+        const unsigned long long old = atomicCAS(&s_pair[slot], (unsigned long long)kKeyMax,
+                                                 (unsigned long long)pair);
+        if (old == kKeyMax || old == pair) break;
+        slot = (slot + 1) & (kDedupSlots - 1);
+    }
+    atomicMin(&s_min[slot], (unsigned long long)key);
+    return slot;
+}
+
+// Exact parallel-edge removal: a global open-addressing table of vertex pairs
+// (dslots entries, a power of two at least twice the edges) holds the
+// lightest key of each pair over the whole view.
+__device__ __forceinline__ uint64_t gpair_slot(uint64_t pair, int64_t dslots) {
+    return ((pair * 0x9E3779B97F4A7C15ULL) >> 20) & (uint64_t)(dslots - 1);
+}
+
+template <int IN>
+__global__ __launch_bounds__(kBlock) void k_dedup_insert(View g, const int32_t* __restrict__ M,
+                                                         unsigned long long* dpair,
+                                                         unsigned long long* dmin,
+                                                         int64_t dslots) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < g.len;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int32_t a, b;
+        load_ends<IN>(g, e, a, b);
+        if (a == b) continue;
+        a = M[a];
+        b = M[b];
+        if (a == b) continue;
+        const uint64_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
+        const uint64_t pair = (lo << 32) | hi;
+        const uint64_t key = ((uint64_t)g.w[e] << 32) | (uint64_t)e;
+        uint64_t slot = gpair_slot(pair, dslots);
+        for (int64_t probe = 0; probe < dslots; ++probe) {
+            const unsigned long long old = atomicCAS(&dpair[slot], (unsigned long long)kKeyMax,
+                                                     (unsigned long long)pair);
+            if (old == kKeyMax || old == pair) break;
+            slot = (slot + 1) & (uint64_t)(dslots - 1);
+        }
+        if (key < dmin[slot]) atomicMin(&dmin[slot], (unsigned long long)key);
+    }
+}
+
+// The lightest key of `pair` in the filled global table.
+__device__ __forceinline__ uint64_t gpair_min(const uint64_t* dpair, const uint64_t* dmin,
+                                              int64_t dslots, uint64_t pair) {
+    uint64_t slot = gpair_slot(pair, dslots);
+    for (int64_t probe = 0; probe < dslots; ++probe) {
+        const uint64_t p = dpair[slot];
+        if (p == pair) return dmin[slot];
+        if (p == kKeyMax) break;              // not entered: cannot happen for a live edge
+        slot = (slot + 1) & (uint64_t)(dslots - 1);
+    }
+    return kKeyMax;
+}
+
 // Relabel through M, drop self-loops and compact the survivors stably into
 // `out` (position order stays edge-id order).  FUSED: each survivor takes
-// part in the next round's minedge with key (w << 32 | new position).  All
-// inputs of a tile are read before its lookback completes and outputs land at
-// or before their inputs, so `out` may alias the view (in-place compaction).
-template <int IN, bool FUSED>
+// part in the next round's minedge with key (w << 32 | new position).  DEDUP
+// (DedupKind): the survivors are also reduced to the lightest edge per vertex
+// pair, within the tile (kDedupLocal, the prefilter above) or over the whole
+// view (kDedupExact, the global table).  All inputs of a tile are read before
+// its lookback completes and outputs land at or before their inputs, so `out`
+// may alias the view (in-place compaction).
+template <int IN, bool FUSED, int DEDUP>
 __global__ __launch_bounds__(kBlock) void k_compact(View g, const int32_t* __restrict__ M,
                                                     EdgeSoA out, uint64_t* __restrict__ best_next,
                                                     uint64_t* status, Ctrl* ctrl,
-                                                    uint32_t ntiles) {
+                                                    uint32_t ntiles, const uint64_t* dpair,
+                                                    const uint64_t* dmin, int64_t dslots) {
     constexpr int kIt = kRelabelItems;
+    constexpr int kTab = DEDUP == kDedupLocal ? kDedupSlots : 1;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wave[kBlock / kWave];
     __shared__ uint64_t s_prefix;
-    const uint32_t tile = take_tile(ctrl, &s_tile);
+    __shared__ unsigned long long s_pair[kTab];
+    __shared__ unsigned long long s_min[kTab];
+    if constexpr (DEDUP == kDedupLocal) {
+        for (int i = threadIdx.x; i < kTab; i += kBlock) {
+            s_pair[i] = kKeyMax;
+            s_min[i] = kKeyMax;
+        }
+    }
+    const uint32_t tile = take_tile(ctrl, &s_tile);   // its barrier also orders the clearing
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t e0 = (int64_t)tile * (kBlock * kIt) + (int64_t)wave * (kWave * kIt) + lane;
     const int64_t mr = g.len;
@@ -544,16 +633,50 @@ __global__ __launch_bounds__(kBlock) void k_compact(View g, const int32_t* __res
             id[k] = edge_id<IN>(g, e);
         }
     }
+    bool keep[kIt];
 #pragma unroll
     for (int k = 0; k < kIt; ++k) {
         const int64_t e = e0 + k * kWave;
-        bool keep = false;
+        keep[k] = false;
         if (e < mr && a[k] != b[k]) {
             a[k] = M[a[k]];
             b[k] = M[b[k]];
-            keep = a[k] != b[k];
+            keep[k] = a[k] != b[k];
         }
-        mk[k] = __ballot(keep);
+    }
+    if constexpr (DEDUP == kDedupExact) {
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            if (keep[k]) {
+                const uint32_t lo = (uint32_t)(a[k] < b[k] ? a[k] : b[k]);
+                const uint32_t hi = (uint32_t)(a[k] < b[k] ? b[k] : a[k]);
+                const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
+                keep[k] = gpair_min(dpair, dmin, dslots, ((uint64_t)lo << 32) | hi) == key;
+            }
+        }
+    }
+    if constexpr (DEDUP == kDedupLocal) {
+        uint32_t slot[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            slot[k] = 0;
+            if (keep[k]) {
+                const uint32_t lo = (uint32_t)(a[k] < b[k] ? a[k] : b[k]);
+                const uint32_t hi = (uint32_t)(a[k] < b[k] ? b[k] : a[k]);
+                const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
+                slot[k] = dedup_insert(s_pair, s_min, ((uint64_t)lo << 32) | hi, key);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
+            if (keep[k] && s_min[slot[k]] != key) keep[k] = false;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        mk[k] = __ballot(keep[k]);
         cnt += __popcll(mk[k]);
     }
     // Every load of this tile has returned before the tile's aggregate is
@@ -841,16 +964,46 @@ bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t 
     }
 }
 
-void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
-                    uint64_t* best_next, uint64_t* status, Ctrl* ctrl, hipStream_t s) {
-    if (g.len <= 0) return;
-    const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
+template <int DEDUP>
+static void launch_compact_t(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
+                             uint64_t* best_next, uint64_t* status, Ctrl* ctrl, uint32_t nt,
+                             const uint64_t* dp, const uint64_t* dm, int64_t ds, hipStream_t s) {
     const dim3 gr(nt), bl(kBlock);
     switch (in_mode) {
-        case kOrig: hipLaunchKernelGGL((k_compact<kOrig, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;
-        case kFull32: hipLaunchKernelGGL((k_compact<kFull32, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;
-        case kFull16: hipLaunchKernelGGL((k_compact<kFull16, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;
-        default: hipLaunchKernelGGL((k_compact<kCompact, true>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt); break;
+        case kOrig: hipLaunchKernelGGL((k_compact<kOrig, true, DEDUP>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt, dp, dm, ds); break;
+        case kFull32: hipLaunchKernelGGL((k_compact<kFull32, true, DEDUP>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt, dp, dm, ds); break;
+        case kFull16: hipLaunchKernelGGL((k_compact<kFull16, true, DEDUP>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt, dp, dm, ds); break;
+        default: hipLaunchKernelGGL((k_compact<kCompact, true, DEDUP>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt, dp, dm, ds); break;
+    }
+}
+
+void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
+                    uint64_t* best_next, uint64_t* status, Ctrl* ctrl, int dedup,
+                    const uint64_t* dpair, const uint64_t* dmin, int64_t dslots, hipStream_t s) {
+    if (g.len <= 0) return;
+    const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
+    if (dedup == kDedupExact && dslots > 0)
+        launch_compact_t<kDedupExact>(in_mode, g, M, out, best_next, status, ctrl, nt, dpair,
+                                      dmin, dslots, s);
+    else if (dedup != kDedupNone)
+        launch_compact_t<kDedupLocal>(in_mode, g, M, out, best_next, status, ctrl, nt, dpair,
+                                      dmin, dslots, s);
+    else
+        launch_compact_t<kDedupNone>(in_mode, g, M, out, best_next, status, ctrl, nt, dpair,
+                                     dmin, dslots, s);
+}
+
+void launch_dedup_insert(int in_mode, const View& g, const int32_t* M, uint64_t* dpair,
+                         uint64_t* dmin, int64_t dslots, hipStream_t s) {
+    if (g.len <= 0 || dslots <= 0) return;
+    const dim3 gr(grid_for(g.len, 4096)), bl(kBlock);
+    auto* p = (unsigned long long*)dpair;
+    auto* q = (unsigned long long*)dmin;
+    switch (in_mode) {
+        case kOrig: hipLaunchKernelGGL(k_dedup_insert<kOrig>, gr, bl, 0, s, g, M, p, q, dslots); break;
+        case kFull32: hipLaunchKernelGGL(k_dedup_insert<kFull32>, gr, bl, 0, s, g, M, p, q, dslots); break;
+        case kFull16: hipLaunchKernelGGL(k_dedup_insert<kFull16>, gr, bl, 0, s, g, M, p, q, dslots); break;
+        default: hipLaunchKernelGGL(k_dedup_insert<kCompact>, gr, bl, 0, s, g, M, p, q, dslots); break;
     }
 }
 

@@ -91,4 +91,8 @@ struct View {
 // Outputs of a streaming pass.
 enum PassOut { kOutNone = 0, kOut32 = 1, kOut16 = 2 };
 
+// Parallel-edge removal in a compaction: none, per tile (an LDS hash table),
+// or exact (a global hash table filled by a pass before the compaction).
+enum DedupKind { kDedupNone = 0, kDedupLocal = 1, kDedupExact = 2 };
+
 }  // namespace msf

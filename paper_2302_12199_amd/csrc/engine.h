@@ -23,15 +23,20 @@ struct EngineBuffers {
     int32_t* perm;        // tail: hot-first permutation of its vertices' labels
     uint32_t* list_xy[2];  // tail: pair list (ping-pong, compacted every round)
     uint64_t* list_key[2];
+    uint64_t* dpair;      // exact parallel-edge removal: global hash table, vertex pairs
+    uint64_t* dmin;       //   and the lightest key of each (dslots entries each)
+    int64_t dslots;       //   0 when the workspace holds no table
     BucketBuffers bk;     // bucketed round 0 (large graphs only)
     int round0;           // msf_round0: when round 0 runs by buckets
+    int dedup;            // msf_dedup: parallel-edge removal in the compactions
     int64_t ncap, mcap;
 };
 
-// buckets: also carve the bucketed round 0's buffers (for graphs it applies to).
-size_t engine_bytes(int64_t m, int64_t n, bool buckets);
+// buckets: also carve the bucketed round 0's buffers (for graphs it applies to);
+// exact: also carve the global pair table of exact parallel-edge removal.
+size_t engine_bytes(int64_t m, int64_t n, bool buckets, bool exact);
 // Carves buffers starting at ws; returns the bytes used.
-size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool buckets);
+size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool buckets, bool exact);
 
 // Runs Borůvka rounds until no edge is left.
 //   view/mode   the current graph: kOrig (the caller's arrays; round 0 runs

@@ -34,7 +34,8 @@ constexpr int64_t kMax16 = 65535;       // label count that still fits the packe
 constexpr int64_t kPreTailMinEdges = 1 << 23;   // smaller views are not worth renumbering
 }  // namespace
 
-size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool buckets) {
+size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool buckets,
+                    bool exact) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -68,17 +69,27 @@ size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool bucke
         b.list_xy[i] = (uint32_t*)take(slots * 4);
         b.list_key[i] = (uint64_t*)take(slots * 8);
     }
+    b.dpair = b.dmin = nullptr;
+    b.dslots = 0;
+    if (exact) {   // a power of two of at least twice the edges: probing always ends
+        int64_t sl = 1024;
+        while (sl < 2 * (int64_t)mm) sl <<= 1;
+        b.dslots = sl;
+        b.dpair = (uint64_t*)take((size_t)sl * 8);
+        b.dmin = (uint64_t*)take((size_t)sl * 8);
+    }
     if (buckets) off += bucket_carve(ws ? ws + off : nullptr, m, n, &b.bk);
     else b.bk = BucketBuffers{};
     b.round0 = MSF_ROUND0_AUTO;
+    b.dedup = MSF_DEDUP_AUTO;
     b.ncap = n;
     b.mcap = m;
     if (B) *B = b;
     return off;
 }
 
-size_t engine_bytes(int64_t m, int64_t n, bool buckets) {
-    return engine_carve(nullptr, m, n, nullptr, buckets);
+size_t engine_bytes(int64_t m, int64_t n, bool buckets, bool exact) {
+    return engine_carve(nullptr, m, n, nullptr, buckets, exact);
 }
 
 // MSF_ALWAYS_COMPACT=1 compacts after every round (a tuning and diagnosis knob).
@@ -148,14 +159,27 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
     // whose positions are already in id order).
     // Large graphs on the caller's arrays without id locality: round 0 by
     // vertex buckets (with locality the edge-list round 0 mostly hits in L2).
-    bool bucketed = mode == kOrig && bucket_r0_enabled() && aligned16(view) &&
-                    bucket_usable(B.bk, view.len, nv);
-    if (bucketed && B.round0 == MSF_ROUND0_AUTO) {
+    // Both choices below read one sample of 4096 evenly spaced edges: do at
+    // least half of them join ids less than 2^14 apart (locality)?
+    const bool can_bucket = mode == kOrig && bucket_r0_enabled() && aligned16(view) &&
+                            bucket_usable(B.bk, view.len, nv);
+    bool local = false;
+    if (mode == kOrig && view.len >= kLocalitySample &&
+        ((can_bucket && B.round0 == MSF_ROUND0_AUTO) || B.dedup == MSF_DEDUP_AUTO)) {
         bucket_sample_locality(view.u, view.v, view.len, dc, s);
         HIP_TRY(hipGetLastError());
         if ((st = read_ctrl(dc, hc, s))) return st;
-        bucketed = hc->aux[0] * 2 < (uint64_t)kLocalitySample;
+        local = hc->aux[0] * 2 >= (uint64_t)kLocalitySample;
     }
+    bool bucketed = can_bucket && (B.round0 != MSF_ROUND0_AUTO || !local);
+    // Parallel-edge removal at every compaction, and compaction from round 0
+    // on (where round 0 runs on the edge list): contracted components of a
+    // graph with locality share many edges, so each round shrinks the next.
+    const int dedup = B.dedup == MSF_DEDUP_EXACT && B.dslots > 0 ? kDedupExact
+                      : B.dedup == MSF_DEDUP_LOCAL || B.dedup == MSF_DEDUP_EXACT ||
+                              (B.dedup == MSF_DEDUP_AUTO && local)
+                          ? kDedupLocal
+                          : kDedupNone;
     int h = -1;
     if (bucketed) {
         bucket_minedge(B.bk, view.u, view.v, view.w, view.len, nv, B.best[cur], dc, s);
@@ -303,7 +327,8 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             }
             break;
         }
-        const bool compact = !aligned || always_compact() ||
+        const bool compact = !aligned || always_compact() || (dedup != kDedupNone && !bucketed) ||
+                             (dedup != kDedupNone && mode != kOrig) ||
                              (mode != kOrig && (double)m_live < kCompactBelow * (double)view.len);
         View next = view;
         int next_mode = mode;
@@ -315,8 +340,16 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             cbsel ^= 1;
             const int64_t nte = (view.len + kRelabelTile - 1) / kRelabelTile;
             launch_scan_prep(B.status, nte, dc, 0, s);
+            if (dedup == kDedupExact) {   // the lightest key of every vertex pair
+                h = prof_begin(K_DEDUP, s);
+                launch_fill_u64(B.dpair, B.dslots, kKeyMax, s);
+                launch_fill_u64(B.dmin, B.dslots, kKeyMax, s);
+                launch_dedup_insert(mode, view, M, B.dpair, B.dmin, B.dslots, s);
+                prof_end(h, s, 16.0 * B.dslots + view_read_bytes(mode) * view.len + 8.0 * m_live);
+            }
             h = prof_begin(K_COMPACT, s);
-            launch_compact(mode, view, M, out, B.best[cur ^ 1], B.status, dc, s);
+            launch_compact(mode, view, M, out, B.best[cur ^ 1], B.status, dc, dedup, B.dpair,
+                           B.dmin, B.dslots, s);
             prof_end(h, s, view_read_bytes(mode) * view.len + 8.0 * m_live);
             next.u = out.u; next.v = out.v; next.w = out.w; next.id = out.id; next.p16 = nullptr;
             next_mode = kCompact;

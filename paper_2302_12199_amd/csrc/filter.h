@@ -11,7 +11,7 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
 
 // Stream base of the pivot sampler for split number `split` (depth-first
 // order): SplitMix64 output function applied as mix(mix(seed) ^ (tag + split)).
-uint64_t pivot_stream_base(uint64_t seed, uint32_t split);
+uint64_t pivot_stream_base(uint64_t seed, uint32_t split, uint32_t attempt);
 
 // filter.hip launchers
 void launch_sample_pivot(int in_mode, const View& g, uint64_t base, int sample, float q,

@@ -37,8 +37,11 @@ __host__ __device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-uint64_t pivot_stream_base(uint64_t seed, uint32_t split) {
-    return sm_mix(sm_mix(seed) ^ (kPivotTag + split));
+// Draw `attempt` of split `split`: the first uses mix(mix(seed) ^ (tag + split)),
+// a redraw a >= 1 (balanced-split retry) mix(that + a * gamma).
+uint64_t pivot_stream_base(uint64_t seed, uint32_t split, uint32_t attempt) {
+    const uint64_t b = sm_mix(sm_mix(seed) ^ (kPivotTag + split));
+    return attempt == 0 ? b : sm_mix(b + (uint64_t)attempt * kGamma);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -755,6 +758,8 @@ struct Ctx {
     uint64_t* flags;   // keep flags of the heavy edges being filtered
     uint64_t* bsum;    // chunk sums of the tile-count scans
     bool filtered;     // a filter step has run (ctrl->giant is meaningful)
+    int retries;       // balanced-split retry: redraws per split (0 = off)
+    int64_t defer;     // filtered sets below this size go back one level (0 = off)
 };
 
 View view_of(const EdgeSoA& e, int64_t len) {
@@ -789,9 +794,20 @@ int base_case(Ctx& C, int mode, const View& g) {
     return engine_solve(C.B, mode, g, C.n, C.mask, C.P, C.s, C.st, hot);
 }
 
+// The balanced-split retry's acceptance band (proof of the paper's Thm. 1:
+// both sides in [|E|/3, 2|E|/3] for the median): the light fraction within 1/6
+// of the target quantile.
+bool balanced_split(int64_t light, int64_t total, float q) {
+    const double qq = (double)q, l6 = 6.0 * (double)light;   // exact for the median
+    return (6.0 * qq - 1.0) * (double)total <= l6 && l6 <= (6.0 * qq + 1.0) * (double)total;
+}
+
 // `where`: 0 / 1 = the graph lives at [0, len) of buffer X / Y, 2 = the
-// caller's arrays.
-int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
+// caller's arrays.  *left = edges this call hands back to its caller (the
+// deferral of small filtered sets, Sec. VI-C); they sit at [0, *left) of
+// buffer X when where == 0, else of buffer Y.
+int rec_filter(Ctx& C, int mode, const View& g, int where, int depth, int64_t* left) {
+    *left = 0;
     if (g.len == 0) return MSF_OK;
     Ctrl* hc = host_ctrl();
     int st = read_ctrl(C.B.ctrl, hc, C.s);
@@ -812,18 +828,34 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
         if (C.q_net > 0.f) q = C.q_net;
         else net = mlp_device_params();
     }
-    int h = prof_begin(K_SAMPLE, C.s);
-    launch_sample_pivot(mode, g, pivot_stream_base(C.opt.seed, split), C.sample, q, net,
-                        (float)comps, depth, C.B.ctrl, C.s);
-    prof_end(h, C.s, 8.0 * C.sample);
     const int tgt = where == 0 ? 1 : 0;
     const EdgeSoA R = C.buf[tgt];
+    uint32_t attempt = 0;
+    int h;
+    for (;; ++attempt) {
+        h = prof_begin(K_SAMPLE, C.s);
+        launch_sample_pivot(mode, g, pivot_stream_base(C.opt.seed, split, attempt), C.sample, q,
+                            net, (float)comps, depth, C.B.ctrl, C.s);
+        prof_end(h, C.s, 8.0 * C.sample);
+        h = prof_begin(K_PARTITION, C.s);
+        launch_split_count(mode, g, &C.B.ctrl->pivot, C.B.status, C.bsum, C.B.ctrl, C.s);
+        prof_end(h, C.s, (mode == kOrig ? 4.0 : 8.0) * g.len);
+        if (attempt >= (uint32_t)C.retries) break;
+        // the retry: is the split balanced?  (one more host read per draw)
+        HIP_TRY(hipGetLastError());
+        if ((st = read_ctrl(C.B.ctrl, hc, C.s))) return st;
+        if (net) {                  // later draws reuse the network's quantile
+            q = hc->q_used;
+            net = nullptr;
+        }
+        if (balanced_split((int64_t)hc->light, g.len, hc->q_used)) break;
+        C.st->pivot_retries += 1;
+    }
     h = prof_begin(K_PARTITION, C.s);
-    launch_split_count(mode, g, &C.B.ctrl->pivot, C.B.status, C.bsum, C.B.ctrl, C.s);
     launch_split(mode, g, C.n, &C.B.ctrl->pivot, R, C.B.status, C.B.ctrl, C.s);
-    // count + split reads (4 + 12 B per edge on the caller's arrays, 8 + 16 B on
-    // a buffer) and writes: everything on a buffer, the light part only on top
-    prof_end(h, C.s, mode == kOrig ? 16.0 * g.len : 40.0 * g.len);
+    // split reads (12 B per edge on the caller's arrays, 16 B on a buffer) and
+    // writes: everything on a buffer, the light part only on top
+    prof_end(h, C.s, mode == kOrig ? 12.0 * g.len : 32.0 * g.len);
     HIP_TRY(hipGetLastError());
     if ((st = read_ctrl(C.B.ctrl, hc, C.s))) return st;
     if (hc->err & kErrRange) return MSF_ERANGE;
@@ -839,6 +871,7 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
         C.st->split_light[split] = (uint64_t)nl;
         C.st->split_q[split] = hc->q_used;
         C.st->split_kept[split] = 0;
+        C.st->split_attempts[split] = attempt + 1;
         memcpy(C.st->split_features[split], hc->feat, sizeof C.st->split_features[split]);
     }
     if (split == 0) {
@@ -862,29 +895,63 @@ int rec_filter(Ctx& C, int mode, const View& g, int where, int depth) {
         H.u += nl_al; H.v += nl_al; H.w += nl_al; H.id += nl_al;
         Hv = view_of(H, nh);
     }
-    if ((st = rec_filter(C, kCompact, view_of(R, nl), tgt, depth + 1))) return st;
+    // The light recursion; the edges it hands back (at [0, nd) of R, below
+    // this graph's heavy part) are filtered first, together with the heavy part.
+    int64_t nd = 0;
+    if ((st = rec_filter(C, kCompact, view_of(R, nl), tgt, depth + 1, &nd))) return st;
 
     // Filter: drop heavy edges inside a light component; the rest, relabelled
     // and in order, go to [0, kept) of the other buffer, which holds nothing
-    // live below this graph's length (this graph itself is no longer needed).
+    // live below this graph's length (this graph itself is no longer needed):
+    // the handed-back edges first (their keys lie below the heavy ones, so
+    // positions still order equal weights by id), then the heavy ones.
     if ((st = compress_p(C))) return st;
     h = prof_begin(K_PMAINT, C.s);
     launch_rep_codes(C.P, C.n, C.codes, C.B.ctrl, C.s);
     C.filtered = true;
     prof_end(h, C.s, 4.0 * C.n + C.n / 4.0);
     const int o = 1 - tgt;
+    int64_t kd = 0;
+    if (nd > 0) {
+        h = prof_begin(K_FILTER, C.s);
+        launch_filter(view_of(R, nd), false, pivot, C.P, C.codes, C.B.ctrl, C.flags, C.B.status,
+                      C.bsum, C.buf[o], &C.B.ctrl->m_next, C.s);
+        prof_end(h, C.s, 8.0 * nd);
+        HIP_TRY(hipGetLastError());
+        if ((st = read_ctrl(C.B.ctrl, hc, C.s))) return st;
+        kd = (int64_t)hc->m_next;
+        prof_add(K_FILTER, 24.0 * kd);
+    }
+    EdgeSoA out = C.buf[o];
+    out.u += kd; out.v += kd; out.w += kd; out.id += kd;
     h = prof_begin(K_FILTER, C.s);
     launch_filter(Hv, heavy_in_place, pivot, C.P, C.codes, C.B.ctrl, C.flags, C.B.status,
-                  C.bsum, C.buf[o], &C.B.ctrl->m_next, C.s);
+                  C.bsum, out, &C.B.ctrl->m_next, C.s);
     prof_end(h, C.s, heavy_in_place ? 12.0 * g.len : 8.0 * nh);
     HIP_TRY(hipGetLastError());
     if ((st = read_ctrl(C.B.ctrl, hc, C.s))) return st;
-    const int64_t kept = (int64_t)hc->m_next;
-    prof_add(K_FILTER, 24.0 * kept);
-    C.st->filtered_in += (uint64_t)nh;
+    int64_t kept = kd + (int64_t)hc->m_next;
+    prof_add(K_FILTER, 24.0 * (kept - kd));
+    C.st->filtered_in += (uint64_t)(nh + nd);
     C.st->filtered_out += (uint64_t)kept;
-    if (split < MSF_MAX_TRACE) C.st->split_kept[split] = (uint64_t)kept;
-    return rec_filter(C, kCompact, view_of(C.buf[o], kept), o, depth + 1);
+    if (split < MSF_MAX_TRACE) {
+        C.st->split_kept[split] = (uint64_t)kept;
+        C.st->split_deferred_in[split] = (uint64_t)nd;
+    }
+    // The filtered edges sit at [0, kept) of buffer o; a recursion on them
+    // (where = o) hands its leftovers back at [0, left) of the same buffer.
+    while (kept > 0) {
+        if (depth > 0 && kept < C.defer) {      // too few: merge them one level up
+            C.st->deferrals += 1;
+            *left = kept;
+            return MSF_OK;
+        }
+        int64_t back = 0;
+        if ((st = rec_filter(C, kCompact, view_of(C.buf[o], kept), o, depth + 1, &back)))
+            return st;
+        kept = back;
+    }
+    return MSF_OK;
 }
 
 }  // namespace
@@ -896,7 +963,8 @@ size_t flags_bytes(int64_t m) {
 }
 
 size_t filter_bytes(int64_t m, int64_t n, const msf_options& opt) {
-    return engine_bytes(m, n, opt.round0 != MSF_ROUND0_EDGES) + align_up((size_t)(n > 0 ? n : 1) * 4) + 2 * buffer_bytes(m) +
+    return engine_bytes(m, n, opt.round0 != MSF_ROUND0_EDGES,
+                        opt.dedup_policy == MSF_DEDUP_EXACT) + align_up((size_t)(n > 0 ? n : 1) * 4) + 2 * buffer_bytes(m) +
            codes_bytes(n) + flags_bytes(m) + align_up(kScanTop * 8);
 }
 
@@ -904,8 +972,10 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
                  uint8_t* mask, char* ws, hipStream_t s, const msf_options& opt,
                  msf_stats* stats) {
     Ctx C;
-    size_t off = engine_carve(ws, m, n, &C.B, opt.round0 != MSF_ROUND0_EDGES);
+    size_t off = engine_carve(ws, m, n, &C.B, opt.round0 != MSF_ROUND0_EDGES,
+                              opt.dedup_policy == MSF_DEDUP_EXACT);
     C.B.round0 = opt.round0;
+    C.B.dedup = opt.dedup_policy;
     C.P = (int32_t*)(ws + off);
     off += align_up((size_t)(n > 0 ? n : 1) * 4);
     C.buf[0] = carve_buffer(ws + off, m);
@@ -927,6 +997,8 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
     C.sample = opt.sample_size > 0 ? opt.sample_size : 4096;
     C.min_split = opt.min_split_edges > 0 ? opt.min_split_edges : (1 << 20);
     C.sparse_deg = opt.sparse_degree > 0 ? opt.sparse_degree : 4;
+    C.retries = opt.split_retries;
+    C.defer = opt.defer_edges;
 
     launch_zero_bytes((uint8_t*)C.B.ctrl, sizeof(Ctrl), s);
     int h = prof_begin(K_FILL, s);
@@ -934,8 +1006,13 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
     launch_iota(C.P, n, s);
     prof_end(h, s, (double)m + 4.0 * n);
     View g{u, v, nullptr, w, nullptr, m};
-    int st = rec_filter(C, kOrig, g, 2, 0);
+    int64_t left = 0;
+    int st = rec_filter(C, kOrig, g, 2, 0, &left);
     if (st) return st;
+    if (left != 0) {
+        set_err_text("the top level of Filter-Boruvka handed edges back");
+        return MSF_EINTERNAL;
+    }
     Ctrl* hc = host_ctrl();
     if ((st = read_ctrl(C.B.ctrl, hc, s))) return st;
     stats->total_weight = hc->total;

@@ -25,7 +25,7 @@ const char* last_err();
 enum KernelId { K_MINEDGE_R0, K_HOOK, K_JUMP, K_SCAN_ROOTS, K_LABEL, K_PASS, K_COMPACT,
                 K_COMPOSE, K_FILL, K_PREP, K_SAMPLE, K_PARTITION, K_FILTER, K_PMAINT,
                 K_MLP, K_BATCH, K_TAIL, K_PASS_R0, K_BK_INDEX, K_BK_SCATTER, K_BK_MIN,
-                K_BK_LABEL, K_BK_PASS, K_COUNT };
+                K_BK_LABEL, K_BK_PASS, K_DEDUP, K_COUNT };
 
 bool prof_on();
 int prof_begin(int kid, hipStream_t s);            // -1 when profiling is off

@@ -35,7 +35,15 @@ void launch_tail(const uint64_t* pairs, int64_t nn, uint32_t* const list_xy[2],
 void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_t* label,
                        int64_t nr, const int32_t* orig_cur, int32_t* orig_next, int32_t* rep,
                        hipStream_t s);
+// dedup (DedupKind): kDedupLocal keeps only the lightest edge per vertex pair
+// within each tile; kDedupExact keeps the edge whose key the global table
+// (dpair, dmin; dslots entries, filled by launch_dedup_insert) holds for its pair.
 void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
-                    uint64_t* best_next, uint64_t* status, Ctrl* ctrl, hipStream_t s);
+                    uint64_t* best_next, uint64_t* status, Ctrl* ctrl, int dedup,
+                    const uint64_t* dpair, const uint64_t* dmin, int64_t dslots, hipStream_t s);
+// Global pair table of exact parallel-edge removal: every live relabelled edge
+// enters its vertex pair and min-reduces its key.  dpair/dmin must hold kKeyMax.
+void launch_dedup_insert(int in_mode, const View& g, const int32_t* M, uint64_t* dpair,
+                         uint64_t* dmin, int64_t dslots, hipStream_t s);
 
 }  // namespace msf

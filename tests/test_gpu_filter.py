@@ -113,6 +113,38 @@ def test_filter_features_match_oracle(kind, sample):
     assert len(st["splits"]) >= 2 and any(f["features"][13] > 0 for f in st["splits"])
 
 
+@pytest.mark.parametrize("graph", ["gnm", "rmat"])
+@pytest.mark.parametrize("retries,defer,sample,q", [(6, 0, 1, 0.5), (6, 0, 1, 0.2),
+                                                    (0, 3000, 256, 0.3), (4, 3000, 16, 0.5),
+                                                    (0, 10**6, 512, 0.5)])
+def test_filter_variants_match_the_oracle(graph, retries, defer, sample, q):
+    """The balanced-split retry and the deferral of small filtered sets: the
+    MSF, every split (including its draws and handed-back edges), the
+    features, and the counts of redraws, deferrals and base cases."""
+    banner(f"filter variants {graph} retries={retries} defer={defer} sample={sample} q={q}")
+    if graph == "gnm":
+        n = 3000
+        u, v, w = graphgen.gnm(n, 90000, 1, 2**31 - 1, seed=12)
+    else:
+        n = 1 << 13
+        u, v, w = graphgen.rmat(13, 150000, wlo=1, whi=2**31 - 1, seed=13)
+    mask, total, st = gpu_msf(u, v, w, n, algo="filter", pivot="quantile", quantile=q, seed=2,
+                              sample_size=sample, min_split_edges=1000, split_retries=retries,
+                              defer_edges=defer)
+    km, kt, kc = oracle.kruskal(u, v, w, n)
+    assert (mask == km).all() and total == kt and st["msf_edges"] == kc
+    info = {}
+    _, _, trace = oracle.filter_boruvka(u, v, w, n, seed=2, sample=sample, q=q, min_split=1000,
+                                        retries=retries, defer=defer, info=info)
+    keys = ("edges", "pivot", "light", "kept", "attempts", "deferred_in")
+    assert [{k: s_[k] for k in keys} for s_ in st["splits"]] == \
+        [{k: t[k] for k in keys} for t in trace[:64]]
+    for s_, t in zip(st["splits"], trace):
+        assert_features_close(s_["features"], t["features"], sample)
+    assert st["pivot_retries"] == info["retries"] and st["deferrals"] == info["deferrals"]
+    assert st["base_cases"] == info["base_cases"]
+
+
 def test_filter_ties_and_selfloops():
     banner("filter ties")
     rng = np.random.default_rng(5)

@@ -186,3 +186,66 @@ def test_network_forward_hand_example():
     assert mlp_ref.forward(p, x, bf=True)[0].tolist() == [-0.5, 17.5]
     # the magnitude pass: |2 x0| + |x1| + 1 for both samples, times 3, plus 0.5
     assert mlp_ref.magnitude(p, x).tolist() == [3 * (2 + 4 + 1) + 0.5, 3 * (6 + 1 + 1) + 0.5]
+
+
+def test_stream_of_a_redraw():
+    from oracle.filter_ref import stream_base
+    first = _mix(_mix(5) ^ (0x50495654 + 2))
+    assert stream_base(5, 2) == first == stream_base(5, 2, 0)
+    assert stream_base(5, 2, 3) == _mix((first + 3 * GAMMA) & MASK64)
+    assert len({stream_base(5, 2, a) for a in range(6)}) == 6
+
+
+def test_balanced_band_is_the_papers_third_for_the_median():
+    from oracle.filter_ref import balanced
+    assert balanced(100, 300, 0.5) and balanced(200, 300, 0.5)
+    assert not balanced(99, 300, 0.5) and not balanced(201, 300, 0.5)
+    assert balanced(0, 100, 0.1) and not balanced(30, 100, 0.1)
+
+
+@pytest.mark.parametrize("q", [0.5, 0.2])
+def test_balanced_retry(q):
+    """One-edge samples often split badly; with redraws every split that did
+    not use up its draws lies in the band, and the MSF is unchanged."""
+    from oracle.filter_ref import balanced
+    u, v, w = graphgen.gnm(3000, 90000, 1, 2**31 - 1, seed=12)
+    km, kt, _ = oracle.kruskal(u, v, w, 3000)
+    _, _, plain = filter_boruvka(u, v, w, 3000, seed=4, sample=1, q=q, min_split=1500)
+    info = {}
+    mask, total, tr = filter_boruvka(u, v, w, 3000, seed=4, sample=1, q=q, min_split=1500,
+                                     retries=6, info=info)
+    assert (mask == km).all() and total == kt
+    assert info["retries"] > 0 and sum(t["attempts"] - 1 for t in tr) == info["retries"]
+    for t in tr:
+        assert 1 <= t["attempts"] <= 7
+        if t["attempts"] < 7:
+            assert balanced(t["light"], t["edges"], q)
+    # without redraws the one-edge pivots leave unbalanced splits
+    assert any(not balanced(t["light"], t["edges"], q) for t in plain)
+    assert all(t["attempts"] == 1 for t in plain)
+
+
+@pytest.mark.parametrize("defer", [0, 200, 3000, 10**6])
+def test_deferral_keeps_the_msf(defer):
+    """Handing small filtered sets back a level changes the work, never the
+    MSF.  On this graph the second split's 2719 filtered edges go back to the
+    top level below 3000, which then filters them with its heavy edges."""
+    u, v, w = graphgen.rmat(13, 150000, wlo=1, whi=2**31 - 1, seed=13)
+    n = 1 << 13
+    km, kt, _ = oracle.kruskal(u, v, w, n)
+    base_info, info = {}, {}
+    _, _, plain = filter_boruvka(u, v, w, n, seed=2, sample=256, q=0.3, min_split=1000,
+                                 info=base_info)
+    mask, total, tr = filter_boruvka(u, v, w, n, seed=2, sample=256, q=0.3, min_split=1000,
+                                     defer=defer, info=info)
+    assert (mask == km).all() and total == kt
+    if defer < plain[1]["kept"] + 1:
+        assert info["deferrals"] == 0 and len(tr) == len(plain)
+        for a, b in zip(tr, plain):
+            assert {k: x for k, x in a.items() if k != "features"} == \
+                {k: x for k, x in b.items() if k != "features"}
+    else:
+        assert info["deferrals"] > 0
+        assert tr[0]["deferred_in"] == plain[1]["kept"]
+    # a split's handed-back edges came from a set below the threshold
+    assert all(t["deferred_in"] < max(defer, 1) for t in tr)
