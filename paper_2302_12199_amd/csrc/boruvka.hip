@@ -17,6 +17,7 @@
 // live edges stably with a decoupled-lookback scan.
 #include <stdlib.h>
 
+#include "launch.h"
 #include "prim.h"
 
 namespace msf {
@@ -520,23 +521,30 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
 // heaviest, so it is in no MSF (cycle property).  The table has twice as many
 // slots as a tile has edges, so every probe sequence ends.
 constexpr int kDedupSlots = 2 * kRelabelTile;
+constexpr uint32_t kCompactGrid = 4096;   // workgroups of the compaction passes (tiles grid-stride)
 
 __device__ __forceinline__ uint32_t pair_slot(uint64_t pair) {
     return (uint32_t)((pair * 0x9E3779B97F4A7C15ULL) >> 40) & (kDedupSlots - 1);
 }
 
 // Inserts `pair` (never kKeyMax) and min-reduces `key` into its entry; returns the slot.
+// Plain reads first: a slot, once taken, keeps its pair, and an entry's minimum
+// only falls, so a read showing the pair (or a minimum at most `key`) makes the
+// atomic unnecessary; most edges of a tile meet a pair already entered.
 __device__ __forceinline__ uint32_t dedup_insert(unsigned long long* s_pair,
                                                  unsigned long long* s_min, uint64_t pair,
                                                  uint64_t key) {
     uint32_t slot = pair_slot(pair);
     for (int probe = 0; probe < kDedupSlots; ++probe) {
-        const unsigned long long old = atomicCAS(&s_pair[slot], (unsigned long long)kKeyMax,
-                                                 (unsigned long long)pair);
-        if (old == kKeyMax || old == pair) break;
+        unsigned long long cur = __hip_atomic_load(&s_pair[slot], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == kKeyMax)
+            cur = atomicCAS(&s_pair[slot], (unsigned long long)kKeyMax, (unsigned long long)pair);
+        if (cur == kKeyMax || cur == pair) break;
         slot = (slot + 1) & (kDedupSlots - 1);
     }
-    atomicMin(&s_min[slot], (unsigned long long)key);
+    if (key < __hip_atomic_load(&s_min[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+        atomicMin(&s_min[slot], (unsigned long long)key);
     return slot;
 }
 
@@ -587,128 +595,184 @@ __device__ __forceinline__ uint64_t gpair_min(const uint64_t* dpair, const uint6
     return kKeyMax;
 }
 
-// Relabel through M, drop self-loops and compact the survivors stably into
-// `out` (position order stays edge-id order).  FUSED: each survivor takes
-// part in the next round's minedge with key (w << 32 | new position).  DEDUP
-// (DedupKind): the survivors are also reduced to the lightest edge per vertex
-// pair, within the tile (kDedupLocal, the prefilter above) or over the whole
-// view (kDedupExact, the global table).  All inputs of a tile are read before
-// its lookback completes and outputs land at or before their inputs, so `out`
-// may alias the view (in-place compaction).
-template <int IN, bool FUSED, int DEDUP>
-__global__ __launch_bounds__(kBlock) void k_compact(View g, const int32_t* __restrict__ M,
-                                                    EdgeSoA out, uint64_t* __restrict__ best_next,
-                                                    uint64_t* status, Ctrl* ctrl,
-                                                    uint32_t ntiles, const uint64_t* dpair,
-                                                    const uint64_t* dmin, int64_t dslots) {
+// Compaction of the live edges after relabelling, in three steps with no
+// waiting between tiles (reduce, scan, scatter):
+//   k_compact_flags    relabel through M, drop self-loops and (DEDUP) every
+//                      edge with a lighter parallel edge in its tile
+//                      (kDedupLocal, the prefilter above) or in the whole view
+//                      (kDedupExact, the global table); one keep bit per
+//                      position and the kept count of every 2048-edge tile;
+//   launch_scan_tiles  exclusive offsets of the tiles, the total to m_next;
+//   k_compact_scatter  the kept edges, relabelled, stably at their offsets
+//                      (position order stays edge-id order) and, FUSED, the
+//                      next round's lightest-edge search on them with key
+//                      (w << 32 | new position).
+// Flag word i covers positions [64 i, 64 i + 64); tile t owns words
+// [32 t, 32 t + 32), wave j of it words 32 t + 8 j + k.  `out` must not alias
+// the view.
+constexpr int kTileWords = kRelabelTile / kWave;
+
+template <int IN, int DEDUP>
+__global__ __launch_bounds__(kBlock) void k_compact_flags(View g, const int32_t* __restrict__ M,
+                                                          uint64_t* __restrict__ flags,
+                                                          uint64_t* __restrict__ cnt,
+                                                          uint32_t ntiles, const uint64_t* dpair,
+                                                          const uint64_t* dmin, int64_t dslots) {
     constexpr int kIt = kRelabelItems;
     constexpr int kTab = DEDUP == kDedupLocal ? kDedupSlots : 1;
-    __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wave[kBlock / kWave];
-    __shared__ uint64_t s_prefix;
     __shared__ unsigned long long s_pair[kTab];
     __shared__ unsigned long long s_min[kTab];
-    if constexpr (DEDUP == kDedupLocal) {
-        for (int i = threadIdx.x; i < kTab; i += kBlock) {
-            s_pair[i] = kKeyMax;
-            s_min[i] = kKeyMax;
-        }
-    }
-    const uint32_t tile = take_tile(ctrl, &s_tile);   // its barrier also orders the clearing
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t e0 = (int64_t)tile * (kBlock * kIt) + (int64_t)wave * (kWave * kIt) + lane;
     const int64_t mr = g.len;
-    int32_t a[kIt], b[kIt];
-    uint32_t wt[kIt], id[kIt];
-    uint64_t mk[kIt];
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        const int64_t e = e0 + k * kWave;
-        a[k] = b[k] = 0;
-        wt[k] = id[k] = 0;
-        if (e < mr) {
-            load_ends<IN>(g, e, a[k], b[k]);
-            wt[k] = g.w[e];
-            id[k] = edge_id<IN>(g, e);
-        }
-    }
-    bool keep[kIt];
-#pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        const int64_t e = e0 + k * kWave;
-        keep[k] = false;
-        if (e < mr && a[k] != b[k]) {
-            a[k] = M[a[k]];
-            b[k] = M[b[k]];
-            keep[k] = a[k] != b[k];
-        }
-    }
-    if constexpr (DEDUP == kDedupExact) {
-#pragma unroll
-        for (int k = 0; k < kIt; ++k) {
-            if (keep[k]) {
-                const uint32_t lo = (uint32_t)(a[k] < b[k] ? a[k] : b[k]);
-                const uint32_t hi = (uint32_t)(a[k] < b[k] ? b[k] : a[k]);
-                const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
-                keep[k] = gpair_min(dpair, dmin, dslots, ((uint64_t)lo << 32) | hi) == key;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t e0 = (int64_t)tile * kRelabelTile + (int64_t)wave * (kWave * kIt) + lane;
+        if constexpr (DEDUP == kDedupLocal) {
+            for (int i = threadIdx.x; i < kTab; i += kBlock) {
+                s_pair[i] = kKeyMax;
+                s_min[i] = kKeyMax;
             }
         }
-    }
-    if constexpr (DEDUP == kDedupLocal) {
-        uint32_t slot[kIt];
+        int32_t a[kIt], b[kIt];
+        uint32_t wt[kIt];
 #pragma unroll
         for (int k = 0; k < kIt; ++k) {
-            slot[k] = 0;
-            if (keep[k]) {
-                const uint32_t lo = (uint32_t)(a[k] < b[k] ? a[k] : b[k]);
-                const uint32_t hi = (uint32_t)(a[k] < b[k] ? b[k] : a[k]);
-                const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
-                slot[k] = dedup_insert(s_pair, s_min, ((uint64_t)lo << 32) | hi, key);
+            const int64_t e = e0 + k * kWave;
+            a[k] = b[k] = 0;
+            wt[k] = 0;
+            if (e < mr) {
+                load_ends<IN>(g, e, a[k], b[k]);
+                if constexpr (DEDUP != kDedupNone) wt[k] = g.w[e];
             }
         }
+        bool keep[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            keep[k] = false;
+            if (a[k] != b[k]) {          // also false past the end (both 0)
+                a[k] = M[a[k]];
+                b[k] = M[b[k]];
+                keep[k] = a[k] != b[k];
+            }
+        }
+        if constexpr (DEDUP == kDedupExact) {
+#pragma unroll
+            for (int k = 0; k < kIt; ++k) {
+                if (keep[k]) {
+                    const uint32_t lo = (uint32_t)(a[k] < b[k] ? a[k] : b[k]);
+                    const uint32_t hi = (uint32_t)(a[k] < b[k] ? b[k] : a[k]);
+                    const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
+                    keep[k] = gpair_min(dpair, dmin, dslots, ((uint64_t)lo << 32) | hi) == key;
+                }
+            }
+        }
+        if constexpr (DEDUP == kDedupLocal) {
+            __syncthreads();             // the table is clear
+            uint32_t slot[kIt];
+#pragma unroll
+            for (int k = 0; k < kIt; ++k) {
+                slot[k] = 0;
+                if (keep[k]) {
+                    const uint32_t lo = (uint32_t)(a[k] < b[k] ? a[k] : b[k]);
+                    const uint32_t hi = (uint32_t)(a[k] < b[k] ? b[k] : a[k]);
+                    const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
+                    slot[k] = dedup_insert(s_pair, s_min, ((uint64_t)lo << 32) | hi, key);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kIt; ++k) {
+                const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
+                if (keep[k] && s_min[slot[k]] != key) keep[k] = false;
+            }
+        }
+        uint32_t c = 0;
+        const int64_t w0 = (int64_t)tile * kTileWords + wave * kIt;
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            const uint64_t mk = __ballot(keep[k]);
+            if (lane == 0) flags[w0 + k] = mk;
+            c += __popcll(mk);
+        }
+        if (lane == 0) s_wave[wave] = c;
         __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t sum = 0;
+            for (int i = 0; i < kBlock / kWave; ++i) sum += s_wave[i];
+            cnt[tile] = sum;
+        }
+        __syncthreads();                 // s_wave and the table are reused by the next tile
+    }
+}
+
+template <int IN, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_compact_scatter(View g, const int32_t* __restrict__ M,
+                                                            const uint64_t* __restrict__ flags,
+                                                            const uint64_t* __restrict__ off,
+                                                            EdgeSoA out,
+                                                            uint64_t* __restrict__ best_next,
+                                                            uint32_t ntiles) {
+    constexpr int kIt = kRelabelItems;
+    __shared__ uint32_t s_wave[kBlock / kWave];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t w0 = (int64_t)tile * kTileWords + wave * kIt;
+        const int64_t e0 = (int64_t)tile * kRelabelTile + (int64_t)wave * (kWave * kIt) + lane;
+        uint64_t mk[kIt];
+        uint32_t c = 0;
 #pragma unroll
         for (int k = 0; k < kIt; ++k) {
-            const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
-            if (keep[k] && s_min[slot[k]] != key) keep[k] = false;
+            mk[k] = flags[w0 + k];
+            c += __popcll(mk[k]);
         }
-    }
+        if (lane == 0) s_wave[wave] = c;
+        __syncthreads();
+        uint32_t woff = 0;
 #pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        mk[k] = __ballot(keep[k]);
-        cnt += __popcll(mk[k]);
-    }
-    // Every load of this tile has returned before the tile's aggregate is
-    // published (in-place use: later tiles may overwrite these positions).
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (lane == 0) s_wave[wave] = cnt;
-    __syncthreads();
-    uint32_t agg = 0, woff = 0;
+        for (int i = 0; i < kBlock / kWave; ++i)
+            if (i < wave) woff += s_wave[i];
+        // all loads, then the label gathers, then the stores: the chains of
+        // the scattered kept edges overlap
+        int32_t a[kIt], b[kIt];
+        uint32_t wt[kIt], id[kIt];
 #pragma unroll
-    for (int i = 0; i < kBlock / kWave; ++i) {
-        if (i < wave) woff += s_wave[i];
-        agg += s_wave[i];
-    }
-    const uint64_t prefix = tile_prefix(status, tile, agg, ctrl, &s_prefix);
-    uint64_t off = prefix + woff;
-#pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-        if ((mk[k] >> lane) & 1) {
-            const uint64_t o = off + lanes_below(mk[k]);
-            out.u[o] = a[k];
-            out.v[o] = b[k];
-            out.w[o] = wt[k];
-            out.id[o] = id[k];
-            if constexpr (FUSED) {
-                const uint64_t key = ((uint64_t)wt[k] << 32) | o;
-                atomic_min_key(&best_next[a[k]], key);
-                atomic_min_key(&best_next[b[k]], key);
+        for (int k = 0; k < kIt; ++k) {
+            a[k] = b[k] = 0;
+            wt[k] = id[k] = 0;
+            if ((mk[k] >> lane) & 1) {
+                const int64_t e = e0 + k * kWave;
+                load_ends<IN>(g, e, a[k], b[k]);
+                wt[k] = g.w[e];
+                id[k] = edge_id<IN>(g, e);
             }
         }
-        off += __popcll(mk[k]);
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            if ((mk[k] >> lane) & 1) {
+                a[k] = M[a[k]];
+                b[k] = M[b[k]];
+            }
+        }
+        uint64_t o = off[tile] + woff;
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            const bool kept = (mk[k] >> lane) & 1;
+            const uint64_t d = o + lanes_below(mk[k]);
+            if (kept) {
+                out.u[d] = a[k];
+                out.v[d] = b[k];
+                out.w[d] = wt[k];
+                out.id[d] = id[k];
+            }
+            if constexpr (FUSED) {
+                const uint64_t key = ((uint64_t)wt[k] << 32) | d;
+                wave_min_update(best_next, a[k], key, kept);
+                wave_min_update(best_next, b[k], key, kept);
+            }
+            o += __popcll(mk[k]);
+        }
+        __syncthreads();                 // s_wave is reused by the next tile
     }
-    if (tile == ntiles - 1 && threadIdx.x == 0) ctrl->m_next = prefix + agg;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -965,32 +1029,38 @@ bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t 
 }
 
 template <int DEDUP>
-static void launch_compact_t(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
-                             uint64_t* best_next, uint64_t* status, Ctrl* ctrl, uint32_t nt,
-                             const uint64_t* dp, const uint64_t* dm, int64_t ds, hipStream_t s) {
-    const dim3 gr(nt), bl(kBlock);
+static void launch_compact_flags(int in_mode, const View& g, const int32_t* M, uint64_t* flags,
+                                 uint64_t* cnt, uint32_t nt, const uint64_t* dp,
+                                 const uint64_t* dm, int64_t ds, hipStream_t s) {
+    const dim3 gr(nt < kCompactGrid ? nt : kCompactGrid), bl(kBlock);
     switch (in_mode) {
-        case kOrig: hipLaunchKernelGGL((k_compact<kOrig, true, DEDUP>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt, dp, dm, ds); break;
-        case kFull32: hipLaunchKernelGGL((k_compact<kFull32, true, DEDUP>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt, dp, dm, ds); break;
-        case kFull16: hipLaunchKernelGGL((k_compact<kFull16, true, DEDUP>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt, dp, dm, ds); break;
-        default: hipLaunchKernelGGL((k_compact<kCompact, true, DEDUP>), gr, bl, 0, s, g, M, out, best_next, status, ctrl, nt, dp, dm, ds); break;
+        case kOrig: hipLaunchKernelGGL((k_compact_flags<kOrig, DEDUP>), gr, bl, 0, s, g, M, flags, cnt, nt, dp, dm, ds); break;
+        case kFull32: hipLaunchKernelGGL((k_compact_flags<kFull32, DEDUP>), gr, bl, 0, s, g, M, flags, cnt, nt, dp, dm, ds); break;
+        case kFull16: hipLaunchKernelGGL((k_compact_flags<kFull16, DEDUP>), gr, bl, 0, s, g, M, flags, cnt, nt, dp, dm, ds); break;
+        default: hipLaunchKernelGGL((k_compact_flags<kCompact, DEDUP>), gr, bl, 0, s, g, M, flags, cnt, nt, dp, dm, ds); break;
     }
 }
 
 void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
-                    uint64_t* best_next, uint64_t* status, Ctrl* ctrl, int dedup,
-                    const uint64_t* dpair, const uint64_t* dmin, int64_t dslots, hipStream_t s) {
+                    uint64_t* best_next, uint64_t* flags, uint64_t* cnt, uint64_t* bsum,
+                    Ctrl* ctrl, int dedup, const uint64_t* dpair, const uint64_t* dmin,
+                    int64_t dslots, hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     if (dedup == kDedupExact && dslots > 0)
-        launch_compact_t<kDedupExact>(in_mode, g, M, out, best_next, status, ctrl, nt, dpair,
-                                      dmin, dslots, s);
+        launch_compact_flags<kDedupExact>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
     else if (dedup != kDedupNone)
-        launch_compact_t<kDedupLocal>(in_mode, g, M, out, best_next, status, ctrl, nt, dpair,
-                                      dmin, dslots, s);
+        launch_compact_flags<kDedupLocal>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
     else
-        launch_compact_t<kDedupNone>(in_mode, g, M, out, best_next, status, ctrl, nt, dpair,
-                                     dmin, dslots, s);
+        launch_compact_flags<kDedupNone>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
+    launch_scan_tiles(cnt, nt, bsum, &ctrl->m_next, s);
+    const dim3 gr(nt < kCompactGrid ? nt : kCompactGrid), bl(kBlock);
+    switch (in_mode) {
+        case kOrig: hipLaunchKernelGGL((k_compact_scatter<kOrig, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt); break;
+        case kFull32: hipLaunchKernelGGL((k_compact_scatter<kFull32, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt); break;
+        case kFull16: hipLaunchKernelGGL((k_compact_scatter<kFull16, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt); break;
+        default: hipLaunchKernelGGL((k_compact_scatter<kCompact, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt); break;
+    }
 }
 
 void launch_dedup_insert(int in_mode, const View& g, const int32_t* M, uint64_t* dpair,

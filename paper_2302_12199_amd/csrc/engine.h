@@ -9,7 +9,9 @@ namespace msf {
 // Device buffers of the round loop, carved out of the caller's workspace.
 struct EngineBuffers {
     Ctrl* ctrl;
-    uint64_t* status;     // lookback tile status words
+    uint64_t* status;     // lookback tile status words; tile counts of a compaction
+    uint64_t* cflags;     // compaction keep bits, one per position
+    uint64_t* cbsum;      // compaction scan chunk sums
     uint64_t* best[2];    // lightest-edge keys, this round / next round
     int32_t* parent;
     int32_t* lab[2];      // per-round label arrays (alternating)

@@ -48,6 +48,8 @@ size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool bucke
     EngineBuffers b;
     b.ctrl = (Ctrl*)take(sizeof(Ctrl));
     b.status = (uint64_t*)take(tiles * 8);
+    b.cflags = (uint64_t*)take(((mm + kRelabelTile - 1) / kRelabelTile) * (kRelabelTile / 8));
+    b.cbsum = (uint64_t*)take(1024 * 8);
     for (int i = 0; i < 2; ++i) b.best[i] = (uint64_t*)take(nn * 8);
     b.parent = (int32_t*)take(nn * 4);
     for (int i = 0; i < 2; ++i) b.lab[i] = (int32_t*)take(nn * 4);
@@ -338,8 +340,6 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         if (compact) {
             EdgeSoA out = B.cbuf[cbsel];
             cbsel ^= 1;
-            const int64_t nte = (view.len + kRelabelTile - 1) / kRelabelTile;
-            launch_scan_prep(B.status, nte, dc, 0, s);
             if (dedup == kDedupExact) {   // the lightest key of every vertex pair
                 h = prof_begin(K_DEDUP, s);
                 launch_fill_u64(B.dpair, B.dslots, kKeyMax, s);
@@ -348,8 +348,8 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
                 prof_end(h, s, 16.0 * B.dslots + view_read_bytes(mode) * view.len + 8.0 * m_live);
             }
             h = prof_begin(K_COMPACT, s);
-            launch_compact(mode, view, M, out, B.best[cur ^ 1], B.status, dc, dedup, B.dpair,
-                           B.dmin, B.dslots, s);
+            launch_compact(mode, view, M, out, B.best[cur ^ 1], B.cflags, B.status, B.cbsum, dc,
+                           dedup, B.dpair, B.dmin, B.dslots, s);
             prof_end(h, s, view_read_bytes(mode) * view.len + 8.0 * m_live);
             next.u = out.u; next.v = out.v; next.w = out.w; next.id = out.id; next.p16 = nullptr;
             next_mode = kCompact;

@@ -38,9 +38,16 @@ void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_
 // dedup (DedupKind): kDedupLocal keeps only the lightest edge per vertex pair
 // within each tile; kDedupExact keeps the edge whose key the global table
 // (dpair, dmin; dslots entries, filled by launch_dedup_insert) holds for its pair.
+// flags: one bit per position (tiles of 2048 positions); cnt: a word per tile;
+// bsum: kScanTop words.  ctrl->m_next receives the number of kept edges.
 void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
-                    uint64_t* best_next, uint64_t* status, Ctrl* ctrl, int dedup,
-                    const uint64_t* dpair, const uint64_t* dmin, int64_t dslots, hipStream_t s);
+                    uint64_t* best_next, uint64_t* flags, uint64_t* cnt, uint64_t* bsum,
+                    Ctrl* ctrl, int dedup, const uint64_t* dpair, const uint64_t* dmin,
+                    int64_t dslots, hipStream_t s);
+// filter.hip: exclusive scan of per-tile counts in place (nt <= 2^21 tiles;
+// bsum holds kScanTop chunk sums), the total to *total.
+void launch_scan_tiles(uint64_t* cnt, uint32_t nt, uint64_t* bsum, uint64_t* total,
+                       hipStream_t s);
 // Global pair table of exact parallel-edge removal: every live relabelled edge
 // enters its vertex pair and min-reduces its key.  dpair/dmin must hold kKeyMax.
 void launch_dedup_insert(int in_mode, const View& g, const int32_t* M, uint64_t* dpair,
