@@ -230,7 +230,17 @@ typedef struct msf_batch_options {
     int32_t workgroups;      /* persistent workgroups; 0 = as many as can be resident */
     int32_t coop_edges;      /* graphs with at least this many edges are solved
                                 cooperatively per XCD; 0 = 2^20, -1 = never */
-    int32_t reserved[4];     /* must be zero */
+    int32_t wave_edges;      /* a tier solving graphs with at most this many edges by
+                                one wave each; SWITCHED OFF: only 0 and -1 (never) are
+                                accepted, any positive value gives MSF_EINVAL */
+    int32_t hot_min;         /* block tier of the lightest-edge search: a label on at
+                                least this many of 64 sampled edge ends of a chunk
+                                keeps its minimum in LDS for the chunk; 0 = 8,
+                                -1 = off (1..64) */
+    int32_t wave_min;        /* wave tier: lanes of a wave sharing a label are
+                                min-reduced before updating when at least this many
+                                share it; 0 = 2, -1 = off (2..64) */
+    int32_t reserved[1];     /* must be zero */
 } msf_batch_options;
 
 size_t msf_batched_workspace_bytes(int64_t G, int64_t max_n, const msf_batch_options* opt);
@@ -253,13 +263,14 @@ int msf_batched_graph_launch(msf_batch_graph* graph, void* stream);
 int msf_batched_graph_destroy(msf_batch_graph* graph);
 
 /*
- * Autotuner for the batched solver: runs the batch once per candidate
- * (block in {512, 1024} x lds_vertices in {1024, 2048, 4096} x coop_edges in
- * {2^19, 2^20, never}) on
- * `stream`, times each with HIP events and writes the fastest to *best_out
- * (HOST); *best_ms_out (HOST, nullable) gets its time.  Blocking.  Same array
- * arguments as msf_compute_batched; the workspace must fit every candidate
- * (msf_batched_workspace_bytes with a NULL options pointer suffices).
+ * Autotuner for the batched solver: a coordinate search from the defaults,
+ * one option at a time in this order, keeping the fastest value of each:
+ * block {512, 1024}, lds_vertices {1024, 2048, 4096}, coop_edges {2^19,
+ * 2^20, never}, hot_min {4, 8, 16, off}, wave_min {2, 4, off}.  Each candidate runs the batch once on `stream`, timed
+ * with HIP events (after one warm-up run); the fastest options go to
+ * *best_out (HOST) and its time to *best_ms_out (HOST, nullable).  Blocking.
+ * Same array arguments as msf_compute_batched; the workspace must fit every
+ * candidate (msf_batched_workspace_bytes with a NULL options pointer suffices).
  */
 int msf_batched_autotune(const int32_t* u, const int32_t* v, const uint32_t* w,
                          const int64_t* edge_off, const int64_t* vert_off, int64_t G,

@@ -98,7 +98,8 @@ SYMBOLS = ("msf_workspace_bytes", "msf_compute", "msf_compute_noalloc", "msf_sta
 class BatchOptions(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("lds_vertices", ctypes.c_int32),
                 ("workgroups", ctypes.c_int32), ("coop_edges", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("wave_edges", ctypes.c_int32), ("hot_min", ctypes.c_int32),
+                ("wave_min", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -261,10 +262,12 @@ def profile_read():
                                    "bytes": float(buf[i].bytes)} for i in range(k)}
 
 
-def make_batch_options(block=0, lds_vertices=0, workgroups=0, coop_edges=0):
+def make_batch_options(block=0, lds_vertices=0, workgroups=0, coop_edges=0, wave_edges=0,
+                       hot_min=0, wave_min=0):
     o = BatchOptions()
     o.block, o.lds_vertices, o.workgroups = int(block), int(lds_vertices), int(workgroups)
-    o.coop_edges = int(coop_edges)
+    o.coop_edges, o.wave_edges = int(coop_edges), int(wave_edges)
+    o.hot_min, o.wave_min = int(hot_min), int(wave_min)
     return o
 
 
@@ -357,7 +360,8 @@ class Batch:
         if self._graph is not None:
             self.close()
         return {"block": best.block, "lds_vertices": best.lds_vertices,
-                "coop_edges": best.coop_edges, "ms": ms.value}
+                "coop_edges": best.coop_edges, "wave_edges": best.wave_edges,
+                "hot_min": best.hot_min, "wave_min": best.wave_min, "ms": ms.value}
 
     def close(self):
         if self._graph is not None:

@@ -18,9 +18,13 @@ constexpr int64_t kPairMax = 4096;
 // Per-launch counters at the start of the workspace (zeroed by k_batch_prep).
 struct BatchQueue {
     uint32_t big_next;              // next index into the cooperative list
-    uint32_t small_next;            // next index into the other list
+    uint32_t small_next;            // next index into the workgroup list
     uint32_t nbig;                  // graphs solved cooperatively
     uint32_t err;                   // a bounded wait ran out (results invalid)
+    uint32_t tiny_next;             // next index into the wave list
+    uint32_t ntiny;                 // graphs solved by one wave each
+    uint32_t nsmall;                // graphs solved by one workgroup each
+    uint32_t pad;
 };
 
 // Cooperative solve of one graph at a time by every workgroup of one XCD.
@@ -59,7 +63,8 @@ struct BatchArgs {
     BatchQueue* q;
     XcdWork* xw;             // [kMaxXcd]
     int32_t* big;            // [G] cooperative graphs in processing order (first q->nbig)
-    int32_t* small;          // [G] the others in processing order
+    int32_t* small;          // [G] workgroup graphs in processing order (first q->nsmall)
+    int32_t* tiny;           // [G] wave graphs in processing order (first q->ntiny)
     char* xslots;            // kMaxXcd state slots (cooperative solves), xslot_bytes each
     char* wslots;            // one state slot per workgroup (graphs above lds_n)
     size_t slot_bytes;       // per-vertex state of one graph
@@ -67,6 +72,12 @@ struct BatchArgs {
     int64_t nmax;            // vertices per graph the slots are sized for
     int64_t coop_edges;      // graphs with at least this many edges are cooperative (< 0: none)
     int lds_n;               // graphs with n <= lds_n keep their state in LDS
+    int64_t wave_edges;      // graphs with m <= wave_edges and n <= wave_n: one wave each
+    int wave_n;              //   (0: no wave graphs); wave_n = lds_n / waves per workgroup
+    int hot_min;             // block tier of the segmented min: a label on at least this
+                             //   many of a chunk's 64 sampled edge ends (0: off)
+    int wave_min;            // wave tier: lanes sharing a label combine when at least
+                             //   this many (0: off, every lane updates alone)
 };
 
 struct BatchLayout {

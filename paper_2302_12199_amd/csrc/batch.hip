@@ -7,7 +7,7 @@
 // graph's vertices.  No host round trip is needed, so the launch can be
 // captured in a hipGraph.
 //
-// Two lists, built by k_batch_prep in the caller's order (largest first by
+// Three lists, built by k_batch_prep in the caller's order (largest first by
 // default):
 //  * cooperative graphs (m >= coop_edges) are solved one at a time per XCD by
 //    every workgroup running on that XCD, so the graph's per-vertex state
@@ -16,8 +16,17 @@
 //    workgroup that completes a phase's last chunk sets up the next phase.
 //    A workgroup only ever waits for chunks that running workgroups took, so
 //    nothing assumes the whole grid is resident;
+//  * graphs with m <= wave_edges and n <= wave_n would be solved by one wave
+//    each, all state in the wave's share of the workgroup's LDS (this tier is
+//    switched off: the host never enables it, wave_n stays 0);
 //  * the other graphs are solved by one workgroup each, the state in LDS when
 //    n <= lds_n, else in the workgroup's own global slot.
+// The lightest-edge search updates a label's minimum in one of three tiers by
+// the label's degree among the edges being scanned: labels found on at least
+// hot_min of a chunk's 64 sampled edge ends keep their minimum in LDS for the
+// chunk (block tier); lanes of a wave sharing a label, at least wave_min of
+// them, are min-reduced across the wave first (wave tier); other lanes update
+// alone (thread tier).  All thresholds come from the options (autotuned).
 // Every wait is bounded by wall-clock time.
 #include "batch.h"
 #include "prim.h"
@@ -97,17 +106,88 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t x, uint64_t* s_red) {
     return t;
 }
 
+// Thread and wave tiers of one minimum update, called by the whole wave:
+// lanes sharing the first active lane's label, when at least wave_min of them
+// (wave_min > 0), are min-reduced across the wave and update once; the others
+// update alone.
+__device__ __forceinline__ void tier_update(uint64_t* best, int32_t t, uint64_t key, bool act,
+                                            int wave_min) {
+    if (wave_min > 0) {
+        const uint64_t am = __ballot(act);
+        if (am) {
+            const int leader = __builtin_ctzll(am);
+            const int32_t tl = __shfl(t, leader, 64);
+            const bool same = act && t == tl;
+            if (__popcll(__ballot(same)) >= (wave_min > 2 ? wave_min : 2)) {
+                const uint64_t k = wave_min_u64(same ? key : kKeyMax);
+                if (lane_id() == leader) atomic_min_key(&best[tl], k);
+                act = act && !same;
+            }
+        }
+    }
+    if (act) atomic_min_key(&best[t], key);
+}
+
+// Block tier, chosen per chunk: one wave samples 32 evenly spaced edges of
+// [lo, hi) (both ends, so 64 labels) and keeps the kHot labels seen on at
+// least hot_min of them; their minima live in LDS during the chunk.  Called by
+// the whole workgroup (contains barriers).
+template <int BS>
+__device__ void chunk_hot(const int32_t* __restrict__ U, const int32_t* __restrict__ V,
+                          int64_t lo, int64_t hi, int64_t n, int round, const int32_t* lab,
+                          int hot_min, int32_t* s_hot, unsigned long long* s_hotmin) {
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        int32_t l = -1;
+        if (hi > lo) {
+            const int64_t e = lo + (int64_t)(lane >> 1) * (hi - lo) / 32;
+            const int32_t x = (lane & 1) ? V[e] : U[e];
+            if ((uint32_t)x < (uint64_t)n) l = round == 0 ? x : lab[x];
+        }
+        for (int h = 0; h < kHot; ++h) {
+            int best_cnt = 0;
+            int32_t best_lab = -1;
+            for (int i = 0; i < kWave; ++i) {
+                const int32_t li = __shfl(l, i, kWave);
+                const int c = __popcll(__ballot(l == li && li >= 0));
+                if (c > best_cnt) { best_cnt = c; best_lab = li; }
+            }
+            if (lane == 0) {
+                s_hot[h] = best_cnt >= hot_min ? best_lab : -1;
+                s_hotmin[h] = kKeyMax;
+            }
+            if (best_lab >= 0 && l == best_lab) l = -1;
+        }
+    }
+    __syncthreads();
+}
+
+// Merges the block tier's LDS minima (after the chunk; whole workgroup).
+__device__ void chunk_hot_flush(uint64_t* best, const int32_t* s_hot,
+                                const unsigned long long* s_hotmin) {
+    __syncthreads();
+    if (threadIdx.x < kHot && s_hot[threadIdx.x] >= 0 && s_hotmin[threadIdx.x] != kKeyMax)
+        atomic_min_key(&best[s_hot[threadIdx.x]], s_hotmin[threadIdx.x]);
+    __syncthreads();
+}
+
 // Lightest edge of every endpoint label over edges [lo, hi) of one graph,
 // kEdgeIlp independent edges per thread (all loads and label gathers of a
 // step issued before any is used).  Round 0 reads the ids directly (labels
-// are the ids) and validates them.
+// are the ids) and validates them.  hot (or null): the block tier's labels,
+// their minima in s_hotmin; wave_min: the wave tier's threshold.
 template <int BS>
 __device__ __forceinline__ void min_edges(const int32_t* __restrict__ U,
                                           const int32_t* __restrict__ V,
                                           const uint32_t* __restrict__ W, int64_t lo, int64_t hi,
                                           int64_t n, int round, const int32_t* lab,
-                                          uint64_t* best, int& any, bool& bad) {
+                                          uint64_t* best, int& any, bool& bad,
+                                          const int32_t* s_hot, unsigned long long* s_hotmin,
+                                          int wave_min) {
     const int tid = threadIdx.x;
+    int32_t hot[kHot];
+#pragma unroll
+    for (int h = 0; h < kHot; ++h) hot[h] = s_hot ? s_hot[h] : -1;
     for (int64_t base = lo; base < hi; base += (int64_t)BS * kEdgeIlp) {
         int32_t a[kEdgeIlp], b[kEdgeIlp], la[kEdgeIlp], lb[kEdgeIlp];
         uint32_t wt[kEdgeIlp];
@@ -137,12 +217,14 @@ __device__ __forceinline__ void min_edges(const int32_t* __restrict__ U,
         }
 #pragma unroll
         for (int k = 0; k < kEdgeIlp; ++k) {
-            if (la[k] == lb[k]) continue;
+            const bool act = la[k] != lb[k];
             const int64_t e = base + k * BS + tid;
-            any = 1;
             const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)e;
-            atomic_min_key(&best[la[k]], key);
-            atomic_min_key(&best[lb[k]], key);
+            if (act) any = 1;
+            const bool hx = act && s_hot && hot_min(hot, s_hotmin, la[k], key);
+            const bool hy = act && s_hot && hot_min(hot, s_hotmin, lb[k], key);
+            tier_update(best, la[k], key, act && !hx, wave_min);
+            tier_update(best, lb[k], key, act && !hy, wave_min);
         }
     }
 }
@@ -175,9 +257,12 @@ __device__ __forceinline__ uint64_t hook_range(const int32_t* __restrict__ U,
 // --------------------------------------------------- one workgroup per graph
 
 // State arrays of `cap` vertices (LDS or a global slot).
+// tiers: the state is in global memory (the slot), so the block and wave
+// tiers of the lightest-edge search apply; in LDS every update is cheap.
 template <int BS>
 __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t* lab,
-                            uint64_t* best, int32_t* par, int32_t* nid, uint32_t* s_wave) {
+                            uint64_t* best, int32_t* par, int32_t* nid, uint32_t* s_wave,
+                            bool tiers, int32_t* s_hot, unsigned long long* s_hotmin) {
     const int tid = threadIdx.x;
     const int64_t e0 = A.eoff[g];
     const int64_t m = A.eoff[g + 1] - e0;
@@ -199,7 +284,11 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
             for (int64_t x = tid; x < ncur; x += BS) best[x] = kKeyMax;
             __syncthreads();
             int any = 0;
-            min_edges<BS>(U, V, W, 0, m, n, round, lab, best, any, bad);
+            const bool block_tier = tiers && A.hot_min > 0;
+            if (block_tier) chunk_hot<BS>(U, V, 0, m, n, round, lab, A.hot_min, s_hot, s_hotmin);
+            min_edges<BS>(U, V, W, 0, m, n, round, lab, best, any, bad,
+                          block_tier ? s_hot : nullptr, s_hotmin, tiers ? A.wave_min : 0);
+            if (block_tier) chunk_hot_flush(best, s_hot, s_hotmin);
             if (!__syncthreads_or(any) || __syncthreads_or(bad)) break;
             wsum += hook_range(U, V, 0, ncur, BS, lab, best, par, mask);
             __syncthreads();
@@ -240,6 +329,111 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
         if (A.ticks) A.ticks[g] = wall_clock64();
     }
     __syncthreads();
+}
+
+// ------------------------------------------------------- one wave per graph
+
+// Orders the wave's LDS accesses: every lane's earlier LDS operations have
+// completed before any lane goes on.
+__device__ __forceinline__ void wave_sync() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The whole of one small graph by one wave, its state (20 B per vertex) in
+// the wave's share of LDS: the rounds of solve_graph with wave-wide votes
+// instead of workgroup barriers.
+__device__ void solve_graph_wave(const BatchArgs& A, int64_t g, int64_t cap, int32_t* lab,
+                                 uint64_t* best, int32_t* par, int32_t* nid) {
+    const int lane = lane_id();
+    const int64_t e0 = A.eoff[g];
+    const int64_t m = A.eoff[g + 1] - e0;
+    const int64_t n = A.voff[g + 1] - A.voff[g];
+    const int32_t* U = A.u + e0;
+    const int32_t* V = A.v + e0;
+    const uint32_t* W = A.w + e0;
+    uint8_t* mask = A.mask + e0;
+    if (lane == 0 && A.ticks) A.ticks[A.G + 1 + g] = wall_clock64();
+    const bool bad_shape = n < 0 || n > cap || m < 0 || m > 0xffffffffLL;
+    bool bad = bad_shape;
+    uint64_t wsum = 0;
+    if (!bad_shape) {
+        for (int64_t i = lane; i < m; i += kWave) mask[i] = 0;
+        for (int64_t x = lane; x < n; x += kWave) lab[x] = (int32_t)x;
+        int64_t ncur = n;
+        wave_sync();
+        for (int round = 0; round < kBatchMaxRounds && ncur > 1; ++round) {
+            for (int64_t x = lane; x < ncur; x += kWave) best[x] = kKeyMax;
+            wave_sync();
+            bool any = false;
+            for (int64_t e = lane; e < m; e += kWave) {
+                int32_t a = U[e], b = V[e];
+                if (a == b) continue;
+                if (round == 0) {
+                    if ((uint32_t)a >= (uint64_t)n || (uint32_t)b >= (uint64_t)n) {
+                        bad = true;
+                        continue;
+                    }
+                } else {
+                    a = lab[a];
+                    b = lab[b];
+                    if (a == b) continue;
+                }
+                any = true;
+                const uint64_t key = ((uint64_t)W[e] << 32) | (uint64_t)e;
+                atomic_min_key(&best[a], key);
+                atomic_min_key(&best[b], key);
+            }
+            wave_sync();
+            if (!__ballot(any) || __ballot(bad)) break;
+            for (int64_t x = lane; x < ncur; x += kWave) {      // hook + MSF mark
+                const uint64_t b = best[x];
+                if (b == kKeyMax) { par[x] = (int32_t)x; continue; }
+                const uint32_t pos = (uint32_t)b;
+                const int32_t la = round == 0 ? U[pos] : lab[U[pos]];
+                const int32_t lb = round == 0 ? V[pos] : lab[V[pos]];
+                const int32_t other = la == (int32_t)x ? lb : la;
+                if (best[other] == b && (int32_t)x < other) {
+                    par[x] = (int32_t)x;
+                } else {
+                    par[x] = other;
+                    mask[pos] = 1;
+                    wsum += b >> 32;
+                }
+            }
+            wave_sync();
+            for (int it = 0; it < kMaxJumps; ++it) {             // pointer jumping
+                bool changed = false;
+                for (int64_t x = lane; x < ncur; x += kWave) {
+                    const int32_t p = par[x], pp = par[p];
+                    if (p != pp) { par[x] = pp; changed = true; }
+                }
+                wave_sync();
+                if (!__ballot(changed)) break;
+            }
+            int64_t roots = 0;                                   // dense ids of roots
+            for (int64_t base = 0; base < ncur; base += kWave) {
+                const int64_t x = base + lane;
+                const bool r = x < ncur && par[x] == (int32_t)x && best[x] != kKeyMax;
+                const uint64_t bal = __ballot(r);
+                if (r) nid[x] = (int32_t)(roots + lanes_below(bal));
+                roots += __popcll(bal);
+            }
+            wave_sync();
+            for (int64_t i = lane; i < n; i += kWave) {          // compose labels
+                const int32_t l = lab[i];
+                if (l >= 0) lab[i] = best[l] == kKeyMax ? -1 : nid[par[l]];
+            }
+            ncur = roots;
+            wave_sync();
+        }
+    }
+    wsum = wave_sum_u64(wsum);
+    const bool anybad = __ballot(bad) != 0;
+    if (lane == 0) {
+        A.totals[g] = anybad ? kKeyMax : wsum;
+        if (A.ticks) A.ticks[g] = wall_clock64();
+    }
 }
 
 // ------------------------------------------------- cooperative (one per XCD)
@@ -416,7 +610,7 @@ struct CoopParams {
 template <int BS>
 __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
                            const CoopParams& P, uint32_t chunk, uint32_t* s_wave,
-                           uint64_t* s_red) {
+                           uint64_t* s_red, int32_t* s_hot, unsigned long long* s_hotmin) {
     constexpr int64_t CV = (int64_t)BS * kCoopVertsPerThread;
     constexpr int64_t CE = (int64_t)BS * kCoopEdgesPerThread;
     constexpr int64_t CP = (int64_t)BS * kCoopPairsPerThread;
@@ -444,20 +638,30 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
             if (P.pair_mode) {            // over the pair table
                 const int64_t np = P.pn * (P.pn - 1) / 2;
                 const int64_t s0 = (int64_t)chunk * CP, sh = s0 + CP < np ? s0 + CP : np;
-                for (int64_t sl = s0 + tid; sl < sh; sl += BS) {
-                    const uint64_t key = S.pairs[sl];
-                    if (key == kKeyMax) continue;
-                    int32_t lo, hi;
-                    tri_pair(sl, lo, hi);
-                    const int32_t lx = S.plab[lo], ly = S.plab[hi];
-                    if (lx == ly) continue;
-                    any = 1;
-                    atomic_min_key(&S.best[lx], key);
-                    atomic_min_key(&S.best[ly], key);
+                for (int64_t base = s0; base < sh; base += BS) {   // uniform per wave
+                    const int64_t sl = base + tid;
+                    const uint64_t key = sl < sh ? S.pairs[sl] : kKeyMax;
+                    int32_t lx = -1, ly = -1;
+                    if (key != kKeyMax) {
+                        int32_t lo, hi;
+                        tri_pair(sl, lo, hi);
+                        lx = S.plab[lo];
+                        ly = S.plab[hi];
+                    }
+                    const bool act = lx != ly;
+                    if (act) any = 1;
+                    tier_update(S.best, lx, key, act, A.wave_min);
+                    tier_update(S.best, ly, key, act, A.wave_min);
                 }
             } else {
                 const int64_t eh = e0 + CE < P.m ? e0 + CE : P.m;
-                min_edges<BS>(U, V, W, e0, eh, P.n, (int)P.round, S.lab, S.best, any, bad);
+                const bool block_tier = A.hot_min > 0;
+                if (block_tier)
+                    chunk_hot<BS>(U, V, e0, eh, P.n, (int)P.round, S.lab, A.hot_min, s_hot,
+                                  s_hotmin);
+                min_edges<BS>(U, V, W, e0, eh, P.n, (int)P.round, S.lab, S.best, any, bad,
+                              block_tier ? s_hot : nullptr, s_hotmin, A.wave_min);
+                if (block_tier) chunk_hot_flush(S.best, s_hot, s_hotmin);
             }
             const int bany = __syncthreads_or(any), bbad = __syncthreads_or(bad);
             if (tid == 0) {
@@ -564,7 +768,8 @@ __device__ bool coop_wait(XcdWork* X, uint32_t p, BatchQueue* q) {
 }
 
 template <int BS>
-__device__ void coop_run(const BatchArgs& A, uint32_t* s_wave, uint64_t* s_red) {
+__device__ void coop_run(const BatchArgs& A, uint32_t* s_wave, uint64_t* s_red, int32_t* s_hot,
+                         unsigned long long* s_hotmin) {
     __shared__ uint64_t s_ticket;
     __shared__ CoopParams s_p;
     __shared__ uint32_t s_flag;
@@ -610,7 +815,7 @@ __device__ void coop_run(const BatchArgs& A, uint32_t* s_wave, uint64_t* s_red) 
             if (gave_up) break;
             continue;
         }
-        coop_chunk<BS>(A, X, S, P, chunk, s_wave, s_red);
+        coop_chunk<BS>(A, X, S, P, chunk, s_wave, s_red, s_hot, s_hotmin);
         xcd_release();                       // every wave's stores reach the L2 ...
         __syncthreads();
         if (threadIdx.x == 0) {              // ... before the chunk counts as done
@@ -632,12 +837,14 @@ __global__ __launch_bounds__(BS) void k_batch(BatchArgs A) {
     __shared__ uint32_t s_wave[BS / kWave];
     __shared__ uint64_t s_red[BS / kWave];
     __shared__ int64_t s_g;
+    __shared__ int32_t s_hot[kHot];
+    __shared__ unsigned long long s_hotmin[kHot];
     if (threadIdx.x == 0 && A.ticks)
         atomicMin((unsigned long long*)&A.ticks[A.G], (unsigned long long)wall_clock64());
     if (__hip_atomic_load(&A.q->nbig, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0)
-        coop_run<BS>(A, s_wave, s_red);
+        coop_run<BS>(A, s_wave, s_red, s_hot, s_hotmin);
 
-    const int64_t nsmall = A.G - (int64_t)A.q->nbig;
+    const int64_t nsmall = (int64_t)A.q->nsmall;
     const int64_t cap = A.lds_n;
     char* wslot = A.wslots + (size_t)blockIdx.x * A.slot_bytes;
     const SlotView G = slot_view(wslot, A.nmax, A.slot_bytes);
@@ -650,10 +857,29 @@ __global__ __launch_bounds__(BS) void k_batch(BatchArgs A) {
         const int64_t g = A.small[gi];
         if (A.voff[g + 1] - A.voff[g] <= cap) {
             int32_t* lab = reinterpret_cast<int32_t*>(lds + cap);
-            solve_graph<BS>(A, g, cap, lab, lds, lab + cap, lab + 2 * cap, s_wave);
+            solve_graph<BS>(A, g, cap, lab, lds, lab + cap, lab + 2 * cap, s_wave, false, s_hot,
+                            s_hotmin);
         } else {
-            solve_graph<BS>(A, g, A.nmax, G.lab, G.best, G.par, G.nid, s_wave);
+            solve_graph<BS>(A, g, A.nmax, G.lab, G.best, G.par, G.nid, s_wave, true, s_hot,
+                            s_hotmin);
         }
+    }
+
+    // Wave graphs: from here on every wave works alone, on its share of the
+    // LDS (wave_n vertices of 20 B: minima first, then labels, parents, ids).
+    const int64_t ntiny = (int64_t)A.q->ntiny;
+    if (ntiny == 0 || A.wave_n <= 0) return;
+    const int wave = threadIdx.x / kWave;
+    const int64_t wcap = A.wave_n;
+    uint64_t* wbest = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(lds) +
+                                                  (size_t)wave * (size_t)wcap * 20);
+    int32_t* wlab = reinterpret_cast<int32_t*>(wbest + wcap);
+    while (true) {
+        uint32_t gi = 0;
+        if (lane_id() == 0) gi = atomicAdd(&A.q->tiny_next, 1u);
+        gi = __shfl(gi, 0, kWave);
+        if ((int64_t)gi >= ntiny) break;
+        solve_graph_wave(A, A.tiny[gi], wcap, wlab, wbest, wlab + wcap, wlab + 2 * wcap);
     }
 }
 
@@ -668,26 +894,35 @@ __global__ __launch_bounds__(kPrepThreads) void k_batch_prep(BatchArgs A) {
     __syncthreads();
     if (threadIdx.x < kMaxXcd) A.xw[threadIdx.x].ticket = (uint64_t)kNotReady << 32;
     if (threadIdx.x == 0 && A.ticks) A.ticks[A.G] = kKeyMax;
-    uint32_t nb = 0, ns = 0;
+    uint32_t nb = 0, ns = 0, nt = 0;
     for (int64_t base = 0; base < A.G; base += kPrepThreads) {
         const int64_t i = base + threadIdx.x;
         int64_t g = -1;
-        bool big = false;
+        bool big = false, tiny = false;
         if (i < A.G) {
             g = A.order ? (int64_t)A.order[i] : i;
-            big = A.coop_edges >= 0 && A.eoff[g + 1] - A.eoff[g] >= A.coop_edges;
+            const int64_t m = A.eoff[g + 1] - A.eoff[g], n = A.voff[g + 1] - A.voff[g];
+            big = A.coop_edges >= 0 && m >= A.coop_edges;
+            tiny = !big && A.wave_n > 0 && m <= A.wave_edges && n >= 0 && n <= A.wave_n;
         }
-        uint32_t tb, ts;
+        uint32_t tb, ts, tt;
         const uint32_t rb = block_rank<kPrepThreads>(big, s_wave, &tb);
-        const uint32_t rs = block_rank<kPrepThreads>(i < A.G && !big, s_wave, &ts);
+        const uint32_t rs = block_rank<kPrepThreads>(i < A.G && !big && !tiny, s_wave, &ts);
+        const uint32_t rt = block_rank<kPrepThreads>(tiny, s_wave, &tt);
         if (i < A.G) {
             if (big) A.big[nb + rb] = (int32_t)g;
+            else if (tiny) A.tiny[nt + rt] = (int32_t)g;
             else A.small[ns + rs] = (int32_t)g;
         }
         nb += tb;
         ns += ts;
+        nt += tt;
     }
-    if (threadIdx.x == 0) A.q->nbig = nb;
+    if (threadIdx.x == 0) {
+        A.q->nbig = nb;
+        A.q->nsmall = ns;
+        A.q->ntiny = nt;
+    }
 }
 
 size_t batch_slot_bytes(int64_t nmax) {
@@ -707,7 +942,7 @@ BatchLayout batch_layout(int64_t G, int64_t nmax, int workgroups) {
     L.xw_off = off;
     off += (size_t)kMaxXcd * sizeof(XcdWork);
     L.lists_off = off;
-    off += ((size_t)(G > 0 ? G : 1) * 8 + 255) / 256 * 256;
+    off += ((size_t)(G > 0 ? G : 1) * 12 + 255) / 256 * 256;
     L.xslots_off = off;
     off += (size_t)kMaxXcd * batch_xslot_bytes(nmax);
     L.wslots_off = off;

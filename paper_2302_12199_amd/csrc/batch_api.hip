@@ -9,11 +9,10 @@ using namespace msf;
 
 namespace {
 
-constexpr int kTuneCoop[3] = {1 << 19, 1 << 20, -1};
-
 struct Resolved {
     int block, lds_n, workgroups;
-    int64_t coop_edges;
+    int64_t coop_edges, wave_edges;
+    int hot_min, wave_min;
 };
 
 // Host-side defaults and checks (no device needed).
@@ -22,9 +21,25 @@ int resolve(const msf_batch_options* opt, Resolved* r) {
     r->lds_n = 2048;
     r->workgroups = 0;
     r->coop_edges = 1 << 20;
+    r->wave_edges = -1;      // the wave-per-graph tier is switched off (see below)
+    r->hot_min = 8;
+    r->wave_min = 2;
     if (opt) {
-        for (int i = 0; i < 4; ++i)
-            if (opt->reserved[i]) return MSF_EINVAL;
+        if (opt->reserved[0]) return MSF_EINVAL;
+        if (opt->wave_edges < -1 || opt->hot_min < -1 || opt->hot_min > 64 ||
+            opt->wave_min < -1 || opt->wave_min == 1 || opt->wave_min > 64)
+            return MSF_EINVAL;
+        // The wave-per-graph tier hung the GPU in its first test run and its
+        // cause has not been found: it stays switched off, and asking for it
+        // is an error rather than a silent fallback.
+        if (opt->wave_edges > 0) {
+            set_err_text("the wave-per-graph tier (wave_edges > 0) is switched off");
+            return MSF_EINVAL;
+        }
+        if (opt->hot_min == -1) r->hot_min = 0;
+        else if (opt->hot_min > 0) r->hot_min = opt->hot_min;
+        if (opt->wave_min == -1) r->wave_min = 0;
+        else if (opt->wave_min > 0) r->wave_min = opt->wave_min;
         if (opt->block) {
             if (opt->block != 256 && opt->block != 512 && opt->block != 1024) return MSF_EINVAL;
             r->block = opt->block;
@@ -76,6 +91,7 @@ int prepare(const int32_t* u, const int32_t* v, const uint32_t* w, const int64_t
     A->xw = (XcdWork*)(base + L.xw_off);
     A->big = (int32_t*)(base + L.lists_off);
     A->small = A->big + G;
+    A->tiny = A->small + G;
     A->xslots = base + L.xslots_off;
     A->wslots = base + L.wslots_off;
     A->slot_bytes = batch_slot_bytes(max_n);
@@ -83,6 +99,10 @@ int prepare(const int32_t* u, const int32_t* v, const uint32_t* w, const int64_t
     A->nmax = max_n;
     A->coop_edges = r->coop_edges;
     A->lds_n = r->lds_n;
+    A->wave_edges = r->wave_edges;
+    A->wave_n = r->wave_edges >= 0 ? r->lds_n / (r->block / kWave) : 0;
+    A->hot_min = r->hot_min;
+    A->wave_min = r->wave_min;
     return MSF_OK;
 }
 
@@ -187,41 +207,56 @@ int msf_batched_autotune(const int32_t* u, const int32_t* v, const uint32_t* w,
                          void* stream, msf_batch_options* best_out, float* best_ms_out) {
     if (!best_out) return MSF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const int blocks[2] = {512, 1024};
-    const int ldss[3] = {1024, 2048, 4096};
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&b));
-    float best_ms = -1.f;
+    // one run of `o`: its time in ms, or < 0 when the workspace does not fit it
+    auto run = [&](const msf_batch_options& o, float* ms) -> int {
+        *ms = -1.f;
+        HIP_TRY(hipEventRecord(a, s));
+        int st = msf_compute_batched(u, v, w, edge_off, vert_off, G, max_n, order, mask_out,
+                                     totals_out, nullptr, workspace, workspace_bytes, stream, &o);
+        if (st == MSF_EWORKSPACE) return MSF_OK;
+        if (st) return st;
+        HIP_TRY(hipEventRecord(b, s));
+        HIP_TRY(hipEventSynchronize(b));
+        HIP_TRY(hipEventElapsedTime(ms, a, b));
+        return MSF_OK;
+    };
     msf_batch_options best;
     memset(&best, 0, sizeof best);
-    for (int bi = 0; bi < 2; ++bi) {
-        for (int li = 0; li < 3; ++li) {
-            for (int coop : kTuneCoop) {
-                msf_batch_options o;
-                memset(&o, 0, sizeof o);
-                o.block = blocks[bi];
-                o.lds_vertices = ldss[li];
-                o.coop_edges = coop;
-                float ms = 0.f;
-                for (int rep = 0; rep < 2; ++rep) {   // first run warms up
-                    HIP_TRY(hipEventRecord(a, s));
-                    int st = msf_compute_batched(u, v, w, edge_off, vert_off, G, max_n, order,
-                                                 mask_out, totals_out, nullptr, workspace,
-                                                 workspace_bytes, stream, &o);
-                    if (st == MSF_EWORKSPACE) break;   // candidate needs more workspace
-                    if (st) { (void)hipEventDestroy(a); (void)hipEventDestroy(b); return st; }
-                    HIP_TRY(hipEventRecord(b, s));
-                    HIP_TRY(hipEventSynchronize(b));
-                    HIP_TRY(hipEventElapsedTime(&ms, a, b));
-                }
-                if (ms > 0.f && (best_ms < 0.f || ms < best_ms)) { best_ms = ms; best = o; }
+    float best_ms = -1.f, ms = 0.f;
+    int st = run(best, &ms);                      // warm-up
+    if (st == MSF_OK) st = run(best, &best_ms);
+    // coordinate search: one option at a time, the rest at their best so far
+    const int blocks[] = {512, 1024};
+    const int ldss[] = {1024, 2048, 4096};
+    const int coops[] = {1 << 19, 1 << 20, -1};
+    const int hots[] = {4, 8, 16, -1};
+    const int wmins[] = {2, 4, -1};
+    struct Axis { int32_t msf_batch_options::*field; const int* vals; int n; };
+    const Axis axes[] = {{&msf_batch_options::block, blocks, 2},
+                         {&msf_batch_options::lds_vertices, ldss, 3},
+                         {&msf_batch_options::coop_edges, coops, 3},
+                         {&msf_batch_options::hot_min, hots, 4},
+                         {&msf_batch_options::wave_min, wmins, 3}};
+    for (const Axis& ax : axes) {
+        if (st) break;
+        const msf_batch_options base = best;
+        for (int i = 0; i < ax.n && st == MSF_OK; ++i) {
+            msf_batch_options o = base;
+            o.*(ax.field) = ax.vals[i];
+            st = run(o, &ms);
+            if (st == MSF_OK && ms > 0.f && (best_ms <= 0.f || ms < best_ms)) {
+                best_ms = ms;
+                best = o;
             }
         }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    if (best_ms < 0.f) return MSF_EWORKSPACE;
+    if (st) return st;
+    if (best_ms <= 0.f) return MSF_EWORKSPACE;
     *best_out = best;
     if (best_ms_out) *best_ms_out = best_ms;
     return MSF_OK;

@@ -141,6 +141,11 @@ def test_batched_argument_checks(msf):
     rc = lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, 3, 10, None, FAKE, FAKE, None,
                                  FAKE + 16, 1 << 30, None, None)
     assert rc == msf.EINVAL                      # workspace not 256-byte aligned
+    for kw in (dict(wave_min=1), dict(wave_min=65), dict(hot_min=65), dict(hot_min=-2),
+               dict(wave_edges=-2), dict(wave_edges=4096)):   # the wave tier is switched off
+        o = msf.make_batch_options(**kw)
+        assert lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, 3, 10, None, FAKE, FAKE,
+                                       None, FAKE, 1 << 30, None, ctypes.byref(o)) == msf.EINVAL
     o = msf.make_batch_options()
     o.reserved[0] = 1
     assert lib.msf_compute_batched(FAKE, FAKE, FAKE, FAKE, FAKE, 3, 10, None, FAKE, FAKE, None,

@@ -66,6 +66,49 @@ def test_batch_cooperative_match_oracle(coop, workgroups):
         assert (mask == rm).all()
 
 
+@pytest.mark.parametrize("hot_min,wave_min,coop", [(0, 0, 1 << 16), (4, 2, 1 << 15),
+                                                   (-1, -1, 1 << 14), (1, 64, 1 << 14)])
+def test_batch_tiers_match_oracle(hot_min, wave_min, coop):
+    """The workgroup and XCD graph tiers with the vertex tiers of the
+    lightest-edge search (block: LDS minima of a chunk's sampled frequent
+    labels; wave: lanes sharing a label combined) at several thresholds,
+    including every label in the block tier (hot_min 1) and a wave tier that
+    never triggers (64)."""
+    import paper_2302_12199_amd as msf
+    wave_edges = -1
+    banner(f"batch tiers hot_min={hot_min} wave_min={wave_min} coop={coop}")
+    u, v, w, eo, vo = graphgen.batch_gnm(300, lo=8, hi=15, dlo=2, dhi=40, wlo=1, whi=40,
+                                         seed=31)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    opts = msf.make_batch_options(block=512, lds_vertices=4096, coop_edges=coop,
+                                  wave_edges=wave_edges, hot_min=hot_min, wave_min=wave_min)
+    b = make_batch(u, v, w, eo, vo, options=opts)
+    for _ in range(2):
+        b.launch()
+        mask, totals = results(b)
+        assert (totals == rt).all()
+        assert (mask == rm).all()
+    ticks = b.ticks.cpu().numpy().view(np.uint64)
+    G = len(rt)
+    assert (ticks[:G] >= ticks[G + 1:]).all()
+
+
+@pytest.mark.skip(reason="the wave-per-graph tier hung the GPU in its first run (cause not "
+                         "found); it is switched off and positive wave_edges are rejected")
+def test_batch_many_tiny_graphs_wave_tier():
+    """20,000 graphs of 8 to 200 vertices: the wave tier's workload."""
+    import paper_2302_12199_amd as msf
+    banner("batch 20k tiny graphs")
+    u, v, w, eo, vo = graphgen.batch_gnm(20000, lo=3, hi=7.6, dlo=1, dhi=12, wlo=1, whi=9,
+                                         seed=33)
+    rm, rt = oracle_batch(u, v, w, eo, vo)
+    for wave_edges in (-1, 8192):
+        b = make_batch(u, v, w, eo, vo, options=msf.make_batch_options(wave_edges=wave_edges))
+        b.launch()
+        mask, totals = results(b)
+        assert (totals == rt).all() and (mask == rm).all()
+
+
 def test_batch_bad_graph_flagged_in_every_path():
     import paper_2302_12199_amd as msf
     banner("batch invalid ids")
@@ -80,7 +123,7 @@ def test_batch_bad_graph_flagged_in_every_path():
     u[eo[small] + 1] = sizes[small]       # in an LDS-solved one
     u[eo[mid] + 2] = -1                   # and in one solved in a global slot
     b = make_batch(u, v, w, eo, vo,
-                   options=msf.make_batch_options(lds_vertices=1024, coop_edges=int(
+                   options=msf.make_batch_options(lds_vertices=1024, wave_edges=-1, coop_edges=int(
                        (eo[big + 1] - eo[big]))))
     b.launch()
     mask, totals = results(b)
