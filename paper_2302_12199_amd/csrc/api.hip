@@ -244,8 +244,6 @@ int msf_compute(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m
         if (workspace_bytes < need) return MSF_EWORKSPACE;
         if ((uintptr_t)ws % 256) return MSF_EINVAL;   // its buffers take 16-byte vector accesses
     } else {
-        const char* fail = getenv("MSF_TEST_FAIL_ALLOC");
-        if (fail && fail[0] == '1') return MSF_ENOMEM;
         if (hipMallocAsync(&ws, need, s) != hipSuccess) {
             (void)hipGetLastError();
             return MSF_ENOMEM;

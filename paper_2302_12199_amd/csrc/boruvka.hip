@@ -953,21 +953,11 @@ static bool allow_lds(size_t bytes) {
     return ok;
 }
 
-// MSF_PASS_LDS=0 turns LDS staging off (a tuning and diagnosis knob).
-static bool lds_enabled() {
-    static int on = -1;
-    if (on < 0) {
-        const char* e = getenv("MSF_PASS_LDS");
-        on = (e && e[0] == '0') ? 0 : 1;
-    }
-    return on == 1;
-}
-
 template <int IN, int OUT, bool PAIR>
 static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* ou, int32_t* ov,
                           uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
                           const uint64_t* pair_hot, Ctrl* ctrl, hipStream_t s) {
-    const bool lds_on = lds_enabled();
+    const bool lds_on = true;
     bool ldsb = false;
     int64_t km = 0;
     size_t lds = 0;

@@ -94,54 +94,9 @@ size_t engine_bytes(int64_t m, int64_t n, bool buckets, bool exact) {
     return engine_carve(nullptr, m, n, nullptr, buckets, exact);
 }
 
-// MSF_ALWAYS_COMPACT=1 compacts after every round (a tuning and diagnosis knob).
-static bool always_compact() {
-    static int on = -1;
-    if (on < 0) {
-        const char* e = getenv("MSF_ALWAYS_COMPACT");
-        on = (e && e[0] == '1') ? 1 : 0;
-    }
-    return on == 1;
-}
-
-// MSF_BUCKET_R0=0 runs round 0 on the caller's edge list directly even where
-// the bucketed round 0 applies (a tuning and diagnosis knob).
-static bool bucket_r0_enabled() {
-    static int on = -1;
-    if (on < 0) {
-        const char* e = getenv("MSF_BUCKET_R0");
-        on = (e && e[0] == '0') ? 0 : 1;
-    }
-    return on == 1;
-}
-
 static bool aligned16(const View& g) {
     return ((((uintptr_t)g.u | (uintptr_t)g.v | (uintptr_t)g.w | (uintptr_t)g.p16 |
               (uintptr_t)g.id) & 15) == 0);
-}
-
-// MSF_DUMP_DIR=<dir> writes each round's parent, label, map and next-best
-// arrays to <dir>/<round>_<name>.bin (a diagnosis aid; off by default).
-static const char* dump_dir() {
-    static int init = 0;
-    static const char* d = nullptr;
-    if (!init) { init = 1; d = getenv("MSF_DUMP_DIR"); }
-    return d;
-}
-
-static void dump(const char* name, uint32_t round, const void* dev, size_t bytes, hipStream_t s) {
-    const char* d = dump_dir();
-    if (!d || bytes == 0) return;
-    void* h = malloc(bytes);
-    if (!h) return;
-    if (hipMemcpyAsync(h, dev, bytes, hipMemcpyDeviceToHost, s) == hipSuccess &&
-        hipStreamSynchronize(s) == hipSuccess) {
-        char path[512];
-        snprintf(path, sizeof path, "%s/%02u_%s.bin", d, round, name);
-        FILE* f = fopen(path, "wb");
-        if (f) { fwrite(h, 1, bytes, f); fclose(f); }
-    }
-    free(h);
 }
 
 static double view_read_bytes(int mode) { return mode == kFull16 ? 8.0 : 12.0; }
@@ -163,7 +118,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
     // vertex buckets (with locality the edge-list round 0 mostly hits in L2).
     // Both choices below read one sample of 4096 evenly spaced edges: do at
     // least half of them join ids less than 2^14 apart (locality)?
-    const bool can_bucket = mode == kOrig && bucket_r0_enabled() && aligned16(view) &&
+    const bool can_bucket = mode == kOrig && aligned16(view) &&
                             bucket_usable(B.bk, view.len, nv);
     bool local = false;
     if (mode == kOrig && view.len >= kLocalitySample &&
@@ -252,7 +207,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         const int64_t nn = (int64_t)hc->n_next;
         // Before the bucketed relabelling pass: the round-1 labels on many
         // edge ends are renumbered first (their minima then stay in LDS).
-        if (bucketed && mode == kOrig && nn > kTailMax && !always_compact())
+        if (bucketed && mode == kOrig && nn > kTailMax)
             bucket_hot_first(B.bk, view.u, view.v, view.len, lab, nr, nn, s);
         // Before the tail: the labels of its vertices are renumbered hot first
         // (the pair pass keeps the pairs among the first ones in LDS).
@@ -278,11 +233,6 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             origsel ^= 1;
         }
 
-        if (dump_dir() && mode == kCompact) {
-            dump("view_u", rounds - 1, view.u, view.len * 4, s);
-            dump("view_v", rounds - 1, view.v, view.len * 4, s);
-            dump("view_id", rounds - 1, view.id, view.len * 4, s);
-        }
         // M: stored labels -> next-round labels.
         const int32_t* M = lab;
         if (cmap) {
@@ -329,7 +279,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             }
             break;
         }
-        const bool compact = !aligned || always_compact() || (dedup != kDedupNone && !bucketed) ||
+        const bool compact = !aligned || (dedup != kDedupNone && !bucketed) ||
                              (dedup != kDedupNone && mode != kOrig) ||
                              (mode != kOrig && (double)m_live < kCompactBelow * (double)view.len);
         View next = view;
@@ -381,13 +331,6 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             }
         }
         HIP_TRY(hipGetLastError());
-        if (dump_dir()) {
-            dump("parent", rounds - 1, B.parent, nr * 4, s);
-            dump("label", rounds - 1, lab, nr * 4, s);
-            dump("map", rounds - 1, M, (cmap ? nc : nr) * 4, s);
-            dump("best_next", rounds - 1, B.best[cur ^ 1], nn * 8, s);
-            dump("best_cur", rounds - 1, B.best[cur], nr * 8, s);
-        }
         m_pending = true;
         m_compacted = compact;
         view = next;

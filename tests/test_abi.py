@@ -105,8 +105,12 @@ def test_workspace_not_256_byte_aligned(msf):
     assert rc == msf.EINVAL
 
 
-def test_forced_allocation_failure(msf, monkeypatch):
-    monkeypatch.setenv("MSF_TEST_FAIL_ALLOC", "1")
+def test_allocation_failure_is_reported(msf):
+    # no workspace given: the library allocates one, which fails without a
+    # usable device (this test runs on the CPU) -> MSF_ENOMEM, nothing launched
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present: the allocation would succeed")
     rc, _ = msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE)
     assert rc == msf.ENOMEM
 
