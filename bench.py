@@ -327,7 +327,8 @@ def run_batch_workload(msf, graphs, steps, warmup, plain_sample, autotune):
 # ------------------------------------------------------------------ extras
 
 EXTRA_WORKLOADS = [("C1", "gnm_n2^16_m2^20"), ("C3a", "grid_4096x4096_keep0.8_w1e6"),
-                   ("C3a_w255", "grid_4096x4096_keep0.8_w255"), ("C3b", "rgg2d_n2^24_deg8")]
+                   ("C3a_w255", "grid_4096x4096_keep0.8_w255"), ("C3b", "rgg2d_n2^24_deg8"),
+                   ("rgg3d", "rgg3d_n2^24_deg16_w254"), ("rhg", "rhg_n2^24_deg16_g3_w254")]
 FILTER_WORKLOAD = "rmat_n2^22_m2^28_w2^31"
 
 
