@@ -14,8 +14,11 @@
 //                next round's minedge (relabel fused with minEdges)
 // The pass either keeps the edge positions (rewriting endpoint labels, or
 // only composing the label map when nothing needs rewriting) or compacts the
-// live edges stably with a decoupled-lookback scan.
+// live edges stably (keep bits and counts per tile, a scan of the counts, a
+// scatter).
 #include <stdlib.h>
+
+#include <atomic>
 
 #include "launch.h"
 #include "prim.h"
@@ -139,6 +142,140 @@ __global__ __launch_bounds__(kBlock) void k_minedge_r0(
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrRange);
     __syncthreads();
     if (threadIdx.x == 0 && hot >= 0 && s_hot != kKeyMax) atomic_min_key(&best[hot], s_hot);
+}
+
+// Round-0 minedge for graphs whose edges join nearby ids (the locality
+// sample): each workgroup walks a contiguous run of tiles and keeps the minima
+// of a window of kWinSlots consecutive vertex ids in LDS.  The window start
+// only moves up (to just below each tile's first endpoint); the ids it leaves
+// behind are written out with one pre-checked global update each, read by
+// consecutive lanes.  Endpoints outside the window take the global path, their
+// reads issued together before the atomics.  Sorted-by-source edge lists (the
+// usual layout of generated and distributed graphs) keep nearly every endpoint
+// in the window; any other order is still correct, only slower.
+constexpr int kWinThreads = 1024;
+constexpr int kWinGroups = 2;                                   // 4-edge groups per lane per tile
+constexpr int64_t kWinTile = (int64_t)kWinThreads * 4 * kWinGroups;   // 8192 edges
+constexpr int64_t kWinSlots = 16384;                            // 128 KiB of minima
+constexpr int64_t kWinSlack = kWinSlots / 8;                    // room below a tile's first id
+
+__device__ __forceinline__ void win_flush(unsigned long long* s_min, uint64_t* best,
+                                          int64_t lo, int64_t hi) {
+    for (int64_t x = lo + threadIdx.x; x < hi; x += kWinThreads) {
+        const int slot = (int)(x & (kWinSlots - 1));
+        const uint64_t k = s_min[slot];
+        if (k != kKeyMax) {
+            s_min[slot] = kKeyMax;
+            atomic_min_key(&best[x], k);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWinThreads) void k_minedge_win(
+    const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
+    int64_t m, int64_t n, uint64_t* __restrict__ best, Ctrl* ctrl, int32_t hot,
+    int64_t tiles_per_block) {
+    __shared__ unsigned long long s_min[kWinSlots];
+    __shared__ unsigned long long s_hot;
+    __shared__ int64_t s_base;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kWinSlots; i += kWinThreads) s_min[i] = kKeyMax;
+    if (tid == 0) s_hot = kKeyMax;
+    const int64_t ntiles = (m + kWinTile - 1) / kWinTile;
+    const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+    const int64_t t1 = t0 + tiles_per_block < ntiles ? t0 + tiles_per_block : ntiles;
+    int64_t base = -1;            // window [base, base + kWinSlots), the same in every thread
+    bool bad = false;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t e0 = t * kWinTile;
+        if (tid == 0) {
+            const uint32_t a0 = (uint32_t)u[e0], b0 = (uint32_t)v[e0];
+            const int64_t f = (int64_t)(a0 < b0 ? a0 : b0);
+            int64_t nb = f < (int64_t)n ? f - kWinSlack : base;
+            if (nb < 0) nb = 0;
+            if (nb < base) nb = base;
+            s_base = nb;
+        }
+        __syncthreads();          // the last tile's LDS updates are done; s_base is set
+        const int64_t nb = s_base;
+        if (base >= 0 && nb > base)
+            win_flush(s_min, best, base, nb < base + kWinSlots ? nb : base + kWinSlots);
+        base = nb;
+        __syncthreads();          // the slots left behind are clear before they are reused
+        int32_t aa[kWinGroups * 4], bb[kWinGroups * 4];
+        uint32_t ww[kWinGroups * 4];
+#pragma unroll
+        for (int j = 0; j < kWinGroups; ++j) {
+            const int64_t g = e0 / 4 + (int64_t)j * kWinThreads + tid;
+            if (g * 4 + 3 < m) {
+                const int4 a4 = reinterpret_cast<const int4*>(u)[g];
+                const int4 b4 = reinterpret_cast<const int4*>(v)[g];
+                const uint4 w4 = reinterpret_cast<const uint4*>(w)[g];
+                aa[j * 4 + 0] = a4.x; aa[j * 4 + 1] = a4.y; aa[j * 4 + 2] = a4.z; aa[j * 4 + 3] = a4.w;
+                bb[j * 4 + 0] = b4.x; bb[j * 4 + 1] = b4.y; bb[j * 4 + 2] = b4.z; bb[j * 4 + 3] = b4.w;
+                ww[j * 4 + 0] = w4.x; ww[j * 4 + 1] = w4.y; ww[j * 4 + 2] = w4.z; ww[j * 4 + 3] = w4.w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t e = g * 4 + k;
+                    aa[j * 4 + k] = bb[j * 4 + k] = 0;
+                    ww[j * 4 + k] = 0;
+                    if (e < m) { aa[j * 4 + k] = u[e]; bb[j * 4 + k] = v[e]; ww[j * 4 + k] = w[e]; }
+                }
+            }
+        }
+        constexpr int kE = kWinGroups * 4;
+        uint64_t key[kE];
+        bool ga[kE], gb[kE];      // endpoint takes the global path
+#pragma unroll
+        for (int i = 0; i < kE; ++i) {
+            const int j = i / 4, k = i % 4;
+            const int64_t e = (e0 / 4 + (int64_t)j * kWinThreads + tid) * 4 + k;
+            int32_t a = aa[i], b = bb[i];
+            bool act = e < m;
+            if (act && ((uint32_t)a >= (uint64_t)n || (uint32_t)b >= (uint64_t)n)) {
+                bad = true;
+                act = false;
+            }
+            act = act && a != b;
+            key[i] = ((uint64_t)ww[i] << 32) | (uint64_t)e;
+            bool act_a = act, act_b = act;
+            if (act && (a == hot || b == hot)) {
+                atomicMin(&s_hot, (unsigned long long)key[i]);
+                act_a = a != hot;
+                act_b = b != hot;
+            }
+            const uint64_t oa = (uint64_t)((int64_t)a - base), ob = (uint64_t)((int64_t)b - base);
+            ga[i] = act_a && oa >= (uint64_t)kWinSlots;
+            gb[i] = act_b && ob >= (uint64_t)kWinSlots;
+            if (act_a && !ga[i]) {
+                unsigned long long* p = &s_min[a & (kWinSlots - 1)];
+                if (key[i] < *p) atomicMin(p, (unsigned long long)key[i]);
+            }
+            if (act_b && !gb[i]) {
+                unsigned long long* p = &s_min[b & (kWinSlots - 1)];
+                if (key[i] < *p) atomicMin(p, (unsigned long long)key[i]);
+            }
+            aa[i] = ga[i] ? a : 0;
+            bb[i] = gb[i] ? b : 0;
+        }
+        // outside the window: every read first, then the atomics that still lower
+        uint64_t ca[kE], cb[kE];
+#pragma unroll
+        for (int i = 0; i < kE; ++i) {
+            ca[i] = ga[i] ? best[aa[i]] : 0;
+            cb[i] = gb[i] ? best[bb[i]] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < kE; ++i) {
+            wave_min_commit(best, aa[i], key[i], ga[i] && key[i] < ca[i]);
+            wave_min_commit(best, bb[i], key[i], gb[i] && key[i] < cb[i]);
+        }
+    }
+    __syncthreads();
+    if (base >= 0) win_flush(s_min, best, base, base + kWinSlots < n ? base + kWinSlots : n);
+    if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrRange);
+    if (tid == 0 && hot >= 0 && s_hot != kKeyMax) atomic_min_key(&best[hot], s_hot);
 }
 
 // ------------------------------------------------------------------ hook
@@ -625,6 +762,23 @@ __global__ __launch_bounds__(kBlock) void k_compact_flags(View g, const int32_t*
     __shared__ unsigned long long s_min[kTab];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t mr = g.len;
+    // A tile's ends and weights are loaded while the previous tile is being
+    // decided (issued after its label gathers, so waiting for those does not
+    // wait for them); past the end (also past the last tile) a lane reads
+    // position mr - 1 and drops it.
+    int32_t na[kIt], nb[kIt];
+    uint32_t nw[kIt];
+    auto load_tile = [&](uint32_t t) {
+        const int64_t e0 = (int64_t)t * kRelabelTile + (int64_t)wave * (kWave * kIt) + lane;
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            const int64_t e = e0 + k * kWave < mr ? e0 + k * kWave : mr - 1;
+            load_ends<IN>(g, e, na[k], nb[k]);
+            nw[k] = 0;
+            if constexpr (DEDUP != kDedupNone) nw[k] = g.w[e];
+        }
+    };
+    if (blockIdx.x < ntiles) load_tile(blockIdx.x);
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t e0 = (int64_t)tile * kRelabelTile + (int64_t)wave * (kWave * kIt) + lane;
         if constexpr (DEDUP == kDedupLocal) {
@@ -635,26 +789,17 @@ __global__ __launch_bounds__(kBlock) void k_compact_flags(View g, const int32_t*
         }
         int32_t a[kIt], b[kIt];
         uint32_t wt[kIt];
-#pragma unroll
-        for (int k = 0; k < kIt; ++k) {
-            const int64_t e = e0 + k * kWave;
-            a[k] = b[k] = 0;
-            wt[k] = 0;
-            if (e < mr) {
-                load_ends<IN>(g, e, a[k], b[k]);
-                if constexpr (DEDUP != kDedupNone) wt[k] = g.w[e];
-            }
-        }
         bool keep[kIt];
 #pragma unroll
         for (int k = 0; k < kIt; ++k) {
-            keep[k] = false;
-            if (a[k] != b[k]) {          // also false past the end (both 0)
-                a[k] = M[a[k]];
-                b[k] = M[b[k]];
-                keep[k] = a[k] != b[k];
-            }
+            keep[k] = e0 + k * kWave < mr && na[k] != nb[k];
+            a[k] = M[keep[k] ? na[k] : 0];
+            b[k] = M[keep[k] ? nb[k] : 0];
+            wt[k] = nw[k];
         }
+        load_tile(tile + gridDim.x);     // unconditional: no branch for the waits to merge over
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) keep[k] = keep[k] && a[k] != b[k];
         if constexpr (DEDUP == kDedupExact) {
 #pragma unroll
             for (int k = 0; k < kIt; ++k) {
@@ -775,6 +920,150 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(View g, const int32_
     }
 }
 
+// k_compact_scatter for graphs with id locality: the kept edges' new labels
+// stay close together along the positions, so the next round's minima are
+// taken in a sliding LDS window of labels (as in k_minedge_win) instead of one
+// global update per endpoint.  A workgroup of 16 waves handles four
+// consecutive flag tiles per step (waves 4j..4j+3 tile j, each as in
+// k_compact_scatter) over a contiguous run of steps.  Same output.
+constexpr int kSwThreads = 1024;
+constexpr int kSwTiles = kSwThreads / kBlock;                 // flag tiles per step
+constexpr int64_t kSwSlots = 8192;                            // 64 KiB of minima
+constexpr int64_t kSwSlack = kSwSlots / 8;
+
+template <int IN>
+__global__ __launch_bounds__(kSwThreads) void k_compact_scatter_win(
+    View g, const int32_t* __restrict__ M, const uint64_t* __restrict__ flags,
+    const uint64_t* __restrict__ off, EdgeSoA out, uint64_t* __restrict__ best_next,
+    uint32_t ntiles, int64_t nn, int64_t steps_per_block) {
+    constexpr int kIt = kRelabelItems;
+    __shared__ unsigned long long s_min[kSwSlots];
+    __shared__ uint32_t s_wave[kSwThreads / kWave];
+    __shared__ int64_t s_base;
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave, lane = tid % kWave;
+    const int sub = wave / (kBlock / kWave), wv = wave % (kBlock / kWave);
+    for (int i = tid; i < kSwSlots; i += kSwThreads) s_min[i] = kKeyMax;
+    const int64_t nsteps = ((int64_t)ntiles + kSwTiles - 1) / kSwTiles;
+    const int64_t s0 = (int64_t)blockIdx.x * steps_per_block;
+    const int64_t s1 = s0 + steps_per_block < nsteps ? s0 + steps_per_block : nsteps;
+    int64_t base = -1;            // label window [base, base + kSwSlots), uniform
+    for (int64_t step = s0; step < s1; ++step) {
+        if (tid == 0) {           // below the label of the step's first position
+            const int64_t p = step * kSwTiles * kRelabelTile;
+            int32_t a, b;
+            load_ends<IN>(g, p, a, b);
+            const int32_t la = M[a];
+            int64_t nb = la >= 0 && la < nn ? (int64_t)la - kSwSlack : base;
+            if (nb < 0) nb = 0;
+            if (nb < base) nb = base;
+            s_base = nb;
+        }
+        __syncthreads();          // the last step's LDS updates are done; s_base is set
+        const int64_t nb = s_base;
+        if (base >= 0 && nb > base) {
+            const int64_t hi = nb < base + kSwSlots ? nb : base + kSwSlots;
+            for (int64_t x = base + tid; x < hi; x += kSwThreads) {
+                const int slot = (int)(x & (kSwSlots - 1));
+                const uint64_t k = s_min[slot];
+                if (k != kKeyMax) {
+                    s_min[slot] = kKeyMax;
+                    atomic_min_key(&best_next[x], k);
+                }
+            }
+        }
+        base = nb;
+        const int64_t tile = step * kSwTiles + sub;
+        const bool live = tile < (int64_t)ntiles;
+        const int64_t w0 = tile * kTileWords + wv * kIt;
+        const int64_t e0 = tile * kRelabelTile + (int64_t)wv * (kWave * kIt) + lane;
+        uint64_t mk[kIt];
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            mk[k] = live ? flags[w0 + k] : 0;
+            c += __popcll(mk[k]);
+        }
+        if (lane == 0) s_wave[wave] = c;
+        __syncthreads();          // the slots left behind are clear; the counts are in
+        uint32_t woff = 0;
+#pragma unroll
+        for (int i = 0; i < kBlock / kWave; ++i)
+            if (i < wv) woff += s_wave[sub * (kBlock / kWave) + i];
+        int32_t a[kIt], b[kIt];
+        uint32_t wt[kIt], id[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            a[k] = b[k] = 0;
+            wt[k] = id[k] = 0;
+            if ((mk[k] >> lane) & 1) {
+                const int64_t e = e0 + k * kWave;
+                load_ends<IN>(g, e, a[k], b[k]);
+                wt[k] = g.w[e];
+                id[k] = edge_id<IN>(g, e);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            if ((mk[k] >> lane) & 1) {
+                a[k] = M[a[k]];
+                b[k] = M[b[k]];
+            }
+        }
+        uint64_t o = (live ? off[tile] : 0) + woff;
+        uint64_t key[kIt];
+        bool ga[kIt], gb[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            const bool kept = (mk[k] >> lane) & 1;
+            const uint64_t d = o + lanes_below(mk[k]);
+            key[k] = ((uint64_t)wt[k] << 32) | d;
+            ga[k] = gb[k] = false;
+            if (kept) {
+                out.u[d] = a[k];
+                out.v[d] = b[k];
+                out.w[d] = wt[k];
+                out.id[d] = id[k];
+                const uint64_t oa = (uint64_t)((int64_t)a[k] - base);
+                const uint64_t ob = (uint64_t)((int64_t)b[k] - base);
+                ga[k] = oa >= (uint64_t)kSwSlots;
+                gb[k] = ob >= (uint64_t)kSwSlots;
+                if (!ga[k]) {
+                    unsigned long long* p = &s_min[a[k] & (kSwSlots - 1)];
+                    if (key[k] < *p) atomicMin(p, (unsigned long long)key[k]);
+                }
+                if (!gb[k]) {
+                    unsigned long long* p = &s_min[b[k] & (kSwSlots - 1)];
+                    if (key[k] < *p) atomicMin(p, (unsigned long long)key[k]);
+                }
+            }
+            if (!ga[k]) a[k] = 0;
+            if (!gb[k]) b[k] = 0;
+            o += __popcll(mk[k]);
+        }
+        // outside the window: every read first, then the atomics that still lower
+        uint64_t ca[kIt], cb[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            ca[k] = ga[k] ? best_next[a[k]] : 0;
+            cb[k] = gb[k] ? best_next[b[k]] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            wave_min_commit(best_next, a[k], key[k], ga[k] && key[k] < ca[k]);
+            wave_min_commit(best_next, b[k], key[k], gb[k] && key[k] < cb[k]);
+        }
+    }
+    __syncthreads();
+    if (base >= 0) {
+        const int64_t hi = base + kSwSlots < nn ? base + kSwSlots : nn;
+        for (int64_t x = base + tid; x < hi; x += kSwThreads) {
+            const uint64_t k = s_min[x & (kSwSlots - 1)];
+            if (k != kKeyMax) atomic_min_key(&best_next[x], k);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline unsigned grid_for(int64_t n, unsigned cap = 2048) {
@@ -795,11 +1084,48 @@ void launch_scan_prep(uint64_t* status, int64_t ntiles, Ctrl* ctrl, int round_be
     hipLaunchKernelGGL(k_scan_prep, dim3(grid_for(ntiles, 256)), dim3(kBlock), 0, s, status,
                        ntiles, ctrl, round_begin);
 }
+// Compute units of the current device (cached per device).
+static int64_t device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int c = cache[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            c <= 0)
+            c = 256;
+        cache[dev].store(c, std::memory_order_relaxed);
+    }
+    return c;
+}
+
+// Workgroups of `kernel` that fit on the device at once.
+template <typename K>
+static int64_t resident_blocks(K kernel, int threads) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
+        per < 1)
+        per = 1;
+    return per * device_cus();
+}
+
 void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
-                       int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, hipStream_t s) {
+                       int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, bool local,
+                       hipStream_t s) {
     if (m <= 0) return;
     if (hot >= n) hot = -1;
     const bool aligned = (((uintptr_t)u | (uintptr_t)v | (uintptr_t)w) & 15) == 0;
+    if (local && aligned && m >= kWinTile) {
+        // as many workgroups as fit at once (one per CU: the window takes
+        // 128 KiB of LDS), each on a contiguous run of tiles
+        const int64_t ntiles = (m + kWinTile - 1) / kWinTile;
+        const int64_t cap = resident_blocks(k_minedge_win, kWinThreads);
+        const int64_t grid = ntiles < cap ? ntiles : cap;
+        const int64_t per = (ntiles + grid - 1) / grid;
+        hipLaunchKernelGGL(k_minedge_win, dim3((unsigned)((ntiles + per - 1) / per)),
+                           dim3(kWinThreads), 0, s, u, v, w, m, n, best, ctrl, hot, per);
+        return;
+    }
     if (aligned)
         hipLaunchKernelGGL(k_minedge_r0<4>, dim3(grid_for((m + 3) / 4)), dim3(kBlock), 0, s, u,
                            v, w, m, n, best, ctrl, hot);
@@ -1032,9 +1358,9 @@ static void launch_compact_flags(int in_mode, const View& g, const int32_t* M, u
 }
 
 void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
-                    uint64_t* best_next, uint64_t* flags, uint64_t* cnt, uint64_t* bsum,
-                    Ctrl* ctrl, int dedup, const uint64_t* dpair, const uint64_t* dmin,
-                    int64_t dslots, hipStream_t s) {
+                    uint64_t* best_next, int64_t nn, uint64_t* flags, uint64_t* cnt,
+                    uint64_t* bsum, Ctrl* ctrl, int dedup, const uint64_t* dpair,
+                    const uint64_t* dmin, int64_t dslots, bool local, hipStream_t s) {
     if (g.len <= 0) return;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     if (dedup == kDedupExact && dslots > 0)
@@ -1044,6 +1370,21 @@ void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
     else
         launch_compact_flags<kDedupNone>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
     launch_scan_tiles(cnt, nt, bsum, &ctrl->m_next, s);
+    if (local && nt >= 4 * (uint32_t)kSwTiles) {
+        // as many workgroups as fit at once, a contiguous run of steps each
+        const int64_t nsteps = ((int64_t)nt + kSwTiles - 1) / kSwTiles;
+        const int64_t cap = resident_blocks(k_compact_scatter_win<kCompact>, kSwThreads);
+        const int64_t grid = nsteps < cap ? nsteps : cap;
+        const int64_t per = (nsteps + grid - 1) / grid;
+        const dim3 gw((unsigned)((nsteps + per - 1) / per)), bw(kSwThreads);
+        switch (in_mode) {
+            case kOrig: hipLaunchKernelGGL(k_compact_scatter_win<kOrig>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per); break;
+            case kFull32: hipLaunchKernelGGL(k_compact_scatter_win<kFull32>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per); break;
+            case kFull16: hipLaunchKernelGGL(k_compact_scatter_win<kFull16>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per); break;
+            default: hipLaunchKernelGGL(k_compact_scatter_win<kCompact>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per); break;
+        }
+        return;
+    }
     const dim3 gr(nt < kCompactGrid ? nt : kCompactGrid), bl(kBlock);
     switch (in_mode) {
         case kOrig: hipLaunchKernelGGL((k_compact_scatter<kOrig, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt); break;

@@ -145,7 +145,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         launch_fill_u64(B.best[cur], nr, kKeyMax, s);
         prof_end(h, s, 8.0 * nr);
         h = prof_begin(K_MINEDGE_R0, s);
-        launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, hot, s);
+        launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, hot, local, s);
         prof_end(h, s, 12.0 * view.len + 8.0 * nv);
     }
     HIP_TRY(hipGetLastError());
@@ -298,8 +298,8 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
                 prof_end(h, s, 16.0 * B.dslots + view_read_bytes(mode) * view.len + 8.0 * m_live);
             }
             h = prof_begin(K_COMPACT, s);
-            launch_compact(mode, view, M, out, B.best[cur ^ 1], B.cflags, B.status, B.cbsum, dc,
-                           dedup, B.dpair, B.dmin, B.dslots, s);
+            launch_compact(mode, view, M, out, B.best[cur ^ 1], nn, B.cflags, B.status, B.cbsum,
+                           dc, dedup, B.dpair, B.dmin, B.dslots, local, s);
             prof_end(h, s, view_read_bytes(mode) * view.len + 8.0 * m_live);
             next.u = out.u; next.v = out.v; next.w = out.w; next.id = out.id; next.p16 = nullptr;
             next_mode = kCompact;

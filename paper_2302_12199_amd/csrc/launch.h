@@ -10,8 +10,11 @@ void launch_fill_u64(uint64_t* p, int64_t n, uint64_t val, hipStream_t s);
 void launch_zero_bytes(uint8_t* p, int64_t n, hipStream_t s);
 void launch_scan_prep(uint64_t* status, int64_t ntiles, Ctrl* ctrl, int round_begin,
                       hipStream_t s);
+// local: the edges join nearby ids (locality sample); then the minima of a
+// sliding window of ids are taken in LDS.
 void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
-                       int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, hipStream_t s);
+                       int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, bool local,
+                       hipStream_t s);
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
                  int32_t* parent, uint8_t* mask, Ctrl* ctrl, hipStream_t s);
 void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s);
@@ -40,10 +43,12 @@ void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_
 // (dpair, dmin; dslots entries, filled by launch_dedup_insert) holds for its pair.
 // flags: one bit per position (tiles of 2048 positions); cnt: a word per tile;
 // bsum: kScanTop words.  ctrl->m_next receives the number of kept edges.
+// best_next holds nn entries; local: the graph has id locality (the next
+// round's minima are then taken in a sliding LDS window of labels).
 void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
-                    uint64_t* best_next, uint64_t* flags, uint64_t* cnt, uint64_t* bsum,
-                    Ctrl* ctrl, int dedup, const uint64_t* dpair, const uint64_t* dmin,
-                    int64_t dslots, hipStream_t s);
+                    uint64_t* best_next, int64_t nn, uint64_t* flags, uint64_t* cnt,
+                    uint64_t* bsum, Ctrl* ctrl, int dedup, const uint64_t* dpair,
+                    const uint64_t* dmin, int64_t dslots, bool local, hipStream_t s);
 // filter.hip: exclusive scan of per-tile counts in place (nt <= 2^21 tiles;
 // bsum holds kScanTop chunk sums), the total to *total.
 void launch_scan_tiles(uint64_t* cnt, uint32_t nt, uint64_t* bsum, uint64_t* total,

@@ -104,6 +104,53 @@ def test_midsize_families_with_rounds(kind, size):
     check_against_oracle(u, v, w, n, rounds=True)
 
 
+@pytest.mark.parametrize("order", ["sorted", "shuffled", "reversed", "swapped", "long_range",
+                                   "ragged", "small_n"])
+def test_local_graph_edge_orders(order):
+    """Graphs that pass the locality sample take round 0's lightest edges in a
+    sliding LDS window over the ids; edges in any order, or far outside the
+    window, must give the same forest (only the speed depends on the order)."""
+    banner(f"locality window, edge order {order}")
+    rng = np.random.default_rng(41)
+    if order == "small_n":      # fewer vertices than the window, several tiles
+        n = 120 * 100
+        u, v, w = graphgen.grid(120, 100, 0.9, 1, 1, 255, seed=5)
+    else:
+        n = 90001
+        u, v, w = graphgen.rgg2d(n, graphgen.rgg_radius(n, 8), 1e6, seed=4)
+    if order == "shuffled":
+        p = rng.permutation(len(u))
+        u, v, w = u[p], v[p], w[p]
+    elif order == "reversed":
+        u, v, w = u[::-1].copy(), v[::-1].copy(), w[::-1].copy()
+    elif order == "swapped":    # every other edge stored as (v, u)
+        s = np.arange(len(u)) % 2 == 1
+        u, v = np.where(s, v, u).astype(np.int32), np.where(s, u, v).astype(np.int32)
+    elif order == "long_range":  # 2 % of the edges join random far-apart ids
+        k = len(u) // 50
+        at = np.sort(rng.choice(len(u), k, replace=False))
+        u = u.copy()
+        v = v.copy()
+        v[at] = rng.integers(0, n, k).astype(np.int32)
+    elif order == "ragged":     # not a multiple of the vector width or the tile
+        u, v, w = u[:len(u) - 8192 - 3], v[:len(v) - 8192 - 3], w[:len(w) - 8192 - 3]
+    assert len(u) >= 8192
+    check_against_oracle(u, v, w, n, rounds=True)
+
+
+def test_out_of_range_id_in_a_local_graph():
+    import paper_2302_12199_amd as msf
+    banner("out of range id in a local graph")
+    n = 90001
+    u, v, w = graphgen.rgg2d(n, graphgen.rgg_radius(n, 8), 1e6, seed=4)
+    for at, bad in ((len(u) // 2, n), (len(u) - 1, 2**31 - 1), (5, -1)):
+        uu = u.copy()
+        uu[at] = bad
+        with pytest.raises(msf.MSFError) as e:
+            gpu_msf(uu, v, w, n)
+        assert e.value.status == msf.ERANGE
+
+
 def test_config_gnm_2p16_2p20():
     banner("GNM n=2^16 m=2^20 (oracle live)")
     u, v, w, n = graphgen.workload("gnm_n2^16_m2^20")
