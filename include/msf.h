@@ -112,7 +112,11 @@ typedef struct msf_options {
                                 set has fewer edges than this hands it back to its
                                 caller, which filters it again with its own heavy
                                 edges (Sec. VI-C, further remarks); 0 = off */
-    int32_t reserved[4];     /* must be zero */
+    int32_t tail_threshold;  /* the single-workgroup tail takes over the remaining rounds
+                                (Sec. II-C's rounds, on the lightest edge of every vertex
+                                pair) once at most this many component labels are left;
+                                0 = 1024 (the largest), 1..1024; 1 = never */
+    int32_t reserved[3];     /* must be zero */
 } msf_options;
 
 #define MSF_MAX_TRACE 64

@@ -32,7 +32,8 @@ class Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("sparse_degree", ctypes.c_int32),
                 ("min_split_edges", ctypes.c_int32), ("round0", ctypes.c_int32),
                 ("dedup_policy", ctypes.c_int32), ("split_retries", ctypes.c_int32),
-                ("defer_edges", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("defer_edges", ctypes.c_int32), ("tail_threshold", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -157,8 +158,9 @@ def library():
 
 def make_options(algo="boruvka", pivot="median", quantile=0.5, seed=1, sample_size=0,
                  sparse_degree=0, min_split_edges=0, round0="auto", dedup="auto",
-                 split_retries=0, defer_edges=0):
+                 split_retries=0, defer_edges=0, tail_threshold=0):
     o = Options()
+    o.tail_threshold = int(tail_threshold)
     o.split_retries = int(split_retries)
     o.defer_edges = int(defer_edges)
     o.round0 = ROUND0[round0] if isinstance(round0, str) else int(round0)

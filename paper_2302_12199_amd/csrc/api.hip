@@ -168,7 +168,8 @@ int check_args(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
             return MSF_EINVAL;
         if (opt->split_retries < 0 || opt->split_retries > 64 || opt->defer_edges < 0)
             return MSF_EINVAL;
-        for (int i = 0; i < 4; ++i)
+        if (opt->tail_threshold < 0 || opt->tail_threshold > kTailMax) return MSF_EINVAL;
+        for (int i = 0; i < 3; ++i)
             if (opt->reserved[i]) return MSF_EINVAL;
     }
     return MSF_OK;
@@ -197,6 +198,7 @@ int solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int6
         engine_carve(ws, m, n, &B, round0_buckets(opt), exact_dedup(opt));
         B.round0 = opt ? opt->round0 : MSF_ROUND0_AUTO;
         B.dedup = opt ? opt->dedup_policy : MSF_DEDUP_AUTO;
+        B.tail = opt && opt->tail_threshold ? opt->tail_threshold : kTailMax;
         launch_zero_bytes((uint8_t*)B.ctrl, sizeof(Ctrl), s);
         int h = prof_begin(K_FILL, s);
         launch_zero_bytes(mask, m, s);

@@ -159,6 +159,9 @@ constexpr int64_t kWinTile = (int64_t)kWinThreads * 4 * kWinGroups;   // 8192 ed
 constexpr int64_t kWinSlots = 16384;                            // 128 KiB of minima
 constexpr int64_t kWinSlack = kWinSlots / 8;                    // room below a tile's first id
 
+// Writes the window's minima of ids [lo, hi) out (and clears them): one
+// atomic per id that has a minimum, consecutive lanes on consecutive ids.  No
+// read first: nearly every id is written out once.
 __device__ __forceinline__ void win_flush(unsigned long long* s_min, uint64_t* best,
                                           int64_t lo, int64_t hi) {
     for (int64_t x = lo + threadIdx.x; x < hi; x += kWinThreads) {
@@ -166,7 +169,38 @@ __device__ __forceinline__ void win_flush(unsigned long long* s_min, uint64_t* b
         const uint64_t k = s_min[slot];
         if (k != kKeyMax) {
             s_min[slot] = kKeyMax;
-            atomic_min_key(&best[x], k);
+            atomicMin((unsigned long long*)&best[x], (unsigned long long)k);
+        }
+    }
+}
+
+// The lane's 4-edge groups of tile t (positions past m read position m - 1,
+// which the caller drops): 16-byte loads, the arrays 16-byte aligned.
+__device__ __forceinline__ void win_load(const int32_t* __restrict__ u,
+                                         const int32_t* __restrict__ v,
+                                         const uint32_t* __restrict__ w, int64_t m, int64_t t,
+                                         int32_t (&aa)[kWinGroups * 4],
+                                         int32_t (&bb)[kWinGroups * 4],
+                                         uint32_t (&ww)[kWinGroups * 4]) {
+    const int64_t ng = m / 4;   // whole groups
+#pragma unroll
+    for (int j = 0; j < kWinGroups; ++j) {
+        const int64_t g = t * (kWinTile / 4) + (int64_t)j * kWinThreads + threadIdx.x;
+        if (g < ng) {
+            const int4 a4 = reinterpret_cast<const int4*>(u)[g];
+            const int4 b4 = reinterpret_cast<const int4*>(v)[g];
+            const uint4 w4 = reinterpret_cast<const uint4*>(w)[g];
+            aa[j * 4 + 0] = a4.x; aa[j * 4 + 1] = a4.y; aa[j * 4 + 2] = a4.z; aa[j * 4 + 3] = a4.w;
+            bb[j * 4 + 0] = b4.x; bb[j * 4 + 1] = b4.y; bb[j * 4 + 2] = b4.z; bb[j * 4 + 3] = b4.w;
+            ww[j * 4 + 0] = w4.x; ww[j * 4 + 1] = w4.y; ww[j * 4 + 2] = w4.z; ww[j * 4 + 3] = w4.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t e = g * 4 + k < m ? g * 4 + k : m - 1;
+                aa[j * 4 + k] = u[e];
+                bb[j * 4 + k] = v[e];
+                ww[j * 4 + k] = w[e];
+            }
         }
     }
 }
@@ -186,45 +220,32 @@ __global__ __launch_bounds__(kWinThreads) void k_minedge_win(
     const int64_t t1 = t0 + tiles_per_block < ntiles ? t0 + tiles_per_block : ntiles;
     int64_t base = -1;            // window [base, base + kWinSlots), the same in every thread
     bool bad = false;
+    constexpr int kE = kWinGroups * 4;
+    // the next tile is loaded while this one is decided
+    int32_t na[kE], nb[kE];
+    uint32_t nw[kE];
+    if (t0 < t1) win_load(u, v, w, m, t0, na, nb, nw);
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t e0 = t * kWinTile;
-        if (tid == 0) {
-            const uint32_t a0 = (uint32_t)u[e0], b0 = (uint32_t)v[e0];
+        int32_t aa[kE], bb[kE];
+        uint32_t ww[kE];
+#pragma unroll
+        for (int i = 0; i < kE; ++i) { aa[i] = na[i]; bb[i] = nb[i]; ww[i] = nw[i]; }
+        win_load(u, v, w, m, t + 1 < t1 ? t + 1 : t, na, nb, nw);
+        if (tid == 0) {           // thread 0's first edge is the tile's first
+            const uint32_t a0 = (uint32_t)aa[0], b0 = (uint32_t)bb[0];
             const int64_t f = (int64_t)(a0 < b0 ? a0 : b0);
-            int64_t nb = f < (int64_t)n ? f - kWinSlack : base;
-            if (nb < 0) nb = 0;
-            if (nb < base) nb = base;
-            s_base = nb;
+            int64_t nbase = f < (int64_t)n ? f - kWinSlack : base;
+            if (nbase < 0) nbase = 0;
+            if (nbase < base) nbase = base;
+            s_base = nbase;
         }
         __syncthreads();          // the last tile's LDS updates are done; s_base is set
-        const int64_t nb = s_base;
-        if (base >= 0 && nb > base)
-            win_flush(s_min, best, base, nb < base + kWinSlots ? nb : base + kWinSlots);
-        base = nb;
+        const int64_t nbase = s_base;
+        if (base >= 0 && nbase > base)
+            win_flush(s_min, best, base, nbase < base + kWinSlots ? nbase : base + kWinSlots);
+        base = nbase;
         __syncthreads();          // the slots left behind are clear before they are reused
-        int32_t aa[kWinGroups * 4], bb[kWinGroups * 4];
-        uint32_t ww[kWinGroups * 4];
-#pragma unroll
-        for (int j = 0; j < kWinGroups; ++j) {
-            const int64_t g = e0 / 4 + (int64_t)j * kWinThreads + tid;
-            if (g * 4 + 3 < m) {
-                const int4 a4 = reinterpret_cast<const int4*>(u)[g];
-                const int4 b4 = reinterpret_cast<const int4*>(v)[g];
-                const uint4 w4 = reinterpret_cast<const uint4*>(w)[g];
-                aa[j * 4 + 0] = a4.x; aa[j * 4 + 1] = a4.y; aa[j * 4 + 2] = a4.z; aa[j * 4 + 3] = a4.w;
-                bb[j * 4 + 0] = b4.x; bb[j * 4 + 1] = b4.y; bb[j * 4 + 2] = b4.z; bb[j * 4 + 3] = b4.w;
-                ww[j * 4 + 0] = w4.x; ww[j * 4 + 1] = w4.y; ww[j * 4 + 2] = w4.z; ww[j * 4 + 3] = w4.w;
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int64_t e = g * 4 + k;
-                    aa[j * 4 + k] = bb[j * 4 + k] = 0;
-                    ww[j * 4 + k] = 0;
-                    if (e < m) { aa[j * 4 + k] = u[e]; bb[j * 4 + k] = v[e]; ww[j * 4 + k] = w[e]; }
-                }
-            }
-        }
-        constexpr int kE = kWinGroups * 4;
         uint64_t key[kE];
         bool ga[kE], gb[kE];      // endpoint takes the global path
 #pragma unroll
@@ -931,6 +952,30 @@ constexpr int kSwTiles = kSwThreads / kBlock;                 // flag tiles per 
 constexpr int64_t kSwSlots = 8192;                            // 64 KiB of minima
 constexpr int64_t kSwSlack = kSwSlots / 8;
 
+// One step's flag words and (every position, past the end position
+// len - 1) ends, weights and ids of the calling lane, for k_compact_scatter_win.
+template <int IN>
+__device__ __forceinline__ void sw_load(const View& g, const uint64_t* __restrict__ flags,
+                                        uint32_t ntiles, int64_t step, int sub, int wv, int lane,
+                                        uint64_t (&mk)[kRelabelItems],
+                                        int32_t (&a)[kRelabelItems], int32_t (&b)[kRelabelItems],
+                                        uint32_t (&wt)[kRelabelItems],
+                                        uint32_t (&id)[kRelabelItems]) {
+    constexpr int kIt = kRelabelItems;
+    const int64_t tile = step * kSwTiles + sub;
+    const bool live = tile < (int64_t)ntiles;
+    const int64_t w0 = tile * kTileWords + wv * kIt;
+    const int64_t e0 = tile * kRelabelTile + (int64_t)wv * (kWave * kIt) + lane;
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        mk[k] = live ? flags[w0 + k] : 0;
+        const int64_t e = e0 + k * kWave < g.len ? e0 + k * kWave : g.len - 1;
+        load_ends<IN>(g, e, a[k], b[k]);
+        wt[k] = g.w[e];
+        id[k] = edge_id<IN>(g, e);
+    }
+}
+
 template <int IN>
 __global__ __launch_bounds__(kSwThreads) void k_compact_scatter_win(
     View g, const int32_t* __restrict__ M, const uint64_t* __restrict__ flags,
@@ -941,76 +986,67 @@ __global__ __launch_bounds__(kSwThreads) void k_compact_scatter_win(
     __shared__ uint32_t s_wave[kSwThreads / kWave];
     __shared__ int64_t s_base;
     const int tid = threadIdx.x;
-    const int wave = tid / kWave, lane = tid % kWave;
+    // the wave index as a wave-uniform value: the flag words become scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
     const int sub = wave / (kBlock / kWave), wv = wave % (kBlock / kWave);
     for (int i = tid; i < kSwSlots; i += kSwThreads) s_min[i] = kKeyMax;
     const int64_t nsteps = ((int64_t)ntiles + kSwTiles - 1) / kSwTiles;
     const int64_t s0 = (int64_t)blockIdx.x * steps_per_block;
     const int64_t s1 = s0 + steps_per_block < nsteps ? s0 + steps_per_block : nsteps;
     int64_t base = -1;            // label window [base, base + kSwSlots), uniform
+    // the next step is loaded while this one is decided (issued after this
+    // step's label gathers, so waiting for those does not wait for it)
+    uint64_t nmk[kIt];
+    int32_t na[kIt], nb[kIt];
+    uint32_t nw[kIt], nid[kIt];
+    if (s0 < s1) sw_load<IN>(g, flags, ntiles, s0, sub, wv, lane, nmk, na, nb, nw, nid);
     for (int64_t step = s0; step < s1; ++step) {
-        if (tid == 0) {           // below the label of the step's first position
-            const int64_t p = step * kSwTiles * kRelabelTile;
-            int32_t a, b;
-            load_ends<IN>(g, p, a, b);
-            const int32_t la = M[a];
-            int64_t nb = la >= 0 && la < nn ? (int64_t)la - kSwSlack : base;
-            if (nb < 0) nb = 0;
-            if (nb < base) nb = base;
-            s_base = nb;
+        const int64_t tile = step * kSwTiles + sub;
+        uint64_t mk[kIt];
+        int32_t a[kIt], b[kIt];
+        uint32_t wt[kIt], id[kIt];
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            mk[k] = nmk[k];
+            wt[k] = nw[k];
+            id[k] = nid[k];
+            c += __popcll(mk[k]);
+            // kept ends are relabelled; the others read M[0] (one request per
+            // wave), except thread 0's first, whose label places the window
+            const bool kept = (mk[k] >> lane) & 1;
+            a[k] = M[kept || (k == 0 && tid == 0) ? na[k] : 0];
+            b[k] = M[kept ? nb[k] : 0];
         }
-        __syncthreads();          // the last step's LDS updates are done; s_base is set
-        const int64_t nb = s_base;
-        if (base >= 0 && nb > base) {
-            const int64_t hi = nb < base + kSwSlots ? nb : base + kSwSlots;
+        sw_load<IN>(g, flags, ntiles, step + 1 < s1 ? step + 1 : step, sub, wv, lane, nmk, na, nb,
+                    nw, nid);
+        if (lane == 0) s_wave[wave] = c;
+        if (tid == 0) {           // below the label of the step's first position
+            int64_t nbase = a[0] >= 0 && a[0] < nn ? (int64_t)a[0] - kSwSlack : base;
+            if (nbase < 0) nbase = 0;
+            if (nbase < base) nbase = base;
+            s_base = nbase;
+        }
+        __syncthreads();          // the last step's LDS updates are done; counts and s_base set
+        const int64_t nbase = s_base;
+        if (base >= 0 && nbase > base) {
+            const int64_t hi = nbase < base + kSwSlots ? nbase : base + kSwSlots;
             for (int64_t x = base + tid; x < hi; x += kSwThreads) {
                 const int slot = (int)(x & (kSwSlots - 1));
                 const uint64_t k = s_min[slot];
                 if (k != kKeyMax) {
                     s_min[slot] = kKeyMax;
-                    atomic_min_key(&best_next[x], k);
+                    atomicMin((unsigned long long*)&best_next[x], (unsigned long long)k);
                 }
             }
         }
-        base = nb;
-        const int64_t tile = step * kSwTiles + sub;
-        const bool live = tile < (int64_t)ntiles;
-        const int64_t w0 = tile * kTileWords + wv * kIt;
-        const int64_t e0 = tile * kRelabelTile + (int64_t)wv * (kWave * kIt) + lane;
-        uint64_t mk[kIt];
-        uint32_t c = 0;
-#pragma unroll
-        for (int k = 0; k < kIt; ++k) {
-            mk[k] = live ? flags[w0 + k] : 0;
-            c += __popcll(mk[k]);
-        }
-        if (lane == 0) s_wave[wave] = c;
-        __syncthreads();          // the slots left behind are clear; the counts are in
+        base = nbase;
         uint32_t woff = 0;
 #pragma unroll
         for (int i = 0; i < kBlock / kWave; ++i)
             if (i < wv) woff += s_wave[sub * (kBlock / kWave) + i];
-        int32_t a[kIt], b[kIt];
-        uint32_t wt[kIt], id[kIt];
-#pragma unroll
-        for (int k = 0; k < kIt; ++k) {
-            a[k] = b[k] = 0;
-            wt[k] = id[k] = 0;
-            if ((mk[k] >> lane) & 1) {
-                const int64_t e = e0 + k * kWave;
-                load_ends<IN>(g, e, a[k], b[k]);
-                wt[k] = g.w[e];
-                id[k] = edge_id<IN>(g, e);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kIt; ++k) {
-            if ((mk[k] >> lane) & 1) {
-                a[k] = M[a[k]];
-                b[k] = M[b[k]];
-            }
-        }
-        uint64_t o = (live ? off[tile] : 0) + woff;
+        __syncthreads();          // the slots left behind are clear
+        uint64_t o = (tile < (int64_t)ntiles ? off[tile] : 0) + woff;
         uint64_t key[kIt];
         bool ga[kIt], gb[kIt];
 #pragma unroll
@@ -1059,7 +1095,7 @@ __global__ __launch_bounds__(kSwThreads) void k_compact_scatter_win(
         const int64_t hi = base + kSwSlots < nn ? base + kSwSlots : nn;
         for (int64_t x = base + tid; x < hi; x += kSwThreads) {
             const uint64_t k = s_min[x & (kSwSlots - 1)];
-            if (k != kKeyMax) atomic_min_key(&best_next[x], k);
+            if (k != kKeyMax) atomicMin((unsigned long long*)&best_next[x], (unsigned long long)k);
         }
     }
 }

@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_min(
     __shared__ uint32_t s_pre[kBucketThreads];   // batch run r0 + k starts at arc s_pre[k] of the batch
     __shared__ uint32_t s_rs[kBucketThreads];    // and at slot s_rs[k] of its tile block
     __shared__ uint64_t s_w[kBucketThreads / kWave];
-    const uint32_t bk = blockIdx.x;
+    const uint32_t bk = xcd_slot(blockIdx.x, gridDim.x);   // neighbouring buckets on one XCD
     const int tid = threadIdx.x;
     for (int i = tid; i < kBucketWidth; i += blockDim.x) s_best[i] = kKeyMax;
     const uint64_t xs0 = base[bk];
@@ -432,13 +432,16 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
     const bool has_bk = bk < (int)nb;
     const uint64_t bbase = has_bk ? base[bk] : 0;
     uint32_t mt_n = 0, of_n = 0;
-    if (has_bk && blockIdx.x < nt) {
-        mt_n = meta[(int64_t)blockIdx.x * nb + bk];
-        of_n = offt[(int64_t)blockIdx.x * nb + bk];
+    // neighbouring tiles read the two ends of shared label-run lines: they go
+    // to workgroups of one XCD (xcd_slot)
+    const uint32_t t0 = xcd_slot(blockIdx.x, gridDim.x);
+    if (has_bk && t0 < nt) {
+        mt_n = meta[(int64_t)t0 * nb + bk];
+        of_n = offt[(int64_t)t0 * nb + bk];
     }
     // tiles are taken grid-stride, so the live-edge count costs one atomic
     // per workgroup (same-address atomics queue at ~13 ns each)
-    for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (uint32_t t = t0; t < nt; t += gridDim.x) {
         const int64_t e0 = (int64_t)t << kBucketTileShift;
         const int64_t e1 = e0 + kBucketTile < m ? e0 + kBucketTile : m;
         if (has_bk) {

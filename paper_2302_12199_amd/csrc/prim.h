@@ -7,6 +7,17 @@ namespace msf {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Workgroups are handed to the XCDs in turn (id mod kXcds), each XCD with its
+// own L2.  xcd_slot renumbers the ids 0..G-1 so that the workgroups of one XCD
+// take consecutive slots: neighbouring tiles or buckets, which share the cache
+// lines at their boundaries, are then read through the same L2.  A bijection
+// on [0, G) whatever the real XCD count.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_slot(uint32_t i, uint32_t G) {
+    const uint32_t x = i % kXcds, r = i / kXcds;
+    return x * (G / kXcds) + (x < G % kXcds ? x : G % kXcds) + r;
+}
+
 // Number of set bits of `mask` in lanes below the calling lane.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

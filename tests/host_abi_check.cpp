@@ -27,14 +27,15 @@ int main() {
     CHECK(msf_compute(nullptr, (const int32_t*)F, (const uint32_t*)F, 3, 5, (uint8_t*)F, &total,
                       nullptr, 0, nullptr, nullptr, nullptr) == MSF_EINVAL);
     // options
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 7; ++k) {
         msf_options b = o;
         if (k == 0) b.algo = 7;
         if (k == 1) b.quantile = 2.f;
         if (k == 2) b.dedup_policy = 9;
         if (k == 3) b.split_retries = -1;
         if (k == 4) b.defer_edges = -5;
-        if (k == 5) b.reserved[3] = 1;
+        if (k == 5) b.reserved[2] = 1;
+        if (k == 6) b.tail_threshold = 2000;
         CHECK(msf_compute((const int32_t*)F, (const int32_t*)F, (const uint32_t*)F, 3, 5,
                           (uint8_t*)F, &total, nullptr, 0, nullptr, &b, nullptr) == MSF_EINVAL);
     }

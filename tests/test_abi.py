@@ -68,11 +68,12 @@ def test_rejects_null_pointers(msf):
 
 def test_rejects_bad_options(msf):
     for kw in [dict(algo=7), dict(pivot=9), dict(quantile=1.5), dict(quantile=float("nan")),
-               dict(sample_size=-1), dict(round0=3), dict(round0=-1)]:
+               dict(sample_size=-1), dict(round0=3), dict(round0=-1),
+               dict(tail_threshold=-1), dict(tail_threshold=1025)]:
         rc, _ = msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE, options=msf.make_options(**kw))
         assert rc == msf.EINVAL, kw
     o = msf.make_options()
-    o.reserved[3] = 1
+    o.reserved[2] = 1
     assert msf.compute_raw(FAKE, FAKE, FAKE, 10, 5, FAKE, options=o)[0] == msf.EINVAL
 
 

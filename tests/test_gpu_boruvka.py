@@ -151,6 +151,28 @@ def test_out_of_range_id_in_a_local_graph():
         assert e.value.status == msf.ERANGE
 
 
+@pytest.mark.parametrize("tail", [1, 2, 100, 1024])
+@pytest.mark.parametrize("kind", ["gnm", "grid", "rmat_filter"])
+def test_tail_threshold(kind, tail):
+    """The single-workgroup tail runs the same rounds (Sec. II-C) on the
+    lightest edge of each vertex pair, so where it takes over changes neither
+    the forest nor the per-round trace; 1 never uses it."""
+    banner(f"tail threshold {tail} on {kind}")
+    if kind == "gnm":
+        n = 1 << 14
+        u, v, w = graphgen.gnm(n, 8 * n + 11, 1, 2**31 - 1, seed=14)
+        check_against_oracle(u, v, w, n, rounds=True, tail_threshold=tail)
+    elif kind == "grid":
+        n = 301 * 277
+        u, v, w = graphgen.grid(301, 277, 0.8, 1, 1, 255, seed=3)
+        check_against_oracle(u, v, w, n, rounds=True, tail_threshold=tail)
+    else:
+        n = 1 << 16
+        u, v, w = graphgen.rmat(16, 32 * n, wlo=1, whi=2**31 - 1, seed=16)
+        check_against_oracle(u, v, w, n, algo="filter", min_split_edges=20000,
+                             tail_threshold=tail)
+
+
 def test_config_gnm_2p16_2p20():
     banner("GNM n=2^16 m=2^20 (oracle live)")
     u, v, w, n = graphgen.workload("gnm_n2^16_m2^20")
