@@ -114,8 +114,10 @@ typedef struct msf_options {
                                 edges (Sec. VI-C, further remarks); 0 = off */
     int32_t tail_threshold;  /* the single-workgroup tail takes over the remaining rounds
                                 (Sec. II-C's rounds, on the lightest edge of every vertex
-                                pair) once at most this many component labels are left;
-                                0 = 1024 (the largest), 1..1024; 1 = never */
+                                pair) once at most this many component labels are left,
+                                1..1024 (1 = never); 0 = automatic: at most 1024 labels
+                                and at most 65536 possible pairs (live edges or label
+                                pairs, whichever is fewer) */
     int32_t reserved[3];     /* must be zero */
 } msf_options;
 

@@ -198,7 +198,7 @@ int solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m, int6
         engine_carve(ws, m, n, &B, round0_buckets(opt), exact_dedup(opt));
         B.round0 = opt ? opt->round0 : MSF_ROUND0_AUTO;
         B.dedup = opt ? opt->dedup_policy : MSF_DEDUP_AUTO;
-        B.tail = opt && opt->tail_threshold ? opt->tail_threshold : kTailMax;
+        B.tail = opt ? opt->tail_threshold : 0;
         launch_zero_bytes((uint8_t*)B.ctrl, sizeof(Ctrl), s);
         int h = prof_begin(K_FILL, s);
         launch_zero_bytes(mask, m, s);

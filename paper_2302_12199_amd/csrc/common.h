@@ -46,6 +46,7 @@ struct Ctrl {
 };
 
 constexpr int kTailMax = 1024;              // vertices the single-workgroup tail handles
+constexpr int64_t kTailAutoPairs = 65536;   // automatic hand-over: at most this many pairs
 constexpr int kTailThreads = 1024;
 constexpr int kTailRoundsMax = 24;
 // Labels whose vertex pairs the pass before the tail keeps in LDS (128 * 127 / 2

@@ -31,7 +31,7 @@ struct EngineBuffers {
     BucketBuffers bk;     // bucketed round 0 (large graphs only)
     int round0;           // msf_round0: when round 0 runs by buckets
     int dedup;            // msf_dedup: parallel-edge removal in the compactions
-    int64_t tail;         // the tail takes over at <= tail labels (1..kTailMax)
+    int64_t tail;         // the tail takes over at <= tail labels (1..kTailMax); 0 = automatic
     int64_t ncap, mcap;
 };
 

@@ -84,7 +84,7 @@ size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool bucke
     else b.bk = BucketBuffers{};
     b.round0 = MSF_ROUND0_AUTO;
     b.dedup = MSF_DEDUP_AUTO;
-    b.tail = kTailMax;
+    b.tail = 0;
     b.ncap = n;
     b.mcap = m;
     if (B) *B = b;
@@ -208,11 +208,19 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         const int64_t nn = (int64_t)hc->n_next;
         // Before the bucketed relabelling pass: the round-1 labels on many
         // edge ends are renumbered first (their minima then stay in LDS).
-        if (bucketed && mode == kOrig && nn > B.tail)
+        // The single-workgroup tail takes over the next rounds once few labels
+        // are left and its pair list is short: automatically at <= kTailMax
+        // labels with at most kTailAutoPairs possible pairs (live edges or
+        // label pairs, whichever is fewer), else at the caller's threshold.
+        const int64_t max_pairs =
+            nn <= kTailMax ? std::min<int64_t>(m_live, nn * (nn - 1) / 2) : INT64_MAX;
+        const bool tail_next = B.tail > 0 ? nn <= B.tail
+                                          : nn <= kTailMax && max_pairs <= kTailAutoPairs;
+        if (bucketed && mode == kOrig && !tail_next)
             bucket_hot_first(B.bk, view.u, view.v, view.len, lab, nr, nn, s);
         // Before the tail: the labels of its vertices are renumbered hot first
         // (the pair pass keeps the pairs among the first ones in LDS).
-        const bool pre_tail_hot = nn <= B.tail && view.len >= kPreTailMinEdges;
+        const bool pre_tail_hot = tail_next && view.len >= kPreTailMinEdges;
         if (pre_tail_hot && nn > kPairHot)
             launch_hot_first_small(mode, view, cmap, lab, nr, nn, B.perm, &dc->aux[2], s);
         else if (pre_tail_hot)   // every pair fits the LDS table
@@ -247,7 +255,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         const bool aligned = ((((uintptr_t)view.u | (uintptr_t)view.v | (uintptr_t)view.w |
                                 (uintptr_t)view.p16 | (uintptr_t)view.id) & 15) == 0);
         if (nn <= 1) break;        // one component left: every remaining edge is a self-loop
-        if (nn <= B.tail && aligned) {
+        if (tail_next && aligned) {
             // Last pass keeps the lightest edge per vertex pair; one workgroup
             // then finishes all remaining rounds.
             const int64_t slots = nn * (nn - 1) / 2;

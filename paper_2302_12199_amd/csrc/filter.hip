@@ -976,7 +976,7 @@ int filter_solve(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t 
                               opt.dedup_policy == MSF_DEDUP_EXACT);
     C.B.round0 = opt.round0;
     C.B.dedup = opt.dedup_policy;
-    C.B.tail = opt.tail_threshold ? opt.tail_threshold : kTailMax;
+    C.B.tail = opt.tail_threshold;
     C.P = (int32_t*)(ws + off);
     off += align_up((size_t)(n > 0 ? n : 1) * 4);
     C.buf[0] = carve_buffer(ws + off, m);

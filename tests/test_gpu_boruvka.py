@@ -151,7 +151,7 @@ def test_out_of_range_id_in_a_local_graph():
         assert e.value.status == msf.ERANGE
 
 
-@pytest.mark.parametrize("tail", [1, 2, 100, 1024])
+@pytest.mark.parametrize("tail", [0, 1, 2, 100, 1024])
 @pytest.mark.parametrize("kind", ["gnm", "grid", "rmat_filter"])
 def test_tail_threshold(kind, tail):
     """The single-workgroup tail runs the same rounds (Sec. II-C) on the
