@@ -681,25 +681,27 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
 constexpr int kDedupSlots = 2 * kRelabelTile;
 constexpr uint32_t kCompactGrid = 4096;   // workgroups of the compaction passes (tiles grid-stride)
 
+template <uint32_t SLOTS = kDedupSlots>
 __device__ __forceinline__ uint32_t pair_slot(uint64_t pair) {
-    return (uint32_t)((pair * 0x9E3779B97F4A7C15ULL) >> 40) & (kDedupSlots - 1);
+    return (uint32_t)((pair * 0x9E3779B97F4A7C15ULL) >> 40) & (SLOTS - 1);
 }
 
 // Inserts `pair` (never kKeyMax) and min-reduces `key` into its entry; returns the slot.
 // Plain reads first: a slot, once taken, keeps its pair, and an entry's minimum
 // only falls, so a read showing the pair (or a minimum at most `key`) makes the
 // atomic unnecessary; most edges of a tile meet a pair already entered.
+template <uint32_t SLOTS = kDedupSlots>
 __device__ __forceinline__ uint32_t dedup_insert(unsigned long long* s_pair,
                                                  unsigned long long* s_min, uint64_t pair,
                                                  uint64_t key) {
-    uint32_t slot = pair_slot(pair);
-    for (int probe = 0; probe < kDedupSlots; ++probe) {
+    uint32_t slot = pair_slot<SLOTS>(pair);
+    for (uint32_t probe = 0; probe < SLOTS; ++probe) {
         unsigned long long cur = __hip_atomic_load(&s_pair[slot], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         if (cur == kKeyMax)
             cur = atomicCAS(&s_pair[slot], (unsigned long long)kKeyMax, (unsigned long long)pair);
         if (cur == kKeyMax || cur == pair) break;
-        slot = (slot + 1) & (kDedupSlots - 1);
+        slot = (slot + 1) & (SLOTS - 1);
     }
     if (key < __hip_atomic_load(&s_min[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
         atomicMin(&s_min[slot], (unsigned long long)key);
@@ -868,6 +870,98 @@ __global__ __launch_bounds__(kBlock) void k_compact_flags(View g, const int32_t*
             cnt[tile] = sum;
         }
         __syncthreads();                 // s_wave and the table are reused by the next tile
+    }
+}
+
+// k_compact_flags with the per-tile parallel-edge table (kDedupLocal) for
+// graphs with id locality: 16 waves decide four consecutive flag tiles per
+// step (waves 4j..4j+3 tile j, each as in k_compact_flags) against one shared
+// table of 8192 pairs in 128 KiB of LDS: twice the waves per CU of the
+// 2048-edge version (which two 64 KiB tables limit to 8) and four times the
+// edges over which a pair's lighter edge is found.  The table holds at most
+// one entry per edge of the step, so probing always ends.
+constexpr int kFwThreads = 1024;
+constexpr int kFwTiles = kFwThreads / kBlock;                  // flag tiles per step
+constexpr uint32_t kFwSlots = (uint32_t)kFwTiles * kRelabelTile;   // 8192
+
+template <int IN>
+__global__ __launch_bounds__(kFwThreads) void k_compact_flags_wide(
+    View g, const int32_t* __restrict__ M, uint64_t* __restrict__ flags,
+    uint64_t* __restrict__ cnt, uint32_t ntiles) {
+    constexpr int kIt = kRelabelItems;
+    __shared__ unsigned long long s_pair[kFwSlots];
+    __shared__ unsigned long long s_min[kFwSlots];
+    __shared__ uint32_t s_wave[kFwThreads / kWave];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    const int sub = wave / (kBlock / kWave), wv = wave % (kBlock / kWave);
+    const int64_t mr = g.len;
+    const int64_t nsteps = ((int64_t)ntiles + kFwTiles - 1) / kFwTiles;
+    // the next step's ends and weights load while this one is decided (past
+    // the end a lane reads position mr - 1 and drops it)
+    int32_t na[kIt], nb[kIt];
+    uint32_t nw[kIt];
+    auto load_step = [&](int64_t st) {
+        const int64_t e0 = (st * kFwTiles + sub) * kRelabelTile + (int64_t)wv * (kWave * kIt) + lane;
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            const int64_t e = e0 + k * kWave < mr ? e0 + k * kWave : mr - 1;
+            load_ends<IN>(g, e, na[k], nb[k]);
+            nw[k] = g.w[e];
+        }
+    };
+    if ((int64_t)blockIdx.x < nsteps) load_step(blockIdx.x);
+    for (int64_t step = blockIdx.x; step < nsteps; step += gridDim.x) {
+        const int64_t tile = step * kFwTiles + sub;
+        const int64_t e0 = tile * kRelabelTile + (int64_t)wv * (kWave * kIt) + lane;
+        for (uint32_t i = tid; i < kFwSlots; i += kFwThreads) {
+            s_pair[i] = kKeyMax;
+            s_min[i] = kKeyMax;
+        }
+        int32_t a[kIt], b[kIt];
+        uint32_t wt[kIt];
+        bool keep[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            keep[k] = e0 + k * kWave < mr && na[k] != nb[k];
+            a[k] = M[keep[k] ? na[k] : 0];
+            b[k] = M[keep[k] ? nb[k] : 0];
+            wt[k] = nw[k];
+        }
+        load_step(step + gridDim.x);     // unconditional: no branch for the waits to merge over
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) keep[k] = keep[k] && a[k] != b[k];
+        __syncthreads();                 // the table is clear
+        uint32_t slot[kIt];
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            slot[k] = 0;
+            if (keep[k]) {
+                const uint32_t lo = (uint32_t)(a[k] < b[k] ? a[k] : b[k]);
+                const uint32_t hi = (uint32_t)(a[k] < b[k] ? b[k] : a[k]);
+                const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
+                slot[k] = dedup_insert<kFwSlots>(s_pair, s_min, ((uint64_t)lo << 32) | hi, key);
+            }
+        }
+        __syncthreads();
+        uint32_t c = 0;
+        const int64_t w0 = tile * kTileWords + wv * kIt;
+#pragma unroll
+        for (int k = 0; k < kIt; ++k) {
+            const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)(e0 + k * kWave);
+            const bool kp = keep[k] && s_min[slot[k]] == key;
+            const uint64_t mk = __ballot(kp);
+            if (lane == 0 && tile < (int64_t)ntiles) flags[w0 + k] = mk;
+            c += __popcll(mk);
+        }
+        if (lane == 0) s_wave[wave] = c;
+        __syncthreads();
+        if (tid < kFwTiles && step * kFwTiles + tid < (int64_t)ntiles) {
+            uint32_t sum = 0;
+            for (int i = 0; i < kBlock / kWave; ++i) sum += s_wave[tid * (kBlock / kWave) + i];
+            cnt[step * kFwTiles + tid] = sum;
+        }
+        __syncthreads();                 // s_wave and the table are reused by the next step
     }
 }
 
@@ -1401,7 +1495,17 @@ void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     if (dedup == kDedupExact && dslots > 0)
         launch_compact_flags<kDedupExact>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
-    else if (dedup != kDedupNone)
+    else if (dedup != kDedupNone && local && nt >= 4 * (uint32_t)kFwTiles) {
+        const int64_t nsteps = ((int64_t)nt + kFwTiles - 1) / kFwTiles;
+        const int64_t cap = resident_blocks(k_compact_flags_wide<kCompact>, kFwThreads);
+        const dim3 gw((unsigned)(nsteps < cap ? nsteps : cap)), bw(kFwThreads);
+        switch (in_mode) {
+            case kOrig: hipLaunchKernelGGL(k_compact_flags_wide<kOrig>, gw, bw, 0, s, g, M, flags, cnt, nt); break;
+            case kFull32: hipLaunchKernelGGL(k_compact_flags_wide<kFull32>, gw, bw, 0, s, g, M, flags, cnt, nt); break;
+            case kFull16: hipLaunchKernelGGL(k_compact_flags_wide<kFull16>, gw, bw, 0, s, g, M, flags, cnt, nt); break;
+            default: hipLaunchKernelGGL(k_compact_flags_wide<kCompact>, gw, bw, 0, s, g, M, flags, cnt, nt); break;
+        }
+    } else if (dedup != kDedupNone)
         launch_compact_flags<kDedupLocal>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
     else
         launch_compact_flags<kDedupNone>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
