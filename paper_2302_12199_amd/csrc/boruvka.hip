@@ -1245,13 +1245,13 @@ void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, in
     if (m <= 0) return;
     if (hot >= n) hot = -1;
     const bool aligned = (((uintptr_t)u | (uintptr_t)v | (uintptr_t)w) & 15) == 0;
-    if (local && aligned && m >= kWinTile) {
-        // as many workgroups as fit at once (one per CU: the window takes
-        // 128 KiB of LDS), each on a contiguous run of tiles
-        const int64_t ntiles = (m + kWinTile - 1) / kWinTile;
-        const int64_t cap = resident_blocks(k_minedge_win, kWinThreads);
-        const int64_t grid = ntiles < cap ? ntiles : cap;
-        const int64_t per = (ntiles + grid - 1) / grid;
+    // the window needs a tile for every workgroup that fits at once (one per
+    // CU: the window takes 128 KiB of LDS); smaller graphs would leave most of
+    // the chip idle, and the grid-stride kernel below spreads them wider
+    const int64_t ntiles = (m + kWinTile - 1) / kWinTile;
+    const int64_t cap = local && aligned ? resident_blocks(k_minedge_win, kWinThreads) : 0;
+    if (local && aligned && ntiles >= cap) {
+        const int64_t per = (ntiles + cap - 1) / cap;   // a contiguous run of tiles each
         hipLaunchKernelGGL(k_minedge_win, dim3((unsigned)((ntiles + per - 1) / per)),
                            dim3(kWinThreads), 0, s, u, v, w, m, n, best, ctrl, hot, per);
         return;
@@ -1495,7 +1495,10 @@ void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     if (dedup == kDedupExact && dslots > 0)
         launch_compact_flags<kDedupExact>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
-    else if (dedup != kDedupNone && local && nt >= 4 * (uint32_t)kFwTiles) {
+    else if (dedup != kDedupNone && local &&
+             ((int64_t)nt + kFwTiles - 1) / kFwTiles >=
+                 resident_blocks(k_compact_flags_wide<kCompact>, kFwThreads)) {
+        // a step for every workgroup that fits at once, else the 256-thread kernel
         const int64_t nsteps = ((int64_t)nt + kFwTiles - 1) / kFwTiles;
         const int64_t cap = resident_blocks(k_compact_flags_wide<kCompact>, kFwThreads);
         const dim3 gw((unsigned)(nsteps < cap ? nsteps : cap)), bw(kFwThreads);
@@ -1510,12 +1513,12 @@ void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
     else
         launch_compact_flags<kDedupNone>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
     launch_scan_tiles(cnt, nt, bsum, &ctrl->m_next, s);
-    if (local && nt >= 4 * (uint32_t)kSwTiles) {
-        // as many workgroups as fit at once, a contiguous run of steps each
-        const int64_t nsteps = ((int64_t)nt + kSwTiles - 1) / kSwTiles;
-        const int64_t cap = resident_blocks(k_compact_scatter_win<kCompact>, kSwThreads);
-        const int64_t grid = nsteps < cap ? nsteps : cap;
-        const int64_t per = (nsteps + grid - 1) / grid;
+    const int64_t nsteps = ((int64_t)nt + kSwTiles - 1) / kSwTiles;
+    const int64_t cap = local ? resident_blocks(k_compact_scatter_win<kCompact>, kSwThreads) : 0;
+    if (local && nsteps >= cap) {
+        // a contiguous run of steps for each workgroup that fits at once (with
+        // fewer steps than that the 256-thread kernel spreads the work wider)
+        const int64_t per = (nsteps + cap - 1) / cap;
         const dim3 gw((unsigned)((nsteps + per - 1) / per)), bw(kSwThreads);
         switch (in_mode) {
             case kOrig: hipLaunchKernelGGL(k_compact_scatter_win<kOrig>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per); break;

@@ -112,11 +112,16 @@ def test_local_graph_edge_orders(order):
     window, must give the same forest (only the speed depends on the order)."""
     banner(f"locality window, edge order {order}")
     rng = np.random.default_rng(41)
-    if order == "small_n":      # fewer vertices than the window, several tiles
-        n = 120 * 100
-        u, v, w = graphgen.grid(120, 100, 0.9, 1, 1, 255, seed=5)
+    # the window kernels take graphs with a tile (8192 edges) for every
+    # resident workgroup, i.e. at least 2^21 edges on this chip
+    if order == "small_n":      # fewer vertices than a window: a local multigraph
+        n = 6000
+        m = (1 << 21) + 4099
+        u = np.sort(rng.integers(0, n, m)).astype(np.int32)
+        v = ((u.astype(np.int64) + rng.integers(1, 40, m)) % n).astype(np.int32)
+        w = rng.integers(1, 256, m).astype(np.uint32)
     else:
-        n = 90001
+        n = 600001
         u, v, w = graphgen.rgg2d(n, graphgen.rgg_radius(n, 8), 1e6, seed=4)
     if order == "shuffled":
         p = rng.permutation(len(u))
@@ -134,14 +139,14 @@ def test_local_graph_edge_orders(order):
         v[at] = rng.integers(0, n, k).astype(np.int32)
     elif order == "ragged":     # not a multiple of the vector width or the tile
         u, v, w = u[:len(u) - 8192 - 3], v[:len(v) - 8192 - 3], w[:len(w) - 8192 - 3]
-    assert len(u) >= 8192
+    assert len(u) >= 1 << 21
     check_against_oracle(u, v, w, n, rounds=True)
 
 
 def test_out_of_range_id_in_a_local_graph():
     import paper_2302_12199_amd as msf
     banner("out of range id in a local graph")
-    n = 90001
+    n = 600001
     u, v, w = graphgen.rgg2d(n, graphgen.rgg_radius(n, 8), 1e6, seed=4)
     for at, bad in ((len(u) // 2, n), (len(u) - 1, 2**31 - 1), (5, -1)):
         uu = u.copy()
