@@ -128,6 +128,27 @@ __device__ __forceinline__ void tier_update(uint64_t* best, int32_t t, uint64_t 
     if (act) atomic_min_key(&best[t], key);
 }
 
+// As tier_update for lanes whose key already beat the entry as read earlier
+// (a caller that issues all its reads first keeps them in flight together):
+// the atomics go out without reading the entry again.
+__device__ __forceinline__ void tier_commit(uint64_t* best, int32_t t, uint64_t key, bool act,
+                                            int wave_min) {
+    if (wave_min > 0) {
+        const uint64_t am = __ballot(act);
+        if (am) {
+            const int leader = __builtin_ctzll(am);
+            const int32_t tl = __shfl(t, leader, 64);
+            const bool same = act && t == tl;
+            if (__popcll(__ballot(same)) >= (wave_min > 2 ? wave_min : 2)) {
+                const uint64_t k = wave_min_u64(same ? key : kKeyMax);
+                if (lane_id() == leader) atomicMin((unsigned long long*)&best[tl], (unsigned long long)k);
+                act = act && !same;
+            }
+        }
+    }
+    if (act) atomicMin((unsigned long long*)&best[t], (unsigned long long)key);
+}
+
 // Block tier, chosen per chunk: one wave samples 32 evenly spaced edges of
 // [lo, hi) (both ends, so 64 labels) and keeps the kHot labels seen on at
 // least hot_min of them; their minima live in LDS during the chunk.  Called by
@@ -215,16 +236,28 @@ __device__ __forceinline__ void min_edges(const int32_t* __restrict__ U,
                 lb[k] = lab[b[k]];
             }
         }
+        // every lane's minimum reads first, then the atomics of the keys that
+        // still lower them: the reads of a lane overlap instead of running one
+        // after another
+        uint64_t key[kEdgeIlp], ca[kEdgeIlp], cb[kEdgeIlp];
+        bool ax[kEdgeIlp], ay[kEdgeIlp];
 #pragma unroll
         for (int k = 0; k < kEdgeIlp; ++k) {
             const bool act = la[k] != lb[k];
             const int64_t e = base + k * BS + tid;
-            const uint64_t key = ((uint64_t)wt[k] << 32) | (uint64_t)e;
+            key[k] = ((uint64_t)wt[k] << 32) | (uint64_t)e;
             if (act) any = 1;
-            const bool hx = act && s_hot && hot_min(hot, s_hotmin, la[k], key);
-            const bool hy = act && s_hot && hot_min(hot, s_hotmin, lb[k], key);
-            tier_update(best, la[k], key, act && !hx, wave_min);
-            tier_update(best, lb[k], key, act && !hy, wave_min);
+            const bool hx = act && s_hot && hot_min(hot, s_hotmin, la[k], key[k]);
+            const bool hy = act && s_hot && hot_min(hot, s_hotmin, lb[k], key[k]);
+            ax[k] = act && !hx;
+            ay[k] = act && !hy;
+            ca[k] = ax[k] ? best[la[k]] : 0;
+            cb[k] = ay[k] ? best[lb[k]] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kEdgeIlp; ++k) {
+            tier_commit(best, la[k], key[k], ax[k] && key[k] < ca[k], wave_min);
+            tier_commit(best, lb[k], key[k], ay[k] && key[k] < cb[k], wave_min);
         }
     }
 }
