@@ -262,6 +262,11 @@ __device__ __forceinline__ void min_edges(const int32_t* __restrict__ U,
     }
 }
 
+// The per-vertex steps below take kVtxIlp vertices per thread at a time and
+// issue each level of their dependent loads together (a lane's chains overlap
+// instead of running one after another).
+constexpr int kVtxIlp = 4;
+
 // Hook + MSF mark over labels [lo, hi): parent = other end of the lightest
 // edge; of a 2-cycle (same edge chosen by both) the smaller label is the root.
 __device__ __forceinline__ uint64_t hook_range(const int32_t* __restrict__ U,
@@ -270,21 +275,101 @@ __device__ __forceinline__ uint64_t hook_range(const int32_t* __restrict__ U,
                                                const uint64_t* best, int32_t* par,
                                                uint8_t* mask) {
     uint64_t wsum = 0;
-    for (int64_t x = lo + threadIdx.x; x < hi; x += stride) {
-        const uint64_t b = best[x];
-        if (b == kKeyMax) { par[x] = (int32_t)x; continue; }
-        const uint32_t pos = (uint32_t)b;
-        const int32_t la = lab[U[pos]], lb = lab[V[pos]];
-        const int32_t other = la == (int32_t)x ? lb : la;
-        if (best[other] == b && (int32_t)x < other) {
-            par[x] = (int32_t)x;
-        } else {
-            par[x] = other;
-            mask[pos] = 1;
-            wsum += b >> 32;
+    for (int64_t x0 = lo + threadIdx.x; x0 < hi; x0 += (int64_t)stride * kVtxIlp) {
+        uint64_t b[kVtxIlp], bo[kVtxIlp];
+        int32_t la[kVtxIlp], lb[kVtxIlp], other[kVtxIlp];
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const int64_t x = x0 + (int64_t)k * stride;
+            b[k] = x < hi ? best[x] : kKeyMax;
+        }
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const uint32_t pos = (uint32_t)b[k];
+            la[k] = b[k] != kKeyMax ? U[pos] : 0;
+            lb[k] = b[k] != kKeyMax ? V[pos] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            la[k] = b[k] != kKeyMax ? lab[la[k]] : 0;
+            lb[k] = b[k] != kKeyMax ? lab[lb[k]] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const int64_t x = x0 + (int64_t)k * stride;
+            other[k] = la[k] == (int32_t)x ? lb[k] : la[k];
+            bo[k] = b[k] != kKeyMax ? best[other[k]] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const int64_t x = x0 + (int64_t)k * stride;
+            if (x >= hi) continue;
+            if (b[k] == kKeyMax || (bo[k] == b[k] && (int32_t)x < other[k])) {
+                par[x] = (int32_t)x;
+            } else {
+                par[x] = other[k];
+                mask[(uint32_t)b[k]] = 1;
+                wsum += b[k] >> 32;
+            }
         }
     }
     return wsum;
+}
+
+// One pointer-jumping step over [lo, hi): par[x] <- par[par[x]]; true if any
+// entry changed.
+__device__ __forceinline__ bool jump_range(int32_t* par, int64_t lo, int64_t hi, int stride) {
+    bool changed = false;
+    for (int64_t x0 = lo + threadIdx.x; x0 < hi; x0 += (int64_t)stride * kVtxIlp) {
+        int32_t p[kVtxIlp], pp[kVtxIlp];
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const int64_t x = x0 + (int64_t)k * stride;
+            p[k] = x < hi ? par[x] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const int64_t x = x0 + (int64_t)k * stride;
+            pp[k] = x < hi ? par[p[k]] : p[k];
+        }
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const int64_t x = x0 + (int64_t)k * stride;
+            if (x < hi && p[k] != pp[k]) {
+                par[x] = pp[k];
+                changed = true;
+            }
+        }
+    }
+    return changed;
+}
+
+// Label composition over [lo, hi): a label whose component found no edge is
+// done (-1), any other becomes the new id of its component's root.
+__device__ __forceinline__ void compose_range(int32_t* lab, const uint64_t* best,
+                                              const int32_t* par, const int32_t* nid,
+                                              int64_t lo, int64_t hi, int stride) {
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (int64_t)stride * kVtxIlp) {
+        int32_t l[kVtxIlp], r[kVtxIlp];
+        uint64_t bl[kVtxIlp];
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const int64_t i = i0 + (int64_t)k * stride;
+            l[k] = i < hi ? lab[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            bl[k] = l[k] >= 0 ? best[l[k]] : kKeyMax;
+            r[k] = l[k] >= 0 ? par[l[k]] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) r[k] = l[k] >= 0 && bl[k] != kKeyMax ? nid[r[k]] : -1;
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const int64_t i = i0 + (int64_t)k * stride;
+            if (i < hi && l[k] >= 0) lab[i] = r[k];
+        }
+    }
 }
 
 // --------------------------------------------------- one workgroup per graph
@@ -326,11 +411,7 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
             wsum += hook_range(U, V, 0, ncur, BS, lab, best, par, mask);
             __syncthreads();
             for (int it = 0; it < kMaxJumps; ++it) {                   // pointer jumping
-                int changed = 0;
-                for (int64_t x = tid; x < ncur; x += BS) {
-                    const int32_t p = par[x], pp = par[p];
-                    if (p != pp) { par[x] = pp; changed = 1; }
-                }
+                const int changed = jump_range(par, 0, ncur, BS) ? 1 : 0;
                 if (!__syncthreads_or(changed)) break;
             }
             int64_t roots = 0;                                         // dense ids of roots
@@ -343,10 +424,7 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
                 roots += tot;
             }
             __syncthreads();
-            for (int64_t i = tid; i < n; i += BS) {                    // compose labels
-                const int32_t l = lab[i];
-                if (l >= 0) lab[i] = best[l] == kKeyMax ? -1 : nid[par[l]];
-            }
+            compose_range(lab, best, par, nid, 0, n, BS);              // compose labels
             ncur = roots;
             __syncthreads();
         }
@@ -710,11 +788,7 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
             break;
         }
         case C_JUMP: {
-            int changed = 0;
-            for (int64_t x = v0 + tid; x < vn; x += BS) {
-                const int32_t p = S.par[x], pp = S.par[p];
-                if (p != pp) { S.par[x] = pp; changed = 1; }
-            }
+            const int changed = jump_range(S.par, v0, vn, BS) ? 1 : 0;
             if (__syncthreads_or(changed) && tid == 0) atomicOr(&X->f_changed, 1u);
             break;
         }
@@ -744,16 +818,10 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
         }
         case C_COMPOSE: {
             const int64_t xh = v0 + CV < P.n ? v0 + CV : P.n;
-            for (int64_t i = v0 + tid; i < xh; i += BS) {
-                const int32_t l = S.lab[i];
-                if (l >= 0) S.lab[i] = S.best[l] == kKeyMax ? -1 : S.nid[S.par[l]];
-            }
+            compose_range(S.lab, S.best, S.par, S.nid, v0, xh, BS);
             if (P.pair_mode) {
                 const int64_t ph = v0 + CV < P.pn ? v0 + CV : P.pn;
-                for (int64_t i = v0 + tid; i < ph; i += BS) {
-                    const int32_t l = S.plab[i];
-                    if (l >= 0) S.plab[i] = S.best[l] == kKeyMax ? -1 : S.nid[S.par[l]];
-                }
+                compose_range(S.plab, S.best, S.par, S.nid, v0, ph, BS);
             }
             break;
         }
