@@ -223,8 +223,15 @@ int msf_batched_autotune(const int32_t* u, const int32_t* v, const uint32_t* w,
         HIP_TRY(hipEventElapsedTime(ms, a, b));
         return MSF_OK;
     };
+    // the defaults, spelled out, so that the result names every choice even
+    // when no candidate beats them
     msf_batch_options best;
     memset(&best, 0, sizeof best);
+    best.block = 1024;
+    best.lds_vertices = 2048;
+    best.coop_edges = 1 << 20;
+    best.hot_min = 8;
+    best.wave_min = 2;
     float best_ms = -1.f, ms = 0.f;
     int st = run(best, &ms);                      // warm-up
     if (st == MSF_OK) st = run(best, &best_ms);
