@@ -105,7 +105,7 @@ def test_midsize_families_with_rounds(kind, size):
 
 
 @pytest.mark.parametrize("order", ["sorted", "shuffled", "reversed", "swapped", "long_range",
-                                   "ragged", "small_n"])
+                                   "ragged", "small_n", "loops_and_copies"])
 def test_local_graph_edge_orders(order):
     """Graphs that pass the locality sample take round 0's lightest edges in a
     sliding LDS window over the ids; edges in any order, or far outside the
@@ -137,6 +137,16 @@ def test_local_graph_edge_orders(order):
         u = u.copy()
         v = v.copy()
         v[at] = rng.integers(0, n, k).astype(np.int32)
+    elif order == "loops_and_copies":   # 10 % self-loops and 10 % heavier parallel copies
+        k = len(u) // 10
+        at = np.sort(rng.choice(len(u), 2 * k, replace=False))
+        u = u.copy()
+        v = v.copy()
+        w = w.copy()
+        v[at[:k]] = u[at[:k]]                         # self-loops in place
+        src = at[k:] - 1                              # a copy of the edge before, heavier
+        u[at[k:]], v[at[k:]] = v[src], u[src]
+        w[at[k:]] = np.minimum(w[src].astype(np.uint64) + 1, 2**32 - 1).astype(np.uint32)
     elif order == "ragged":     # not a multiple of the vector width or the tile
         u, v, w = u[:len(u) - 8192 - 3], v[:len(v) - 8192 - 3], w[:len(w) - 8192 - 3]
     assert len(u) >= 1 << 21
