@@ -148,11 +148,12 @@ __global__ __launch_bounds__(kBlock) void k_minedge_r0(
 // sample): each workgroup walks a contiguous run of tiles and keeps the minima
 // of a window of kWinSlots consecutive vertex ids in LDS.  The window start
 // only moves up (to just below each tile's first endpoint); the ids it leaves
-// behind are written out with one pre-checked global update each, read by
-// consecutive lanes.  Endpoints outside the window take the global path, their
+// behind are written out with one atomic each, consecutive lanes on
+// consecutive ids.  Endpoints outside the window take the global path, their
 // reads issued together before the atomics.  Sorted-by-source edge lists (the
 // usual layout of generated and distributed graphs) keep nearly every endpoint
-// in the window; any other order is still correct, only slower.
+// in the window; any other order is still correct, only slower.  Used when
+// every workgroup that fits at once gets a tile (launch_minedge_r0).
 constexpr int kWinThreads = 1024;
 constexpr int kWinGroups = 2;                                   // 4-edge groups per lane per tile
 constexpr int64_t kWinTile = (int64_t)kWinThreads * 4 * kWinGroups;   // 8192 edges
