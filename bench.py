@@ -20,6 +20,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -52,13 +53,21 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def _code_only(text):
+    """Source text without comments and blank space: an edited comment does not
+    change the code a counter reading was taken on."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def family_source_hash(family):
     h = hashlib.sha256()
     for name in sorted(set(FAMILY_SOURCES.get(family, []) + COMMON)):
         p = os.path.join(CSRC, name)
         if os.path.exists(p):
             h.update(name.encode())
-            h.update(open(p, "rb").read())
+            h.update(_code_only(open(p, encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 
