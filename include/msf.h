@@ -230,9 +230,9 @@ int msf_compute_noalloc(const int32_t* u, const int32_t* v, const uint32_t* w, i
  * Errors: MSF_EINVAL (bad host arguments), MSF_EWORKSPACE, MSF_EDEVICE.
  */
 typedef struct msf_batch_options {
-    int32_t block;           /* threads per workgroup: 256, 512 or 1024; 0 = 1024 */
+    int32_t block;           /* threads per workgroup: 256, 512 or 1024; 0 = 512 */
     int32_t lds_vertices;    /* graphs with at most this many vertices keep their
-                                state in LDS (20 B per vertex); 0 = 2048, -1 = never */
+                                state in LDS (20 B per vertex); 0 = 4096, -1 = never */
     int32_t workgroups;      /* persistent workgroups; 0 = as many as can be resident */
     int32_t coop_edges;      /* graphs with at least this many edges are solved
                                 cooperatively per XCD; 0 = 2^20, -1 = never */
