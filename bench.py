@@ -227,6 +227,25 @@ def to_device(u, v, w):
     return [torch.from_numpy(np.ascontiguousarray(x).view(np.int32)).to(dev) for x in (u, v, w)]
 
 
+def copy_bandwidth(dev, nbytes=1 << 31, reps=5):
+    """Attainable HBM bandwidth: a plain device-to-device copy of nbytes, bytes
+    read plus bytes written per second (GB/s)."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (time.perf_counter() - t) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 # ------------------------------------------------------------- CPU baseline
 
 def cpu_baseline(u, v, w, n, sample_edges, runs=3):
@@ -466,8 +485,14 @@ def main():
     rec = measure_graph(msf, tu, tv, tw, n, args.workload, args.steps, args.warmup, 2, **opts)
     log(f"timed {args.steps} steps: {rec['ms_per_step']:.3f} ms/step total={rec['total_weight']}")
     roofline = roofline_of(rec, args.workload)
+    dev = tu.device
     del tu, tv, tw
     torch.cuda.empty_cache()
+    if roofline:
+        cg = copy_bandwidth(dev)
+        roofline["copy_GBps"] = round(cg, 1)
+        roofline["achieved_vs_copy"] = round(roofline["achieved"] / cg, 4)
+        log(f"attainable copy bandwidth {cg:.0f} GB/s")
 
     cpu = None
     if args.cpu_sample > 0:
