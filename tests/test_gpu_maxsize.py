@@ -99,3 +99,57 @@ def test_maximum_vertex_count():
     finally:
         del tu, tv, tw, ws
         _release()
+
+
+@pytest.mark.timeout(900)
+def test_batched_maximum_sizes():
+    """One batch whose edge offsets pass 2^32: a graph of 2^32 - 1 edges and
+    one of 2^29 + 3 (each solved by the workgroups of one XCD together), then
+    two smaller ones at offsets above 2^32 (one workgroup each, one with its
+    state in LDS, one in a global slot); known MSFs, the small random graph
+    against the oracle."""
+    import torch
+    import paper_2302_12199_amd as msf
+    banner("batched maximum sizes: generating")
+    _release()
+    dev = torch.device("cuda:0")
+    parts, exps, totals, counts, ns = [], [], [], [], []
+    for m, n, seed in ((M_MAX, 1 << 20, 51), (2**29 + 3, 1 << 18, 52), (2**20 - 3, 1 << 16, 53)):
+        u, v, w, exp, t, c = known_msf_graph(m, n, device=dev, seed=seed)
+        parts.append((u, v, w))
+        exps.append(exp)
+        totals.append(t)
+        counts.append(c)
+        ns.append(n)
+    rng = np.random.default_rng(54)
+    su = rng.integers(0, 3000, 20000).astype(np.int32)
+    sv = rng.integers(0, 3000, 20000).astype(np.int32)
+    sw = rng.integers(0, 50, 20000).astype(np.uint32)
+    rm, rt, _ = oracle.kruskal(su, sv, sw, 3000)
+    parts.insert(2, tuple(to_dev(su, sv, sw)))
+    exps.insert(2, torch.from_numpy(rm).to(dev))
+    totals.insert(2, rt)
+    ns.insert(2, 3000)
+    sizes = [p[0].numel() for p in parts]
+    eo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    vo = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    assert eo[2] > 2**32
+    cat = [torch.empty(int(eo[-1]), dtype=torch.int32, device=dev) for _ in range(3)]
+    for g, p in enumerate(parts):
+        for k in range(3):
+            cat[k][eo[g]:eo[g + 1]] = p[k]
+    del parts
+    _release()
+    b = None
+    try:
+        b = msf.Batch(cat[0], cat[1], cat[2], eo, vo)
+        banner("batched maximum sizes: solving")
+        b.launch()
+        torch.cuda.synchronize()
+        got = b.totals[:4].cpu().numpy().view(np.uint64)
+        assert [int(x) for x in got] == totals
+        for g in range(4):
+            assert _equal_chunks(b.mask[eo[g]:eo[g + 1]], exps[g])
+    finally:
+        del cat, exps, b
+        _release()
