@@ -306,9 +306,12 @@ __global__ __launch_bounds__(kWinThreads) void k_minedge_win(
 // 2-cycle picked the same edge (strict order), recognised as best[other] ==
 // best[x]; the smaller id is the root.  Every other live vertex owns exactly
 // one MSF edge and marks it, so each MSF edge is counted once.  `cmap` maps
-// the view's stored labels to this round's labels (null: identity).
+// the view's stored labels to this round's labels (null: identity).  SIDE:
+// the keys are w << 32 | position << 1 | side (side 1: x is the edge's v
+// end), so only the other end is read, and the other end's key for the same
+// edge has the opposite side bit.
 constexpr int kHookBlock = 1024;
-template <int MODE>
+template <int MODE, bool SIDE>
 __global__ __launch_bounds__(kHookBlock) void k_hook(const uint64_t* __restrict__ best, int64_t nr,
                                                  View g, const int32_t* __restrict__ cmap,
                                                  int32_t* __restrict__ parent,
@@ -320,21 +323,29 @@ __global__ __launch_bounds__(kHookBlock) void k_hook(const uint64_t* __restrict_
         const uint64_t b = best[x];
         if (b == kKeyMax) { parent[x] = (int32_t)x; continue; }
         ++nlive;
-        const uint32_t pos = (uint32_t)b;
-        int32_t eu, ev;
-        if constexpr (MODE == kOrig) {
+        uint32_t pos;
+        int32_t other;
+        if constexpr (SIDE) {
             // the caller's arrays are far larger than the caches: these lines
             // are read once, so non-temporal loads leave the caches to best[]
-            eu = __builtin_nontemporal_load(g.u + pos);
-            ev = __builtin_nontemporal_load(g.v + pos);
+            pos = (uint32_t)b >> 1;
+            other = ((uint32_t)b & 1u) ? __builtin_nontemporal_load(g.u + pos)
+                                       : __builtin_nontemporal_load(g.v + pos);
         } else {
-            load_ends<MODE>(g, pos, eu, ev);
+            pos = (uint32_t)b;
+            int32_t eu, ev;
+            if constexpr (MODE == kOrig) {
+                eu = __builtin_nontemporal_load(g.u + pos);
+                ev = __builtin_nontemporal_load(g.v + pos);
+            } else {
+                load_ends<MODE>(g, pos, eu, ev);
+            }
+            if (cmap) { eu = cmap[eu]; ev = cmap[ev]; }
+            if (eu != x && ev != x) bad = true;
+            other = eu == (int32_t)x ? ev : eu;
         }
-        if (cmap) { eu = cmap[eu]; ev = cmap[ev]; }
-        if (eu != x && ev != x) bad = true;
-        const int32_t other = eu == (int32_t)x ? ev : eu;
         if ((uint32_t)other >= (uint64_t)nr) { bad = true; parent[x] = (int32_t)x; continue; }
-        if (best[other] == b && (int32_t)x < other) {
+        if (best[other] == (SIDE ? b ^ 1u : b) && (int32_t)x < other) {
             parent[x] = (int32_t)x;
         } else {
             parent[x] = other;
@@ -1265,15 +1276,19 @@ void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, in
                            n, best, ctrl, hot);
 }
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
-                 int32_t* parent, uint8_t* mask, Ctrl* ctrl, hipStream_t s) {
+                 int32_t* parent, uint8_t* mask, Ctrl* ctrl, bool side_keys, hipStream_t s) {
     int64_t hb = (nr + kHookBlock - 1) / kHookBlock;
     hb = hb < 1 ? 1 : (hb > 256 ? 256 : hb);
     const dim3 gr((unsigned)hb), bl(kHookBlock);
+    if (side_keys && mode == kOrig && !cmap) {
+        hipLaunchKernelGGL((k_hook<kOrig, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl);
+        return;
+    }
     switch (mode) {
-        case kOrig: hipLaunchKernelGGL(k_hook<kOrig>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
-        case kFull32: hipLaunchKernelGGL(k_hook<kFull32>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
-        case kFull16: hipLaunchKernelGGL(k_hook<kFull16>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
-        default: hipLaunchKernelGGL(k_hook<kCompact>, gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+        case kOrig: hipLaunchKernelGGL((k_hook<kOrig, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+        case kFull32: hipLaunchKernelGGL((k_hook<kFull32, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+        case kFull16: hipLaunchKernelGGL((k_hook<kFull16, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+        default: hipLaunchKernelGGL((k_hook<kCompact, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
     }
 }
 void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s) {

@@ -12,12 +12,14 @@ constexpr int kBucketTileShift = 13;
 constexpr int64_t kBucketTile = 1ll << kBucketTileShift;   // edges per tile
 constexpr int64_t kTileArcs = 2 * kBucketTile;              // arc slots per tile block
 constexpr int kBucketMax = 1024;                      // buckets (n <= 2^24)
+constexpr int kArcSideBit = kBucketShift + kBucketTileShift;   // which end of its edge an arc is
 constexpr int kBucketThreads = 1024;
 
 struct BucketBuffers {
     uint64_t* arcs;      // [nt * kTileArcs] per tile, its arcs sorted by bucket:
-                         // w << 32 | (edge - first edge of the tile) << 14 | vertex in bucket;
-                         // later the arcs' new labels, bucket-major (uint32)
+                         // w << 32 | side << 27 | (edge - first edge of the tile) << 14 |
+                         // vertex in bucket (side 1: the edge's v end); later the arcs'
+                         // new labels, bucket-major (uint32)
     uint32_t* meta;      // [nt * nb] tile-major: run start in the tile block | run length << 16
     uint32_t* metat;     // [nb * nt] the same, bucket-major
     uint32_t* offb;      // [nb * nt] bucket-major: first arc of run (b, t) counted from the bucket's start
@@ -46,7 +48,11 @@ constexpr int kLocalitySample = 4096;
 void bucket_sample_locality(const int32_t* u, const int32_t* v, int64_t m, Ctrl* ctrl,
                             hipStream_t s);
 
-// Lightest edge of every vertex: best[0, n) (validates the ids: kErrRange).
+// Lightest edge of every vertex: best[0, n) (validates the ids: kErrRange),
+// as w << 32 | position << 1 | side, side 1 when the vertex is the edge's v
+// end (the bucketed path takes m < 2^31, so this fits; the order is that of
+// (w, position): only a self-loop has both ends at one vertex, and it has no
+// arcs).  The hook then reads one end of the edge, not both.
 void bucket_minedge(const BucketBuffers& B, const int32_t* u, const int32_t* v,
                     const uint32_t* w, int64_t m, int64_t n, uint64_t* best, Ctrl* ctrl,
                     hipStream_t s);

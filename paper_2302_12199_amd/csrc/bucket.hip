@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_scatter(
                 const uint32_t px = atomicAdd(&s_cur[(uint32_t)x >> kBucketShift], 1u) & kArcMask;
                 const uint32_t py = atomicAdd(&s_cur[(uint32_t)y >> kBucketShift], 1u) & kArcMask;
                 s_stage[px] = hi | (uint64_t)(x & (kBucketWidth - 1));
-                s_stage[py] = hi | (uint64_t)(y & (kBucketWidth - 1));
+                s_stage[py] = hi | (1ull << kArcSideBit) | (uint64_t)(y & (kBucketWidth - 1));
                 rk[k] = px | (py << 16);
             }
             if (q * 4 + 3 < e1) {
@@ -332,7 +332,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_min(
                 const uint32_t xl = (uint32_t)arc[k] & (uint32_t)(kBucketWidth - 1);
                 const uint64_t e = ((uint64_t)(r0 + run[k]) << kBucketTileShift) +
                                    (((uint32_t)arc[k] >> kBucketShift) & (uint32_t)(kBucketTile - 1));
-                const uint64_t key = (arc[k] & 0xffffffff00000000ull) | e;
+                const uint64_t key = (arc[k] & 0xffffffff00000000ull) | (e << 1) |
+                                     (((uint32_t)arc[k] >> kArcSideBit) & 1u);
                 if (key < s_best[xl]) atomicMin(&s_best[xl], (unsigned long long)key);
                 const uint64_t o = xs0 + pre + x;
                 if (o < (uint64_t)narcs) xs[o] = (uint16_t)xl;
@@ -638,10 +639,20 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_locality(const int32_t* _
                                                                 const int32_t* __restrict__ v,
                                                                 int64_t m, Ctrl* ctrl) {
     __shared__ uint64_t s_w[kBucketThreads / kWave];
+    constexpr int kPer = kLocalitySample / kBucketThreads;
+    static_assert(kPer * kBucketThreads == kLocalitySample, "whole samples per thread");
+    int32_t a[kPer], b[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {     // every load issued before the first compare
+        const uint64_t k = (uint64_t)(threadIdx.x + j * kBucketThreads);
+        const int64_t e = (int64_t)((k * (uint64_t)m) / kLocalitySample);
+        a[j] = u[e];
+        b[j] = v[e];
+    }
     uint64_t local = 0;
-    for (int k = threadIdx.x; k < kLocalitySample; k += blockDim.x) {
-        const int64_t e = (int64_t)(((uint64_t)k * (uint64_t)m) / kLocalitySample);
-        const int64_t d = (int64_t)u[e] - (int64_t)v[e];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t d = (int64_t)a[j] - (int64_t)b[j];
         local += (d < kBucketWidth && -d < kBucketWidth) ? 1 : 0;
     }
     uint64_t tot;

@@ -161,10 +161,12 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
     bool m_pending = false, m_compacted = false;
     uint32_t rounds = stats ? stats->rounds : 0;
     const uint32_t first_round = rounds;
+    bool side_keys = bucketed;   // the bucketed minima also say which end x is
     while (m_live > 0 || m_pending) {
         launch_scan_prep(B.status, 0, dc, 1, s);
         const int hh = prof_begin(K_HOOK, s);
-        launch_hook(mode, B.best[cur], nr, view, cmap, B.parent, mask, dc, s);
+        launch_hook(mode, B.best[cur], nr, view, cmap, B.parent, mask, dc, side_keys, s);
+        side_keys = false;
         prof_end(hh, s, 12.0 * nr);
         int32_t* lab = B.lab[labsel];
         for (int attempt = 0;; ++attempt) {

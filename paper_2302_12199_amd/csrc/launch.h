@@ -15,8 +15,10 @@ void launch_scan_prep(uint64_t* status, int64_t ntiles, Ctrl* ctrl, int round_be
 void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
                        int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, bool local,
                        hipStream_t s);
+// side_keys: best[] holds w << 32 | position << 1 | side (the bucketed round
+// 0 on the caller's arrays, mode kOrig), else w << 32 | position.
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
-                 int32_t* parent, uint8_t* mask, Ctrl* ctrl, hipStream_t s);
+                 int32_t* parent, uint8_t* mask, Ctrl* ctrl, bool side_keys, hipStream_t s);
 void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s);
 void launch_scan_roots(const int32_t* parent, const uint64_t* best, int64_t nr, int32_t* label,
                        uint64_t* status, Ctrl* ctrl, hipStream_t s);
