@@ -84,11 +84,13 @@ __device__ __forceinline__ uint32_t edge_id(const View& g, int64_t p) {
 // arrays are 16-byte aligned).  Validates ids (kErrRange), skips self-loops.
 // `hot` (or -1) names a vertex expected on very many edges (the largest
 // component after a filter step): its minimum is taken in LDS per workgroup
-// and merged with one global atomic at the end.
+// and merged with one global atomic at the end.  sh = 1: side keys, w << 32
+// | position << 1 | side (side 1 at the v end; m <= 2^31); sh = 0: w << 32 |
+// position.
 template <int VEC>
 __global__ __launch_bounds__(kBlock) void k_minedge_r0(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
-    int64_t m, int64_t n, uint64_t* __restrict__ best, Ctrl* ctrl, int32_t hot) {
+    int64_t m, int64_t n, uint64_t* __restrict__ best, Ctrl* ctrl, int32_t hot, int sh) {
     __shared__ unsigned long long s_hot;
     if (threadIdx.x == 0) s_hot = kKeyMax;
     __syncthreads();
@@ -128,15 +130,16 @@ __global__ __launch_bounds__(kBlock) void k_minedge_r0(
             }
             act = act && a != b;
             if (!act) a = b = 0;
-            const uint64_t key = ((uint64_t)ww[k] << 32) | (uint64_t)e;
+            const uint64_t key = ((uint64_t)ww[k] << 32) | ((uint64_t)e << sh);
+            const uint64_t key_b = key | (uint64_t)sh;
             bool act_a = act, act_b = act;
             if (act && (a == hot || b == hot)) {
-                atomicMin(&s_hot, (unsigned long long)key);
+                atomicMin(&s_hot, (unsigned long long)(a == hot ? key : key_b));
                 act_a = a != hot;
                 act_b = b != hot;
             }
             wave_min_update(best, a, key, act_a);
-            wave_min_update(best, b, key, act_b);
+            wave_min_update(best, b, key_b, act_b);
         }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, kErrRange);
@@ -209,7 +212,7 @@ __device__ __forceinline__ void win_load(const int32_t* __restrict__ u,
 __global__ __launch_bounds__(kWinThreads) void k_minedge_win(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, const uint32_t* __restrict__ w,
     int64_t m, int64_t n, uint64_t* __restrict__ best, Ctrl* ctrl, int32_t hot,
-    int64_t tiles_per_block) {
+    int64_t tiles_per_block, int sh) {
     __shared__ unsigned long long s_min[kWinSlots];
     __shared__ unsigned long long s_hot;
     __shared__ int64_t s_base;
@@ -260,10 +263,11 @@ __global__ __launch_bounds__(kWinThreads) void k_minedge_win(
                 act = false;
             }
             act = act && a != b;
-            key[i] = ((uint64_t)ww[i] << 32) | (uint64_t)e;
+            key[i] = ((uint64_t)ww[i] << 32) | ((uint64_t)e << sh);   // the a end's key
+            const uint64_t key_b = key[i] | (uint64_t)sh;
             bool act_a = act, act_b = act;
             if (act && (a == hot || b == hot)) {
-                atomicMin(&s_hot, (unsigned long long)key[i]);
+                atomicMin(&s_hot, (unsigned long long)(a == hot ? key[i] : key_b));
                 act_a = a != hot;
                 act_b = b != hot;
             }
@@ -276,7 +280,7 @@ __global__ __launch_bounds__(kWinThreads) void k_minedge_win(
             }
             if (act_b && !gb[i]) {
                 unsigned long long* p = &s_min[b & (kWinSlots - 1)];
-                if (key[i] < *p) atomicMin(p, (unsigned long long)key[i]);
+                if (key_b < *p) atomicMin(p, (unsigned long long)key_b);
             }
             aa[i] = ga[i] ? a : 0;
             bb[i] = gb[i] ? b : 0;
@@ -290,8 +294,9 @@ __global__ __launch_bounds__(kWinThreads) void k_minedge_win(
         }
 #pragma unroll
         for (int i = 0; i < kE; ++i) {
+            const uint64_t key_b = key[i] | (uint64_t)sh;
             wave_min_commit(best, aa[i], key[i], ga[i] && key[i] < ca[i]);
-            wave_min_commit(best, bb[i], key[i], gb[i] && key[i] < cb[i]);
+            wave_min_commit(best, bb[i], key_b, gb[i] && key_b < cb[i]);
         }
     }
     __syncthreads();
@@ -326,11 +331,16 @@ __global__ __launch_bounds__(kHookBlock) void k_hook(const uint64_t* __restrict_
         uint32_t pos;
         int32_t other;
         if constexpr (SIDE) {
-            // the caller's arrays are far larger than the caches: these lines
-            // are read once, so non-temporal loads leave the caches to best[]
             pos = (uint32_t)b >> 1;
-            other = ((uint32_t)b & 1u) ? __builtin_nontemporal_load(g.u + pos)
-                                       : __builtin_nontemporal_load(g.v + pos);
+            if constexpr (MODE == kOrig) {
+                // the caller's arrays are far larger than the caches: these
+                // lines are read once, so non-temporal loads leave the caches
+                // to best[]
+                other = ((uint32_t)b & 1u) ? __builtin_nontemporal_load(g.u + pos)
+                                           : __builtin_nontemporal_load(g.v + pos);
+            } else {
+                other = ((uint32_t)b & 1u) ? g.u[pos] : g.v[pos];
+            }
         } else {
             pos = (uint32_t)b;
             int32_t eu, ev;
@@ -1253,9 +1263,10 @@ static int64_t resident_blocks(K kernel, int threads) {
 
 void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
                        int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, bool local,
-                       hipStream_t s) {
+                       bool side_keys, hipStream_t s) {
     if (m <= 0) return;
     if (hot >= n) hot = -1;
+    const int sh = side_keys && m <= kSideKeyMaxEdges ? 1 : 0;
     const bool aligned = (((uintptr_t)u | (uintptr_t)v | (uintptr_t)w) & 15) == 0;
     // the window needs a tile for every workgroup that fits at once (one per
     // CU: the window takes 128 KiB of LDS); smaller graphs would leave most of
@@ -1265,23 +1276,26 @@ void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, in
     if (local && aligned && ntiles >= cap) {
         const int64_t per = (ntiles + cap - 1) / cap;   // a contiguous run of tiles each
         hipLaunchKernelGGL(k_minedge_win, dim3((unsigned)((ntiles + per - 1) / per)),
-                           dim3(kWinThreads), 0, s, u, v, w, m, n, best, ctrl, hot, per);
+                           dim3(kWinThreads), 0, s, u, v, w, m, n, best, ctrl, hot, per, sh);
         return;
     }
     if (aligned)
         hipLaunchKernelGGL(k_minedge_r0<4>, dim3(grid_for((m + 3) / 4)), dim3(kBlock), 0, s, u,
-                           v, w, m, n, best, ctrl, hot);
+                           v, w, m, n, best, ctrl, hot, sh);
     else
         hipLaunchKernelGGL(k_minedge_r0<1>, dim3(grid_for(m)), dim3(kBlock), 0, s, u, v, w, m,
-                           n, best, ctrl, hot);
+                           n, best, ctrl, hot, sh);
 }
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
                  int32_t* parent, uint8_t* mask, Ctrl* ctrl, bool side_keys, hipStream_t s) {
     int64_t hb = (nr + kHookBlock - 1) / kHookBlock;
     hb = hb < 1 ? 1 : (hb > 256 ? 256 : hb);
     const dim3 gr((unsigned)hb), bl(kHookBlock);
-    if (side_keys && mode == kOrig && !cmap) {
-        hipLaunchKernelGGL((k_hook<kOrig, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl);
+    if (side_keys) {   // round 0 on the caller's arrays or a compact view: cmap is null
+        if (mode == kOrig)
+            hipLaunchKernelGGL((k_hook<kOrig, true>), gr, bl, 0, s, best, nr, g, nullptr, parent, mask, ctrl);
+        else
+            hipLaunchKernelGGL((k_hook<kCompact, true>), gr, bl, 0, s, best, nr, g, nullptr, parent, mask, ctrl);
         return;
     }
     switch (mode) {

@@ -138,6 +138,11 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
                               (B.dedup == MSF_DEDUP_AUTO && local)
                           ? kDedupLocal
                           : kDedupNone;
+    // The round-0 minima also say which end of its edge the vertex is (up to
+    // 2^31 positions: the position takes 31 bits, the side one), so the first
+    // hook reads only the other end.
+    const bool side_keys0 =
+        bucketed || ((mode == kOrig || mode == kCompact) && view.len <= kSideKeyMaxEdges);
     int h = -1;
     if (bucketed) {
         bucket_minedge(B.bk, view.u, view.v, view.w, view.len, nv, B.best[cur], dc, s);
@@ -146,7 +151,8 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         launch_fill_u64(B.best[cur], nr, kKeyMax, s);
         prof_end(h, s, 8.0 * nr);
         h = prof_begin(K_MINEDGE_R0, s);
-        launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, hot, local, s);
+        launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, hot, local,
+                          side_keys0, s);
         prof_end(h, s, 12.0 * view.len + 8.0 * nv);
     }
     HIP_TRY(hipGetLastError());
@@ -161,7 +167,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
     bool m_pending = false, m_compacted = false;
     uint32_t rounds = stats ? stats->rounds : 0;
     const uint32_t first_round = rounds;
-    bool side_keys = bucketed;   // the bucketed minima also say which end x is
+    bool side_keys = side_keys0;
     while (m_live > 0 || m_pending) {
         launch_scan_prep(B.status, 0, dc, 1, s);
         const int hh = prof_begin(K_HOOK, s);

@@ -12,11 +12,15 @@ void launch_scan_prep(uint64_t* status, int64_t ntiles, Ctrl* ctrl, int round_be
                       hipStream_t s);
 // local: the edges join nearby ids (locality sample); then the minima of a
 // sliding window of ids are taken in LDS.
+// side_keys (taken when m <= kSideKeyMaxEdges): best[] gets w << 32 |
+// position << 1 | side (side 1: the vertex is the edge's v end), which the
+// hook reads to fetch only the other end; else w << 32 | position.
+constexpr int64_t kSideKeyMaxEdges = 1ll << 31;
 void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
                        int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, bool local,
-                       hipStream_t s);
-// side_keys: best[] holds w << 32 | position << 1 | side (the bucketed round
-// 0 on the caller's arrays, mode kOrig), else w << 32 | position.
+                       bool side_keys, hipStream_t s);
+// side_keys: best[] holds w << 32 | position << 1 | side (round 0 on the
+// caller's arrays or a compact view, cmap null), else w << 32 | position.
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
                  int32_t* parent, uint8_t* mask, Ctrl* ctrl, bool side_keys, hipStream_t s);
 void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s);
