@@ -332,15 +332,20 @@ __global__ __launch_bounds__(kHookBlock) void k_hook(const uint64_t* __restrict_
         int32_t other;
         if constexpr (SIDE) {
             pos = (uint32_t)b >> 1;
+            const bool at_v = (uint32_t)b & 1u;   // x is the edge's v end: u is the other
             if constexpr (MODE == kOrig) {
                 // the caller's arrays are far larger than the caches: these
                 // lines are read once, so non-temporal loads leave the caches
                 // to best[]
-                other = ((uint32_t)b & 1u) ? __builtin_nontemporal_load(g.u + pos)
-                                           : __builtin_nontemporal_load(g.v + pos);
+                other = at_v ? __builtin_nontemporal_load(g.u + pos)
+                             : __builtin_nontemporal_load(g.v + pos);
+            } else if constexpr (MODE == kFull16) {
+                const uint32_t p = g.p16[pos];
+                other = (int32_t)(at_v ? (p & 0xffffu) : (p >> 16));
             } else {
-                other = ((uint32_t)b & 1u) ? g.u[pos] : g.v[pos];
+                other = at_v ? g.u[pos] : g.v[pos];
             }
+            if (cmap) other = cmap[other];
         } else {
             pos = (uint32_t)b;
             int32_t eu, ev;
@@ -564,7 +569,7 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
                                                      uint64_t* __restrict__ best_next, int64_t nn,
                                                      uint64_t* __restrict__ pairs, int64_t km,
                                                      const uint64_t* __restrict__ pair_hot,
-                                                     Ctrl* ctrl) {
+                                                     Ctrl* ctrl, int sh) {
     extern __shared__ uint64_t lds[];
     uint64_t* s_best = lds;                                        // nn entries (LDS_B)
     int32_t* s_map = reinterpret_cast<int32_t*>(lds + (LDS_B ? nn : 0));  // km entries (LDS_M)
@@ -643,7 +648,7 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
                         rb[k] = y;
                         ++kept;
                         act = true;
-                        key = ((uint64_t)w[j][k] << 32) | (uint64_t)(q * 4 + k);
+                        key = ((uint64_t)w[j][k] << 32) | ((uint64_t)(q * 4 + k) << (PAIR ? 0 : sh));
                         if constexpr (PAIR) {   // lightest edge per vertex pair, for the tail
                             const int64_t lo = x < y ? x : y, hi = x < y ? y : x;
                             const int64_t slot = hi * (hi - 1) / 2 + lo;
@@ -655,11 +660,12 @@ __global__ __launch_bounds__(kPassBlock) void k_pass(View g, const int32_t* __re
                         }
                     }
                 }
-                if constexpr (!PAIR) {
+                if constexpr (!PAIR) {   // the v end's key has the side bit (sh = 1)
+                    const uint64_t key_b = key | (uint64_t)sh;
                     const bool hx = act && hot_min(hot, s_hotmin, ra[k], key);
-                    const bool hy = act && hot_min(hot, s_hotmin, rb[k], key);
+                    const bool hy = act && hot_min(hot, s_hotmin, rb[k], key_b);
                     wave_min_update(bst, ra[k], key, act && !hx);
-                    wave_min_update(bst, rb[k], key, act && !hy);
+                    wave_min_update(bst, rb[k], key_b, act && !hy);
                 }
             }
             if (q < groups) store_group<OUT>(q, m, ra, rb, ou, ov, op16);
@@ -788,7 +794,7 @@ __device__ __forceinline__ uint64_t gpair_min(const uint64_t* dpair, const uint6
 //   k_compact_scatter  the kept edges, relabelled, stably at their offsets
 //                      (position order stays edge-id order) and, FUSED, the
 //                      next round's lightest-edge search on them with key
-//                      (w << 32 | new position).
+//                      w << 32 | new position << sh, the v end's | sh.
 // Flag word i covers positions [64 i, 64 i + 64); tile t owns words
 // [32 t, 32 t + 32), wave j of it words 32 t + 8 j + k.  `out` must not alias
 // the view.
@@ -993,7 +999,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(View g, const int32_
                                                             const uint64_t* __restrict__ off,
                                                             EdgeSoA out,
                                                             uint64_t* __restrict__ best_next,
-                                                            uint32_t ntiles) {
+                                                            uint32_t ntiles, int sh) {
     constexpr int kIt = kRelabelItems;
     __shared__ uint32_t s_wave[kBlock / kWave];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -1046,10 +1052,10 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(View g, const int32_
                 out.w[d] = wt[k];
                 out.id[d] = id[k];
             }
-            if constexpr (FUSED) {
-                const uint64_t key = ((uint64_t)wt[k] << 32) | d;
+            if constexpr (FUSED) {   // the v end's key has the side bit (sh = 1)
+                const uint64_t key = ((uint64_t)wt[k] << 32) | (d << sh);
                 wave_min_update(best_next, a[k], key, kept);
-                wave_min_update(best_next, b[k], key, kept);
+                wave_min_update(best_next, b[k], key | (uint64_t)sh, kept);
             }
             o += __popcll(mk[k]);
         }
@@ -1096,7 +1102,7 @@ template <int IN>
 __global__ __launch_bounds__(kSwThreads) void k_compact_scatter_win(
     View g, const int32_t* __restrict__ M, const uint64_t* __restrict__ flags,
     const uint64_t* __restrict__ off, EdgeSoA out, uint64_t* __restrict__ best_next,
-    uint32_t ntiles, int64_t nn, int64_t steps_per_block) {
+    uint32_t ntiles, int64_t nn, int64_t steps_per_block, int sh) {
     constexpr int kIt = kRelabelItems;
     __shared__ unsigned long long s_min[kSwSlots];
     __shared__ uint32_t s_wave[kSwThreads / kWave];
@@ -1169,7 +1175,7 @@ __global__ __launch_bounds__(kSwThreads) void k_compact_scatter_win(
         for (int k = 0; k < kIt; ++k) {
             const bool kept = (mk[k] >> lane) & 1;
             const uint64_t d = o + lanes_below(mk[k]);
-            key[k] = ((uint64_t)wt[k] << 32) | d;
+            key[k] = ((uint64_t)wt[k] << 32) | (d << sh);   // the a end's; the b end's adds sh
             ga[k] = gb[k] = false;
             if (kept) {
                 out.u[d] = a[k];
@@ -1185,8 +1191,9 @@ __global__ __launch_bounds__(kSwThreads) void k_compact_scatter_win(
                     if (key[k] < *p) atomicMin(p, (unsigned long long)key[k]);
                 }
                 if (!gb[k]) {
+                    const uint64_t kb = key[k] | (uint64_t)sh;
                     unsigned long long* p = &s_min[b[k] & (kSwSlots - 1)];
-                    if (key[k] < *p) atomicMin(p, (unsigned long long)key[k]);
+                    if (kb < *p) atomicMin(p, (unsigned long long)kb);
                 }
             }
             if (!ga[k]) a[k] = 0;
@@ -1202,8 +1209,9 @@ __global__ __launch_bounds__(kSwThreads) void k_compact_scatter_win(
         }
 #pragma unroll
         for (int k = 0; k < kIt; ++k) {
+            const uint64_t kb = key[k] | (uint64_t)sh;
             wave_min_commit(best_next, a[k], key[k], ga[k] && key[k] < ca[k]);
-            wave_min_commit(best_next, b[k], key[k], gb[k] && key[k] < cb[k]);
+            wave_min_commit(best_next, b[k], kb, gb[k] && kb < cb[k]);
         }
     }
     __syncthreads();
@@ -1291,11 +1299,13 @@ void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, cons
     int64_t hb = (nr + kHookBlock - 1) / kHookBlock;
     hb = hb < 1 ? 1 : (hb > 256 ? 256 : hb);
     const dim3 gr((unsigned)hb), bl(kHookBlock);
-    if (side_keys) {   // round 0 on the caller's arrays or a compact view: cmap is null
-        if (mode == kOrig)
-            hipLaunchKernelGGL((k_hook<kOrig, true>), gr, bl, 0, s, best, nr, g, nullptr, parent, mask, ctrl);
-        else
-            hipLaunchKernelGGL((k_hook<kCompact, true>), gr, bl, 0, s, best, nr, g, nullptr, parent, mask, ctrl);
+    if (side_keys) {
+        switch (mode) {
+            case kOrig: hipLaunchKernelGGL((k_hook<kOrig, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+            case kFull32: hipLaunchKernelGGL((k_hook<kFull32, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+            case kFull16: hipLaunchKernelGGL((k_hook<kFull16, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+            default: hipLaunchKernelGGL((k_hook<kCompact, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+        }
         return;
     }
     switch (mode) {
@@ -1442,7 +1452,7 @@ static bool allow_lds(size_t bytes) {
 template <int IN, int OUT, bool PAIR>
 static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* ou, int32_t* ov,
                           uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
-                          const uint64_t* pair_hot, Ctrl* ctrl, hipStream_t s) {
+                          const uint64_t* pair_hot, Ctrl* ctrl, int sh, hipStream_t s) {
     const bool lds_on = true;
     bool ldsb = false;
     int64_t km = 0;
@@ -1469,37 +1479,38 @@ static void pass_dispatch(const View& g, const int32_t* M, int64_t nc, int32_t* 
     const unsigned grid = (unsigned)(want < 1 ? 1 : (want > cap ? cap : want));
     const dim3 bl(kPassBlock);
     if (ldsb && km)
-        hipLaunchKernelGGL((k_pass<IN, OUT, true, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl, sh);
     else if (ldsb)
-        hipLaunchKernelGGL((k_pass<IN, OUT, false, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, true, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl, sh);
     else if (km)
-        hipLaunchKernelGGL((k_pass<IN, OUT, true, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, true, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl, sh);
     else
-        hipLaunchKernelGGL((k_pass<IN, OUT, false, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl);
+        hipLaunchKernelGGL((k_pass<IN, OUT, false, false, PAIR>), dim3(grid), bl, lds, s, g, M, nc, ou, ov, op16, best_next, nn, pairs, km, pair_hot, ctrl, sh);
 }
 
 // Streaming pass; returns false for a layout/output pair it does not support.
 // pairs != null: last pass before the tail (output kOutNone only).
 bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t nc, int32_t* ou,
                  int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
-                 const uint64_t* pair_hot, Ctrl* ctrl, hipStream_t s) {
+                 const uint64_t* pair_hot, Ctrl* ctrl, bool side_keys, hipStream_t s) {
     if (g.len <= 0) return true;
+    const int sh = side_keys ? 1 : 0;
     if (pairs) {
         if (out != kOutNone) return false;
         switch (in_mode) {
-            case kOrig: pass_dispatch<kOrig, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, s); return true;
-            case kFull32: pass_dispatch<kFull32, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, s); return true;
-            case kFull16: pass_dispatch<kFull16, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, s); return true;
-            default: pass_dispatch<kCompact, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, s); return true;
+            case kOrig: pass_dispatch<kOrig, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, sh, s); return true;
+            case kFull32: pass_dispatch<kFull32, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, sh, s); return true;
+            case kFull16: pass_dispatch<kFull16, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, sh, s); return true;
+            default: pass_dispatch<kCompact, kOutNone, true>(g, M, nc, ou, ov, op16, best_next, nn, pairs, pair_hot, ctrl, sh, s); return true;
         }
     }
     switch (in_mode * 3 + out) {
-        case kOrig * 3 + kOut32: pass_dispatch<kOrig, kOut32, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
-        case kOrig * 3 + kOut16: pass_dispatch<kOrig, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
-        case kFull32 * 3 + kOutNone: pass_dispatch<kFull32, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
-        case kFull32 * 3 + kOut16: pass_dispatch<kFull32, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
-        case kFull16 * 3 + kOutNone: pass_dispatch<kFull16, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
-        case kCompact * 3 + kOutNone: pass_dispatch<kCompact, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, s); return true;
+        case kOrig * 3 + kOut32: pass_dispatch<kOrig, kOut32, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, sh, s); return true;
+        case kOrig * 3 + kOut16: pass_dispatch<kOrig, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, sh, s); return true;
+        case kFull32 * 3 + kOutNone: pass_dispatch<kFull32, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, sh, s); return true;
+        case kFull32 * 3 + kOut16: pass_dispatch<kFull32, kOut16, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, sh, s); return true;
+        case kFull16 * 3 + kOutNone: pass_dispatch<kFull16, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, sh, s); return true;
+        case kCompact * 3 + kOutNone: pass_dispatch<kCompact, kOutNone, false>(g, M, nc, ou, ov, op16, best_next, nn, nullptr, nullptr, ctrl, sh, s); return true;
         default: return false;
     }
 }
@@ -1520,8 +1531,10 @@ static void launch_compact_flags(int in_mode, const View& g, const int32_t* M, u
 void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
                     uint64_t* best_next, int64_t nn, uint64_t* flags, uint64_t* cnt,
                     uint64_t* bsum, Ctrl* ctrl, int dedup, const uint64_t* dpair,
-                    const uint64_t* dmin, int64_t dslots, bool local, hipStream_t s) {
+                    const uint64_t* dmin, int64_t dslots, bool local, bool side_keys,
+                    hipStream_t s) {
     if (g.len <= 0) return;
+    const int sh = side_keys ? 1 : 0;
     const uint32_t nt = (uint32_t)((g.len + kRelabelTile - 1) / kRelabelTile);
     if (dedup == kDedupExact && dslots > 0)
         launch_compact_flags<kDedupExact>(in_mode, g, M, flags, cnt, nt, dpair, dmin, dslots, s);
@@ -1551,19 +1564,19 @@ void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
         const int64_t per = (nsteps + cap - 1) / cap;
         const dim3 gw((unsigned)((nsteps + per - 1) / per)), bw(kSwThreads);
         switch (in_mode) {
-            case kOrig: hipLaunchKernelGGL(k_compact_scatter_win<kOrig>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per); break;
-            case kFull32: hipLaunchKernelGGL(k_compact_scatter_win<kFull32>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per); break;
-            case kFull16: hipLaunchKernelGGL(k_compact_scatter_win<kFull16>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per); break;
-            default: hipLaunchKernelGGL(k_compact_scatter_win<kCompact>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per); break;
+            case kOrig: hipLaunchKernelGGL(k_compact_scatter_win<kOrig>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per, sh); break;
+            case kFull32: hipLaunchKernelGGL(k_compact_scatter_win<kFull32>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per, sh); break;
+            case kFull16: hipLaunchKernelGGL(k_compact_scatter_win<kFull16>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per, sh); break;
+            default: hipLaunchKernelGGL(k_compact_scatter_win<kCompact>, gw, bw, 0, s, g, M, flags, cnt, out, best_next, nt, nn, per, sh); break;
         }
         return;
     }
     const dim3 gr(nt < kCompactGrid ? nt : kCompactGrid), bl(kBlock);
     switch (in_mode) {
-        case kOrig: hipLaunchKernelGGL((k_compact_scatter<kOrig, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt); break;
-        case kFull32: hipLaunchKernelGGL((k_compact_scatter<kFull32, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt); break;
-        case kFull16: hipLaunchKernelGGL((k_compact_scatter<kFull16, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt); break;
-        default: hipLaunchKernelGGL((k_compact_scatter<kCompact, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt); break;
+        case kOrig: hipLaunchKernelGGL((k_compact_scatter<kOrig, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt, sh); break;
+        case kFull32: hipLaunchKernelGGL((k_compact_scatter<kFull32, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt, sh); break;
+        case kFull16: hipLaunchKernelGGL((k_compact_scatter<kFull16, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt, sh); break;
+        default: hipLaunchKernelGGL((k_compact_scatter<kCompact, true>), gr, bl, 0, s, g, M, flags, cnt, out, best_next, nt, sh); break;
     }
 }
 

@@ -64,7 +64,8 @@ void bucket_hot_first(const BucketBuffers& B, const int32_t* u, const int32_t* v
 // Relabel every edge through M (round-0 vertex -> next label), write the
 // OUT layout (kOut32 or kOut16; dead edges as (0, 0)), count the live edges
 // into ctrl->m_next and run the next round's lightest-edge search into
-// best_next[0, nn).  Uses the arcs of the last bucket_minedge call on the
+// best_next[0, nn), as side keys (w << 32 | position << 1 | side, side 1 at
+// the edge's v end).  Uses the arcs of the last bucket_minedge call on the
 // same edges.
 void bucket_relabel(const BucketBuffers& B, const uint32_t* w, int64_t m, int64_t n,
                     const int32_t* M, int out,

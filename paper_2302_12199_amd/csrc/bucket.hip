@@ -402,7 +402,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bk_label(
 // its two at the places recorded in rank[].  Then, as the plain relabelling
 // pass does: dead edges (self-loops, equal labels) are written as (0, 0),
 // live ones as label pairs, and take part in the next round's lightest-edge
-// search with key (w << 32 | position).
+// search with side keys (w << 32 | position << 1 | side, side 1 at the v end).
 template <int OUT>
 __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
     const uint32_t* __restrict__ w, int64_t m, uint32_t nb, uint32_t nt,
@@ -519,13 +519,14 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
                                 ra[i] = (int32_t)lx;
                                 rb[i] = (int32_t)ly;
                                 ++kept;
-                                key[i] = ((uint64_t)ww[j][k] << 32) | (uint64_t)e;
+                                // side keys: the v end's key has bit 0 set
+                                key[i] = ((uint64_t)ww[j][k] << 32) | ((uint64_t)e << 1);
                                 ax[i] = lx >= kh;
                                 ay[i] = ly >= kh;
                                 if (!ax[i] && key[i] < s_hmin[lx])
                                     atomicMin(&s_hmin[lx], (unsigned long long)key[i]);
-                                if (!ay[i] && key[i] < s_hmin[ly])
-                                    atomicMin(&s_hmin[ly], (unsigned long long)key[i]);
+                                if (!ay[i] && (key[i] | 1u) < s_hmin[ly])
+                                    atomicMin(&s_hmin[ly], (unsigned long long)(key[i] | 1u));
                             }
                         }
                     }
@@ -541,8 +542,9 @@ __global__ __launch_bounds__(kPassThreads) void k_bk_pass(
             }
 #pragma unroll
             for (int i = 0; i < kE; ++i) {
+                const uint64_t kb = key[i] | 1u;
                 wave_min_commit(best_next, ra[i], key[i], ax[i] && key[i] < cx[i]);
-                wave_min_commit(best_next, rb[i], key[i], ay[i] && key[i] < cy[i]);
+                wave_min_commit(best_next, rb[i], kb, ay[i] && kb < cy[i]);
             }
         }
         __syncthreads();   // the next tile reuses the LDS tables

@@ -138,11 +138,10 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
                               (B.dedup == MSF_DEDUP_AUTO && local)
                           ? kDedupLocal
                           : kDedupNone;
-    // The round-0 minima also say which end of its edge the vertex is (up to
-    // 2^31 positions: the position takes 31 bits, the side one), so the first
-    // hook reads only the other end.
-    const bool side_keys0 =
-        bucketed || ((mode == kOrig || mode == kCompact) && view.len <= kSideKeyMaxEdges);
+    // Every round's minima also say which end of its edge the vertex is (up
+    // to 2^31 positions: the position takes 31 bits, the side one), so the
+    // hook reads only the other end.  The bucketed path takes m < 2^31.
+    const bool side_keys = view.len <= kSideKeyMaxEdges;
     int h = -1;
     if (bucketed) {
         bucket_minedge(B.bk, view.u, view.v, view.w, view.len, nv, B.best[cur], dc, s);
@@ -152,7 +151,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         prof_end(h, s, 8.0 * nr);
         h = prof_begin(K_MINEDGE_R0, s);
         launch_minedge_r0(view.u, view.v, view.w, view.len, nv, B.best[cur], dc, hot, local,
-                          side_keys0, s);
+                          side_keys, s);
         prof_end(h, s, 12.0 * view.len + 8.0 * nv);
     }
     HIP_TRY(hipGetLastError());
@@ -167,12 +166,10 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
     bool m_pending = false, m_compacted = false;
     uint32_t rounds = stats ? stats->rounds : 0;
     const uint32_t first_round = rounds;
-    bool side_keys = side_keys0;
     while (m_live > 0 || m_pending) {
         launch_scan_prep(B.status, 0, dc, 1, s);
         const int hh = prof_begin(K_HOOK, s);
         launch_hook(mode, B.best[cur], nr, view, cmap, B.parent, mask, dc, side_keys, s);
-        side_keys = false;
         prof_end(hh, s, 12.0 * nr);
         int32_t* lab = B.lab[labsel];
         for (int attempt = 0;; ++attempt) {
@@ -270,7 +267,8 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             h = prof_begin(K_PASS, s);
             launch_fill_u64(B.pairs, slots, kKeyMax, s);
             if (!launch_pass(mode, kOutNone, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1],
-                             nn, B.pairs, pre_tail_hot ? &dc->aux[2] : nullptr, dc, s)) {
+                             nn, B.pairs, pre_tail_hot ? &dc->aux[2] : nullptr, dc, side_keys,
+                             s)) {
                 set_err_text("unsupported pass layout");
                 return MSF_EINTERNAL;
             }
@@ -316,7 +314,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             }
             h = prof_begin(K_COMPACT, s);
             launch_compact(mode, view, M, out, B.best[cur ^ 1], nn, B.cflags, B.status, B.cbsum,
-                           dc, dedup, B.dpair, B.dmin, B.dslots, local, s);
+                           dc, dedup, B.dpair, B.dmin, B.dslots, local, side_keys, s);
             prof_end(h, s, view_read_bytes(mode) * view.len + 8.0 * m_live);
             next.u = out.u; next.v = out.v; next.w = out.w; next.id = out.id; next.p16 = nullptr;
             next_mode = kCompact;
@@ -330,7 +328,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             } else {
                 h = prof_begin(mode == kOrig ? K_PASS_R0 : K_PASS, s);
                 if (!launch_pass(mode, out, view, M, nc, B.f32u, B.f32v, B.p16, B.best[cur ^ 1],
-                                 nn, nullptr, nullptr, dc, s)) {
+                                 nn, nullptr, nullptr, dc, side_keys, s)) {
                     set_err_text("unsupported pass layout");
                     return MSF_EINTERNAL;
                 }

@@ -19,8 +19,8 @@ constexpr int64_t kSideKeyMaxEdges = 1ll << 31;
 void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, int64_t m,
                        int64_t n, uint64_t* best, Ctrl* ctrl, int32_t hot, bool local,
                        bool side_keys, hipStream_t s);
-// side_keys: best[] holds w << 32 | position << 1 | side (round 0 on the
-// caller's arrays or a compact view, cmap null), else w << 32 | position.
+// side_keys: best[] holds w << 32 | position << 1 | side, else w << 32 |
+// position (the form every kernel that fills best[] was given).
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
                  int32_t* parent, uint8_t* mask, Ctrl* ctrl, bool side_keys, hipStream_t s);
 void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s);
@@ -30,9 +30,11 @@ void launch_label(const int32_t* parent, const uint64_t* best, int64_t nr, int32
                   uint64_t* best_next, const Ctrl* ctrl, hipStream_t s);
 void launch_compose(const int32_t* cmap, int64_t nc, const int32_t* label, int32_t* out,
                     hipStream_t s);
+// side_keys: the next round's minima as side keys (see launch_minedge_r0);
+// the pair table before the tail always holds w << 32 | position.
 bool launch_pass(int in_mode, int out, const View& g, const int32_t* M, int64_t nc, int32_t* ou,
                  int32_t* ov, uint32_t* op16, uint64_t* best_next, int64_t nn, uint64_t* pairs,
-                 const uint64_t* pair_hot, Ctrl* ctrl, hipStream_t s);
+                 const uint64_t* pair_hot, Ctrl* ctrl, bool side_keys, hipStream_t s);
 // Before the tail: this round's labels lab[0, nr) (values in [0, nn), nn <= the
 // tail's limit) renumbered hot first; *hot = the number of hot labels.
 void launch_hot_first_small(int mode, const View& g, const int32_t* cmap, int32_t* lab, int64_t nr,
@@ -49,12 +51,14 @@ void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_
 // (dpair, dmin; dslots entries, filled by launch_dedup_insert) holds for its pair.
 // flags: one bit per position (tiles of 2048 positions); cnt: a word per tile;
 // bsum: kScanTop words.  ctrl->m_next receives the number of kept edges.
-// best_next holds nn entries; local: the graph has id locality (the next
-// round's minima are then taken in a sliding LDS window of labels).
+// best_next holds nn entries (side keys when side_keys); local: the graph has
+// id locality (the next round's minima are then taken in a sliding LDS window
+// of labels).
 void launch_compact(int in_mode, const View& g, const int32_t* M, EdgeSoA out,
                     uint64_t* best_next, int64_t nn, uint64_t* flags, uint64_t* cnt,
                     uint64_t* bsum, Ctrl* ctrl, int dedup, const uint64_t* dpair,
-                    const uint64_t* dmin, int64_t dslots, bool local, hipStream_t s);
+                    const uint64_t* dmin, int64_t dslots, bool local, bool side_keys,
+                    hipStream_t s);
 // filter.hip: exclusive scan of per-tile counts in place (nt <= 2^21 tiles;
 // bsum holds kScanTop chunk sums), the total to *total.
 void launch_scan_tiles(uint64_t* cnt, uint32_t nt, uint64_t* bsum, uint64_t* total,
