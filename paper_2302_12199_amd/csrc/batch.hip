@@ -192,11 +192,16 @@ __device__ void chunk_hot_flush(uint64_t* best, const int32_t* s_hot,
     __syncthreads();
 }
 
+// Side keys (w << 32 | edge << 1 | side) for graphs of at most 2^31 edges:
+// the edge index takes 31 bits.
+__device__ __forceinline__ int side_keys(int64_t m) { return m <= (1ll << 31) ? 1 : 0; }
+
 // Lightest edge of every endpoint label over edges [lo, hi) of one graph,
 // kEdgeIlp independent edges per thread (all loads and label gathers of a
 // step issued before any is used).  Round 0 reads the ids directly (labels
 // are the ids) and validates them.  hot (or null): the block tier's labels,
-// their minima in s_hotmin; wave_min: the wave tier's threshold.
+// their minima in s_hotmin; wave_min: the wave tier's threshold; sh: side
+// keys (1) or w << 32 | edge (0).
 template <int BS>
 __device__ __forceinline__ void min_edges(const int32_t* __restrict__ U,
                                           const int32_t* __restrict__ V,
@@ -204,7 +209,7 @@ __device__ __forceinline__ void min_edges(const int32_t* __restrict__ U,
                                           int64_t n, int round, const int32_t* lab,
                                           uint64_t* best, int& any, bool& bad,
                                           const int32_t* s_hot, unsigned long long* s_hotmin,
-                                          int wave_min) {
+                                          int wave_min, int sh) {
     const int tid = threadIdx.x;
     int32_t hot[kHot];
 #pragma unroll
@@ -239,16 +244,17 @@ __device__ __forceinline__ void min_edges(const int32_t* __restrict__ U,
         // every lane's minimum reads first, then the atomics of the keys that
         // still lower them: the reads of a lane overlap instead of running one
         // after another
+        // sh = 1: side keys, the V end's key has bit 0 set (see hook_range)
         uint64_t key[kEdgeIlp], ca[kEdgeIlp], cb[kEdgeIlp];
         bool ax[kEdgeIlp], ay[kEdgeIlp];
 #pragma unroll
         for (int k = 0; k < kEdgeIlp; ++k) {
             const bool act = la[k] != lb[k];
             const int64_t e = base + k * BS + tid;
-            key[k] = ((uint64_t)wt[k] << 32) | (uint64_t)e;
+            key[k] = ((uint64_t)wt[k] << 32) | ((uint64_t)e << sh);
             if (act) any = 1;
             const bool hx = act && s_hot && hot_min(hot, s_hotmin, la[k], key[k]);
-            const bool hy = act && s_hot && hot_min(hot, s_hotmin, lb[k], key[k]);
+            const bool hy = act && s_hot && hot_min(hot, s_hotmin, lb[k], key[k] | (uint64_t)sh);
             ax[k] = act && !hx;
             ay[k] = act && !hy;
             ca[k] = ax[k] ? best[la[k]] : 0;
@@ -256,8 +262,9 @@ __device__ __forceinline__ void min_edges(const int32_t* __restrict__ U,
         }
 #pragma unroll
         for (int k = 0; k < kEdgeIlp; ++k) {
+            const uint64_t kb = key[k] | (uint64_t)sh;
             tier_commit(best, la[k], key[k], ax[k] && key[k] < ca[k], wave_min);
-            tier_commit(best, lb[k], key[k], ay[k] && key[k] < cb[k], wave_min);
+            tier_commit(best, lb[k], kb, ay[k] && kb < cb[k], wave_min);
         }
     }
 }
@@ -269,11 +276,15 @@ constexpr int kVtxIlp = 4;
 
 // Hook + MSF mark over labels [lo, hi): parent = other end of the lightest
 // edge; of a 2-cycle (same edge chosen by both) the smaller label is the root.
+// sh = 1: side keys (w << 32 | edge << 1 | side, side 1 when the label is
+// the edge's V end), so only the other end is read and mapped, and the other
+// end's key for the same edge has the side bit flipped; sh = 0: w << 32 |
+// edge, both ends read.
 __device__ __forceinline__ uint64_t hook_range(const int32_t* __restrict__ U,
                                                const int32_t* __restrict__ V, int64_t lo,
                                                int64_t hi, int stride, const int32_t* lab,
                                                const uint64_t* best, int32_t* par,
-                                               uint8_t* mask) {
+                                               uint8_t* mask, int sh) {
     uint64_t wsum = 0;
     for (int64_t x0 = lo + threadIdx.x; x0 < hi; x0 += (int64_t)stride * kVtxIlp) {
         uint64_t b[kVtxIlp], bo[kVtxIlp];
@@ -283,32 +294,43 @@ __device__ __forceinline__ uint64_t hook_range(const int32_t* __restrict__ U,
             const int64_t x = x0 + (int64_t)k * stride;
             b[k] = x < hi ? best[x] : kKeyMax;
         }
+        if (sh) {
 #pragma unroll
-        for (int k = 0; k < kVtxIlp; ++k) {
-            const uint32_t pos = (uint32_t)b[k];
-            la[k] = b[k] != kKeyMax ? U[pos] : 0;
-            lb[k] = b[k] != kKeyMax ? V[pos] : 0;
+            for (int k = 0; k < kVtxIlp; ++k) {
+                const uint32_t pos = (uint32_t)b[k] >> 1;
+                la[k] = b[k] != kKeyMax ? ((b[k] & 1u) ? U[pos] : V[pos]) : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kVtxIlp; ++k) other[k] = b[k] != kKeyMax ? lab[la[k]] : 0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kVtxIlp; ++k) {
+                const uint32_t pos = (uint32_t)b[k];
+                la[k] = b[k] != kKeyMax ? U[pos] : 0;
+                lb[k] = b[k] != kKeyMax ? V[pos] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kVtxIlp; ++k) {
+                la[k] = b[k] != kKeyMax ? lab[la[k]] : 0;
+                lb[k] = b[k] != kKeyMax ? lab[lb[k]] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kVtxIlp; ++k) {
+                const int64_t x = x0 + (int64_t)k * stride;
+                other[k] = la[k] == (int32_t)x ? lb[k] : la[k];
+            }
         }
 #pragma unroll
-        for (int k = 0; k < kVtxIlp; ++k) {
-            la[k] = b[k] != kKeyMax ? lab[la[k]] : 0;
-            lb[k] = b[k] != kKeyMax ? lab[lb[k]] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < kVtxIlp; ++k) {
-            const int64_t x = x0 + (int64_t)k * stride;
-            other[k] = la[k] == (int32_t)x ? lb[k] : la[k];
-            bo[k] = b[k] != kKeyMax ? best[other[k]] : 0;
-        }
+        for (int k = 0; k < kVtxIlp; ++k) bo[k] = b[k] != kKeyMax ? best[other[k]] : 0;
 #pragma unroll
         for (int k = 0; k < kVtxIlp; ++k) {
             const int64_t x = x0 + (int64_t)k * stride;
             if (x >= hi) continue;
-            if (b[k] == kKeyMax || (bo[k] == b[k] && (int32_t)x < other[k])) {
+            if (b[k] == kKeyMax || (bo[k] == (b[k] ^ (uint64_t)sh) && (int32_t)x < other[k])) {
                 par[x] = (int32_t)x;
             } else {
                 par[x] = other[k];
-                mask[(uint32_t)b[k]] = 1;
+                mask[(uint32_t)b[k] >> sh] = 1;
                 wsum += b[k] >> 32;
             }
         }
@@ -393,6 +415,7 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
     const bool bad_shape = n < 0 || n > cap || m < 0 || m > 0xffffffffLL;
     bool bad = bad_shape;
     uint64_t wsum = 0;
+    const int sh = side_keys(m);
     if (!bad_shape) {
         for (int64_t i = tid; i < m; i += BS) mask[i] = 0;
         for (int64_t x = tid; x < n; x += BS) lab[x] = (int32_t)x;
@@ -405,10 +428,10 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
             const bool block_tier = tiers && A.hot_min > 0;
             if (block_tier) chunk_hot<BS>(U, V, 0, m, n, round, lab, A.hot_min, s_hot, s_hotmin);
             min_edges<BS>(U, V, W, 0, m, n, round, lab, best, any, bad,
-                          block_tier ? s_hot : nullptr, s_hotmin, tiers ? A.wave_min : 0);
+                          block_tier ? s_hot : nullptr, s_hotmin, tiers ? A.wave_min : 0, sh);
             if (block_tier) chunk_hot_flush(best, s_hot, s_hotmin);
             if (!__syncthreads_or(any) || __syncthreads_or(bad)) break;
-            wsum += hook_range(U, V, 0, ncur, BS, lab, best, par, mask);
+            wsum += hook_range(U, V, 0, ncur, BS, lab, best, par, mask, sh);
             __syncthreads();
             for (int it = 0; it < kMaxJumps; ++it) {                   // pointer jumping
                 const int changed = jump_range(par, 0, ncur, BS) ? 1 : 0;
@@ -771,7 +794,8 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
                     chunk_hot<BS>(U, V, e0, eh, P.n, (int)P.round, S.lab, A.hot_min, s_hot,
                                   s_hotmin);
                 min_edges<BS>(U, V, W, e0, eh, P.n, (int)P.round, S.lab, S.best, any, bad,
-                              block_tier ? s_hot : nullptr, s_hotmin, A.wave_min);
+                              block_tier ? s_hot : nullptr, s_hotmin, A.wave_min,
+                              side_keys(P.m));
                 if (block_tier) chunk_hot_flush(S.best, s_hot, s_hotmin);
             }
             const int bany = __syncthreads_or(any), bbad = __syncthreads_or(bad);
@@ -782,8 +806,11 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
             break;
         }
         case C_HOOK: {
+            // the pair table's keys (w << 32 | edge) carry no side
             const uint64_t ws = block_sum_u64<BS>(
-                hook_range(U, V, v0, vn, BS, S.lab, S.best, S.par, mask), s_red);
+                hook_range(U, V, v0, vn, BS, S.lab, S.best, S.par, mask,
+                           P.pair_mode ? 0 : side_keys(P.m)),
+                s_red);
             if (tid == 0 && ws) atomicAdd((unsigned long long*)&X->total, (unsigned long long)ws);
             break;
         }
