@@ -40,7 +40,7 @@ constexpr uint32_t kNotReady = 0xffffffffu;       // phase id before the first s
 constexpr uint64_t kWaitTicks = 200000000ull;     // 2 s of the 100 MHz wall clock
 
 enum CoopKind : uint32_t {
-    C_NONE = 0, C_INIT, C_FILL, C_MINEDGE, C_HOOK, C_JUMP, C_COUNT, C_IDS, C_COMPOSE, C_PFILL,
+    C_NONE = 0, C_INIT, C_MINEDGE, C_HOOK, C_JUMP, C_COUNT, C_IDS, C_COMPOSE, C_PFILL,
     C_PBUILD, C_DONE
 };
 
@@ -338,54 +338,68 @@ __device__ __forceinline__ uint64_t hook_range(const int32_t* __restrict__ U,
     return wsum;
 }
 
-// One pointer-jumping step over [lo, hi): par[x] <- par[par[x]]; true if any
-// entry changed.
+// Pointer jumping over [lo, hi): each vertex walks up its parent chain, at
+// most kWalkSteps steps, and keeps the furthest vertex reached as its
+// parent (the root when the walk ends there).  Parents only ever move towards
+// the root, so reading entries that others update meanwhile is harmless.
+// True if some walk stopped short of its root (another pass is needed).
+constexpr int kWalkSteps = 32;
 __device__ __forceinline__ bool jump_range(int32_t* par, int64_t lo, int64_t hi, int stride) {
-    bool changed = false;
+    bool cut = false;
     for (int64_t x0 = lo + threadIdx.x; x0 < hi; x0 += (int64_t)stride * kVtxIlp) {
-        int32_t p[kVtxIlp], pp[kVtxIlp];
+        int32_t p[kVtxIlp], p0[kVtxIlp];
+        bool walk[kVtxIlp];
 #pragma unroll
         for (int k = 0; k < kVtxIlp; ++k) {
             const int64_t x = x0 + (int64_t)k * stride;
             p[k] = x < hi ? par[x] : 0;
+            p0[k] = p[k];
+            walk[k] = x < hi && p[k] != (int32_t)x;
         }
+        for (int step = 0; step < kWalkSteps; ++step) {   // the lane's walks in lockstep
+            int32_t pp[kVtxIlp];
+            bool more = false;
 #pragma unroll
-        for (int k = 0; k < kVtxIlp; ++k) {
-            const int64_t x = x0 + (int64_t)k * stride;
-            pp[k] = x < hi ? par[p[k]] : p[k];
-        }
+            for (int k = 0; k < kVtxIlp; ++k) pp[k] = walk[k] ? par[p[k]] : p[k];
 #pragma unroll
-        for (int k = 0; k < kVtxIlp; ++k) {
-            const int64_t x = x0 + (int64_t)k * stride;
-            if (x < hi && p[k] != pp[k]) {
-                par[x] = pp[k];
-                changed = true;
+            for (int k = 0; k < kVtxIlp; ++k) {
+                if (!walk[k]) continue;
+                if (pp[k] == p[k]) {
+                    walk[k] = false;                       // p[k] is the root
+                } else {
+                    p[k] = pp[k];
+                    more = true;
+                }
             }
+            if (!more) break;
+        }
+#pragma unroll
+        for (int k = 0; k < kVtxIlp; ++k) {
+            const int64_t x = x0 + (int64_t)k * stride;
+            if (x < hi && p[k] != p0[k]) par[x] = p[k];
+            if (walk[k]) cut = true;
         }
     }
-    return changed;
+    return cut;
 }
 
-// Label composition over [lo, hi): a label whose component found no edge is
-// done (-1), any other becomes the new id of its component's root.
-__device__ __forceinline__ void compose_range(int32_t* lab, const uint64_t* best,
-                                              const int32_t* par, const int32_t* nid,
-                                              int64_t lo, int64_t hi, int stride) {
+// Label composition over [lo, hi): each label becomes nid of its component's
+// root, the new id (the ids pass gives a root whose component found no edge
+// nid -1: that label is done).
+__device__ __forceinline__ void compose_range(int32_t* lab, const int32_t* par,
+                                              const int32_t* nid, int64_t lo, int64_t hi,
+                                              int stride) {
     for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (int64_t)stride * kVtxIlp) {
         int32_t l[kVtxIlp], r[kVtxIlp];
-        uint64_t bl[kVtxIlp];
 #pragma unroll
         for (int k = 0; k < kVtxIlp; ++k) {
             const int64_t i = i0 + (int64_t)k * stride;
             l[k] = i < hi ? lab[i] : -1;
         }
 #pragma unroll
-        for (int k = 0; k < kVtxIlp; ++k) {
-            bl[k] = l[k] >= 0 ? best[l[k]] : kKeyMax;
-            r[k] = l[k] >= 0 ? par[l[k]] : 0;
-        }
+        for (int k = 0; k < kVtxIlp; ++k) r[k] = l[k] >= 0 ? par[l[k]] : 0;
 #pragma unroll
-        for (int k = 0; k < kVtxIlp; ++k) r[k] = l[k] >= 0 && bl[k] != kKeyMax ? nid[r[k]] : -1;
+        for (int k = 0; k < kVtxIlp; ++k) r[k] = l[k] >= 0 ? nid[r[k]] : -1;
 #pragma unroll
         for (int k = 0; k < kVtxIlp; ++k) {
             const int64_t i = i0 + (int64_t)k * stride;
@@ -418,12 +432,13 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
     const int sh = side_keys(m);
     if (!bad_shape) {
         for (int64_t i = tid; i < m; i += BS) mask[i] = 0;
-        for (int64_t x = tid; x < n; x += BS) lab[x] = (int32_t)x;
+        for (int64_t x = tid; x < n; x += BS) {
+            lab[x] = (int32_t)x;
+            best[x] = kKeyMax;
+        }
         int64_t ncur = n;
         __syncthreads();
         for (int round = 0; round < kBatchMaxRounds && ncur > 1; ++round) {
-            for (int64_t x = tid; x < ncur; x += BS) best[x] = kKeyMax;
-            __syncthreads();
             int any = 0;
             const bool block_tier = tiers && A.hot_min > 0;
             if (block_tier) chunk_hot<BS>(U, V, 0, m, n, round, lab, A.hot_min, s_hot, s_hotmin);
@@ -440,14 +455,17 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
             int64_t roots = 0;                                         // dense ids of roots
             for (int64_t base = 0; base < ncur; base += BS) {
                 const int64_t x = base + tid;
-                const bool r = x < ncur && par[x] == (int32_t)x && best[x] != kKeyMax;
+                const bool self = x < ncur && par[x] == (int32_t)x;
+                const bool r = self && best[x] != kKeyMax;
                 uint32_t tot;
                 const uint32_t rk = block_rank<BS>(r, s_wave, &tot);
                 if (r) nid[x] = (int32_t)(roots + rk);
+                else if (self) nid[x] = -1;                             // no edge: done
                 roots += tot;
             }
             __syncthreads();
-            compose_range(lab, best, par, nid, 0, n, BS);              // compose labels
+            compose_range(lab, par, nid, 0, n, BS);                    // compose labels
+            for (int64_t x = tid; x < roots; x += BS) best[x] = kKeyMax;   // next round
             ncur = roots;
             __syncthreads();
         }
@@ -662,13 +680,7 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
     switch (kind) {
         case C_INIT:
             if (X->ncur <= 1 || X->m == 0) coop_finish<BS>(A, X, q, false);
-            else coop_setup(X, q, C_FILL, chunks_of(X->ncur, CV));
-            break;
-        case C_FILL:
-            if (X->pair_mode)
-                coop_setup(X, q, C_MINEDGE, chunks_of(X->pn * (X->pn - 1) / 2, CP));
-            else
-                coop_setup(X, q, C_MINEDGE, chunks_of(X->m, CE));
+            else coop_setup(X, q, C_MINEDGE, chunks_of(X->m, CE));
             break;
         case C_MINEDGE: {
             const uint32_t any = X->f_any, bad = X->f_bad;
@@ -708,7 +720,7 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
             coop_setup(X, q, C_COMPOSE, cn > cp ? cn : cp);
             break;
         }
-        case C_COMPOSE:
+        case C_COMPOSE:   // the compose phase also cleared the next round's minima
             X->ncur = X->nnext;
             X->round += 1;
             if (X->ncur <= 1 || X->round >= (uint32_t)kBatchMaxRounds) {
@@ -719,8 +731,10 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
                 const uint32_t cs = chunks_of(X->pn * (X->pn - 1) / 2, CP);
                 const uint32_t cv = chunks_of(X->pn, CV);
                 coop_setup(X, q, C_PFILL, cs > cv ? cs : cv);
+            } else if (X->pair_mode) {
+                coop_setup(X, q, C_MINEDGE, chunks_of(X->pn * (X->pn - 1) / 2, CP));
             } else {
-                coop_setup(X, q, C_FILL, chunks_of(X->ncur, CV));
+                coop_setup(X, q, C_MINEDGE, chunks_of(X->m, CE));
             }
             break;
         case C_PFILL:
@@ -728,7 +742,7 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
             break;
         case C_PBUILD:
             X->pair_mode = 1;
-            coop_setup(X, q, C_FILL, chunks_of(X->ncur, CV));
+            coop_setup(X, q, C_MINEDGE, chunks_of(X->pn * (X->pn - 1) / 2, CP));
             break;
         default:
             break;
@@ -736,7 +750,7 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
 }
 
 struct CoopParams {
-    int64_t g, n, m, ncur, e0, pn;
+    int64_t g, n, m, ncur, nnext, e0, pn;
     uint32_t kind, nchunks, round, pair_mode;
 };
 
@@ -760,12 +774,12 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
             const int64_t eh = e0 + CE < P.m ? e0 + CE : P.m;
             for (int64_t i = e0 + tid; i < eh; i += BS) mask[i] = 0;
             const int64_t xh = v0 + CV < P.n ? v0 + CV : P.n;
-            for (int64_t x = v0 + tid; x < xh; x += BS) S.lab[x] = (int32_t)x;
+            for (int64_t x = v0 + tid; x < xh; x += BS) {
+                S.lab[x] = (int32_t)x;
+                S.best[x] = kKeyMax;
+            }
             break;
         }
-        case C_FILL:
-            for (int64_t x = v0 + tid; x < vn; x += BS) S.best[x] = kKeyMax;
-            break;
         case C_MINEDGE: {
             int any = 0;
             bool bad = false;
@@ -835,20 +849,24 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
             int64_t roots = S.cnt[chunk];
             for (int64_t base = v0; base < v0 + CV; base += BS) {
                 const int64_t x = base + tid;
-                const bool rt = x < vn && S.par[x] == (int32_t)x && S.best[x] != kKeyMax;
+                const bool self = x < vn && S.par[x] == (int32_t)x;
+                const bool rt = self && S.best[x] != kKeyMax;
                 uint32_t tot;
                 const uint32_t rk = block_rank<BS>(rt, s_wave, &tot);
                 if (rt) S.nid[x] = (int32_t)(roots + rk);
+                else if (self) S.nid[x] = -1;           // no edge: its labels are done
                 roots += tot;
             }
             break;
         }
-        case C_COMPOSE: {
+        case C_COMPOSE: {   // compose reads no minimum: the next round's are cleared here
             const int64_t xh = v0 + CV < P.n ? v0 + CV : P.n;
-            compose_range(S.lab, S.best, S.par, S.nid, v0, xh, BS);
+            compose_range(S.lab, S.par, S.nid, v0, xh, BS);
+            const int64_t bh = v0 + CV < P.nnext ? v0 + CV : P.nnext;
+            for (int64_t x = v0 + tid; x < bh; x += BS) S.best[x] = kKeyMax;
             if (P.pair_mode) {
                 const int64_t ph = v0 + CV < P.pn ? v0 + CV : P.pn;
-                compose_range(S.plab, S.best, S.par, S.nid, v0, ph, BS);
+                compose_range(S.plab, S.par, S.nid, v0, ph, BS);
             }
             break;
         }
@@ -923,6 +941,7 @@ __device__ void coop_run(const BatchArgs& A, uint32_t* s_wave, uint64_t* s_red, 
                 s_p.n = X->n;
                 s_p.m = X->m;
                 s_p.ncur = X->ncur;
+                s_p.nnext = X->nnext;
                 s_p.round = X->round;
                 s_p.pn = X->pn;
                 s_p.pair_mode = X->pair_mode;
