@@ -40,7 +40,7 @@ constexpr uint32_t kNotReady = 0xffffffffu;       // phase id before the first s
 constexpr uint64_t kWaitTicks = 200000000ull;     // 2 s of the 100 MHz wall clock
 
 enum CoopKind : uint32_t {
-    C_NONE = 0, C_INIT, C_MINEDGE, C_HOOK, C_JUMP, C_COUNT, C_IDS, C_COMPOSE, C_PFILL,
+    C_NONE = 0, C_INIT, C_MINEDGE, C_HOOK, C_JUMP, C_IDS, C_COMPOSE, C_PFILL,
     C_PBUILD, C_DONE
 };
 
@@ -279,12 +279,13 @@ constexpr int kVtxIlp = 4;
 // sh = 1: side keys (w << 32 | edge << 1 | side, side 1 when the label is
 // the edge's V end), so only the other end is read and mapped, and the other
 // end's key for the same edge has the side bit flipped; sh = 0: w << 32 |
-// edge, both ends read.
+// edge, both ends read.  *roots counts the roots that found an edge (the
+// next round's labels).
 __device__ __forceinline__ uint64_t hook_range(const int32_t* __restrict__ U,
                                                const int32_t* __restrict__ V, int64_t lo,
                                                int64_t hi, int stride, const int32_t* lab,
                                                const uint64_t* best, int32_t* par,
-                                               uint8_t* mask, int sh) {
+                                               uint8_t* mask, int sh, uint32_t* roots) {
     uint64_t wsum = 0;
     for (int64_t x0 = lo + threadIdx.x; x0 < hi; x0 += (int64_t)stride * kVtxIlp) {
         uint64_t b[kVtxIlp], bo[kVtxIlp];
@@ -328,6 +329,7 @@ __device__ __forceinline__ uint64_t hook_range(const int32_t* __restrict__ U,
             if (x >= hi) continue;
             if (b[k] == kKeyMax || (bo[k] == (b[k] ^ (uint64_t)sh) && (int32_t)x < other[k])) {
                 par[x] = (int32_t)x;
+                if (b[k] != kKeyMax) ++*roots;
             } else {
                 par[x] = other[k];
                 mask[(uint32_t)b[k] >> sh] = 1;
@@ -446,7 +448,8 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
                           block_tier ? s_hot : nullptr, s_hotmin, tiers ? A.wave_min : 0, sh);
             if (block_tier) chunk_hot_flush(best, s_hot, s_hotmin);
             if (!__syncthreads_or(any) || __syncthreads_or(bad)) break;
-            wsum += hook_range(U, V, 0, ncur, BS, lab, best, par, mask, sh);
+            uint32_t nroot_unused = 0;
+            wsum += hook_range(U, V, 0, ncur, BS, lab, best, par, mask, sh, &nroot_unused);
             __syncthreads();
             for (int it = 0; it < kMaxJumps; ++it) {                   // pointer jumping
                 const int changed = jump_range(par, 0, ncur, BS) ? 1 : 0;
@@ -697,13 +700,12 @@ __device__ void coop_transition(const BatchArgs& A, XcdWork* X, const SlotView& 
         case C_JUMP: {
             const uint32_t changed = X->f_changed;
             X->f_changed = 0;
-            if (changed && ++X->jit < (uint32_t)kMaxJumps)
+            if (changed && ++X->jit < (uint32_t)kMaxJumps) {
                 coop_setup(X, q, C_JUMP, chunks_of(X->ncur, CV));
-            else
-                coop_setup(X, q, C_COUNT, chunks_of(X->ncur, CV));
-            break;
-        }
-        case C_COUNT: {
+                break;
+            }
+            // the roots counted per chunk by the hook phase: their exclusive
+            // prefix, the first id of each chunk's roots
             const uint32_t nch = chunks_of(X->ncur, CV);
             uint64_t sum = 0;
             for (uint32_t c = 0; c < nch; ++c) {
@@ -819,30 +821,23 @@ __device__ void coop_chunk(const BatchArgs& A, XcdWork* X, const SlotView& S,
             }
             break;
         }
-        case C_HOOK: {
+        case C_HOOK: {   // also counts the chunk's roots (jumping leaves roots as they are)
             // the pair table's keys (w << 32 | edge) carry no side
+            uint32_t nr = 0;
             const uint64_t ws = block_sum_u64<BS>(
                 hook_range(U, V, v0, vn, BS, S.lab, S.best, S.par, mask,
-                           P.pair_mode ? 0 : side_keys(P.m)),
+                           P.pair_mode ? 0 : side_keys(P.m), &nr),
                 s_red);
-            if (tid == 0 && ws) atomicAdd((unsigned long long*)&X->total, (unsigned long long)ws);
+            const uint64_t rc = block_sum_u64<BS>(nr, s_red);
+            if (tid == 0) {
+                if (ws) atomicAdd((unsigned long long*)&X->total, (unsigned long long)ws);
+                S.cnt[chunk] = (uint32_t)rc;
+            }
             break;
         }
         case C_JUMP: {
             const int changed = jump_range(S.par, v0, vn, BS) ? 1 : 0;
             if (__syncthreads_or(changed) && tid == 0) atomicOr(&X->f_changed, 1u);
-            break;
-        }
-        case C_COUNT: {
-            uint32_t c = 0;
-            for (int64_t base = v0; base < v0 + CV; base += BS) {
-                const int64_t x = base + tid;
-                const bool rt = x < vn && S.par[x] == (int32_t)x && S.best[x] != kKeyMax;
-                uint32_t tot;
-                (void)block_rank<BS>(rt, s_wave, &tot);
-                c += tot;
-            }
-            if (tid == 0) S.cnt[chunk] = c;
             break;
         }
         case C_IDS: {
