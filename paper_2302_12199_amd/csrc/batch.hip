@@ -192,6 +192,14 @@ __device__ void chunk_hot_flush(uint64_t* best, const int32_t* s_hot,
     __syncthreads();
 }
 
+// Labels whose pair table (8 B per pair), minima (8 B) and pair-label map
+// (4 B) fit `bytes` of LDS: the largest p with 4 p (p - 1) + 12 p <= bytes.
+__device__ __forceinline__ int64_t pair_labels(int64_t bytes) {
+    int64_t p = (int64_t)sqrt((double)bytes / 4.0) + 2;
+    while (p > 0 && 4 * p * (p - 1) + 12 * p > bytes) --p;
+    return p;
+}
+
 // Side keys (w << 32 | edge << 1 | side) for graphs of at most 2^31 edges:
 // the edge index takes 31 bits.
 __device__ __forceinline__ int side_keys(int64_t m) { return m <= (1ll << 31) ? 1 : 0; }
@@ -415,10 +423,15 @@ __device__ __forceinline__ void compose_range(int32_t* lab, const int32_t* par,
 // State arrays of `cap` vertices (LDS or a global slot).
 // tiers: the state is in global memory (the slot), so the block and wave
 // tiers of the lightest-edge search apply; in LDS every update is cheap.
+// pair_lds (or null), pair_bytes: LDS the state does not use.  Once at most
+// pair_labels(pair_bytes) labels are left and their pairs are fewer than half
+// the edges, the edges are reduced to the lightest edge of each label pair
+// (a triangular table in that LDS) and the remaining rounds scan the table.
 template <int BS>
 __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t* lab,
                             uint64_t* best, int32_t* par, int32_t* nid, uint32_t* s_wave,
-                            bool tiers, int32_t* s_hot, unsigned long long* s_hotmin) {
+                            bool tiers, int32_t* s_hot, unsigned long long* s_hotmin,
+                            unsigned long long* pair_lds, int64_t pair_bytes) {
     const int tid = threadIdx.x;
     const int64_t e0 = A.eoff[g];
     const int64_t m = A.eoff[g + 1] - e0;
@@ -432,6 +445,10 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
     bool bad = bad_shape;
     uint64_t wsum = 0;
     const int sh = side_keys(m);
+    const int64_t pmax = pair_lds ? pair_labels(pair_bytes) : 0;
+    int64_t pn = 0;                          // > 0: the rounds scan the pair table of pn labels
+    unsigned long long* pbest = nullptr;     // pair rounds: this round's minima, in LDS
+    int32_t* plab = nullptr;                 // pair-table label -> current label
     if (!bad_shape) {
         for (int64_t i = tid; i < m; i += BS) mask[i] = 0;
         for (int64_t x = tid; x < n; x += BS) {
@@ -442,14 +459,36 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
         __syncthreads();
         for (int round = 0; round < kBatchMaxRounds && ncur > 1; ++round) {
             int any = 0;
-            const bool block_tier = tiers && A.hot_min > 0;
-            if (block_tier) chunk_hot<BS>(U, V, 0, m, n, round, lab, A.hot_min, s_hot, s_hotmin);
-            min_edges<BS>(U, V, W, 0, m, n, round, lab, best, any, bad,
-                          block_tier ? s_hot : nullptr, s_hotmin, tiers ? A.wave_min : 0, sh);
-            if (block_tier) chunk_hot_flush(best, s_hot, s_hotmin);
+            if (pn) {                        // minima over the pair table, in LDS
+                for (int64_t x = tid; x < ncur; x += BS) pbest[x] = kKeyMax;
+                __syncthreads();
+                const int64_t np = pn * (pn - 1) / 2;
+                for (int64_t s = tid; s < np; s += BS) {
+                    const uint64_t key = pair_lds[s];
+                    if (key == kKeyMax) continue;
+                    int32_t lo, hi;
+                    tri_pair(s, lo, hi);
+                    const int32_t lx = plab[lo], ly = plab[hi];
+                    if (lx == ly) continue;
+                    any = 1;
+                    if (key < pbest[lx]) atomicMin(&pbest[lx], (unsigned long long)key);
+                    if (key < pbest[ly]) atomicMin(&pbest[ly], (unsigned long long)key);
+                }
+                __syncthreads();
+                for (int64_t x = tid; x < ncur; x += BS) best[x] = pbest[x];
+            } else {
+                const bool block_tier = tiers && A.hot_min > 0;
+                if (block_tier)
+                    chunk_hot<BS>(U, V, 0, m, n, round, lab, A.hot_min, s_hot, s_hotmin);
+                min_edges<BS>(U, V, W, 0, m, n, round, lab, best, any, bad,
+                              block_tier ? s_hot : nullptr, s_hotmin, tiers ? A.wave_min : 0,
+                              sh);
+                if (block_tier) chunk_hot_flush(best, s_hot, s_hotmin);
+            }
             if (!__syncthreads_or(any) || __syncthreads_or(bad)) break;
-            uint32_t nroot_unused = 0;
-            wsum += hook_range(U, V, 0, ncur, BS, lab, best, par, mask, sh, &nroot_unused);
+            uint32_t nroot_unused = 0;   // the pair table's keys (w << 32 | edge) carry no side
+            wsum += hook_range(U, V, 0, ncur, BS, lab, best, par, mask, pn ? 0 : sh,
+                               &nroot_unused);
             __syncthreads();
             for (int it = 0; it < kMaxJumps; ++it) {                   // pointer jumping
                 const int changed = jump_range(par, 0, ncur, BS) ? 1 : 0;
@@ -468,9 +507,31 @@ __device__ void solve_graph(const BatchArgs& A, int64_t g, int64_t cap, int32_t*
             }
             __syncthreads();
             compose_range(lab, par, nid, 0, n, BS);                    // compose labels
+            if (pn) compose_range(plab, par, nid, 0, pn, BS);
             for (int64_t x = tid; x < roots; x += BS) best[x] = kKeyMax;   // next round
             ncur = roots;
             __syncthreads();
+            if (!pn && ncur >= 2 && ncur <= pmax && ncur * (ncur - 1) / 2 < m / 2) {
+                // the lightest edge of each pair of the ncur labels; pair-table
+                // label i is label i now
+                pn = ncur;
+                const int64_t np = pn * (pn - 1) / 2;
+                pbest = pair_lds + np;
+                plab = reinterpret_cast<int32_t*>(pbest + pn);
+                for (int64_t s = tid; s < np; s += BS) pair_lds[s] = kKeyMax;
+                for (int64_t i = tid; i < pn; i += BS) plab[i] = (int32_t)i;
+                __syncthreads();
+                for (int64_t e = tid; e < m; e += BS) {
+                    const int32_t a = U[e], b = V[e];
+                    if (a == b) continue;
+                    const int32_t la = lab[a], lb = lab[b];
+                    if (la == lb || la < 0 || lb < 0) continue;
+                    const uint64_t key = ((uint64_t)W[e] << 32) | (uint64_t)e;
+                    unsigned long long* p = &pair_lds[tri_slot(la, lb)];
+                    if (key < *p) atomicMin(p, (unsigned long long)key);
+                }
+                __syncthreads();
+            }
         }
     }
     wsum = wave_sum_u64(wsum);
@@ -1000,10 +1061,10 @@ __global__ __launch_bounds__(BS) void k_batch(BatchArgs A) {
         if (A.voff[g + 1] - A.voff[g] <= cap) {
             int32_t* lab = reinterpret_cast<int32_t*>(lds + cap);
             solve_graph<BS>(A, g, cap, lab, lds, lab + cap, lab + 2 * cap, s_wave, false, s_hot,
-                            s_hotmin);
-        } else {
+                            s_hotmin, nullptr, 0);
+        } else {   // the state is in the slot: the LDS holds the pair table
             solve_graph<BS>(A, g, A.nmax, G.lab, G.best, G.par, G.nid, s_wave, true, s_hot,
-                            s_hotmin);
+                            s_hotmin, reinterpret_cast<unsigned long long*>(lds), cap * 20);
         }
     }
 
