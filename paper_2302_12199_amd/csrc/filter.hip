@@ -88,6 +88,57 @@ __device__ __forceinline__ void bitonic_stage(T* a, int n, int k, int j) {
     }
 }
 
+// Ascending bitonic sort of a[0, kRegSort) in LDS by the whole workgroup:
+// thread t keeps elements 4t .. 4t + 3 in registers.  Stages whose partner is
+// in the same thread run in registers, those with a partner in another lane
+// of the wave by lane shuffles, and only the stages that cross waves (partner
+// distance >= 4 * kWave) go through LDS, with workgroup barriers.
+constexpr int kRegSort = 4 * kSampleThreads;
+template <typename T>
+__device__ __forceinline__ void cmpx(T& a, T& b, bool up) {
+    if ((a > b) == up) { const T t = a; a = b; b = t; }
+}
+template <typename T>
+__device__ __forceinline__ void bitonic_sort_regs(T* a) {
+    const int t = threadIdx.x;
+    T x[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = a[4 * t + r];
+    for (int k = 2; k <= kRegSort; k <<= 1) {
+        int j = k >> 1;
+        if (j >= 4 * kWave) {                      // partners in other waves: LDS
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[4 * t + r] = x[r];
+            __syncthreads();
+            for (; j >= 4 * kWave; j >>= 1) {
+                bitonic_stage(a, kRegSort, k, j);
+                __syncthreads();
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x[r] = a[4 * t + r];
+        }
+        for (; j >= 4; j >>= 1) {                  // partner in lane t ^ (j / 4)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * t + r;
+                const T y = __shfl_xor(x[r], j / 4, kWave);
+                const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                x[r] = keep_min ? (y < x[r] ? y : x[r]) : (y < x[r] ? x[r] : y);
+            }
+        }
+        const bool up0 = ((4 * t) & k) == 0, up2 = ((4 * t + 2) & k) == 0;
+        if (j == 2) {                              // partners in this thread
+            cmpx(x[0], x[2], up0);
+            cmpx(x[1], x[3], up0);
+            j = 1;
+        }
+        cmpx(x[0], x[1], up0);
+        cmpx(x[2], x[3], up2);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[4 * t + r] = x[r];
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kSampleThreads) void k_sample_pivot(View g, uint64_t base,
                                                                  int sample, float q,
@@ -127,13 +178,18 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_pivot(View g, uint64_
     // only stages that cross waves, and the stages right before them, need the
     // workgroup barrier; the others only drain the wave's LDS operations.
     const int kmax = p2 > e2 ? p2 : e2;
-    for (int k = 2; k <= kmax; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (k <= p2) bitonic_stage(keys, p2, k, j);
-            if (k <= e2) bitonic_stage(ends, e2, k, j);
-            const int next_j = j > 1 ? j >> 1 : k;       // first stage of the next k is j = k
-            if (j >= kWave || next_j >= kWave) __syncthreads();
-            else asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    if (p2 == kRegSort && e2 == kRegSort) {          // the default sample of 4096
+        bitonic_sort_regs(keys);
+        bitonic_sort_regs(ends);
+    } else {
+        for (int k = 2; k <= kmax; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                if (k <= p2) bitonic_stage(keys, p2, k, j);
+                if (k <= e2) bitonic_stage(ends, e2, k, j);
+                const int next_j = j > 1 ? j >> 1 : k;   // first stage of the next k is j = k
+                if (j >= kWave || next_j >= kWave) __syncthreads();
+                else asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            }
         }
     }
     __syncthreads();
