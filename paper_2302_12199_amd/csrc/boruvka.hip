@@ -314,19 +314,29 @@ __global__ __launch_bounds__(kWinThreads) void k_minedge_win(
 // the view's stored labels to this round's labels (null: identity).  SIDE:
 // the keys are w << 32 | position << 1 | side (side 1: x is the edge's v
 // end), so only the other end is read, and the other end's key for the same
-// edge has the opposite side bit.
+// edge has the opposite side bit.  rootbits / livebits: bit x of word x / 64
+// says whether x is a root that found an edge / found an edge at all (the
+// root scan and the labelling read these instead of parent[] and best[]).
 constexpr int kHookBlock = 1024;
 template <int MODE, bool SIDE>
 __global__ __launch_bounds__(kHookBlock) void k_hook(const uint64_t* __restrict__ best, int64_t nr,
                                                  View g, const int32_t* __restrict__ cmap,
                                                  int32_t* __restrict__ parent,
-                                                 uint8_t* __restrict__ mask, Ctrl* ctrl) {
+                                                 uint8_t* __restrict__ mask,
+                                                 uint64_t* __restrict__ rootbits,
+                                                 uint64_t* __restrict__ livebits, Ctrl* ctrl) {
     uint64_t wsum = 0, nfound = 0, nlive = 0;
     bool bad = false;
+    // a wave's lanes take 64 consecutive vertices from a multiple of 64 (the
+    // block size and the grid stride are multiples of 64), so lane 0 writes
+    // the wave's root and live bits as one word each
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nr;
          x += (int64_t)gridDim.x * blockDim.x) {
+        bool live = false, root = false;
+        do {
         const uint64_t b = best[x];
-        if (b == kKeyMax) { parent[x] = (int32_t)x; continue; }
+        if (b == kKeyMax) { parent[x] = (int32_t)x; break; }
+        live = true;
         ++nlive;
         uint32_t pos;
         int32_t other;
@@ -359,14 +369,21 @@ __global__ __launch_bounds__(kHookBlock) void k_hook(const uint64_t* __restrict_
             if (eu != x && ev != x) bad = true;
             other = eu == (int32_t)x ? ev : eu;
         }
-        if ((uint32_t)other >= (uint64_t)nr) { bad = true; parent[x] = (int32_t)x; continue; }
+        if ((uint32_t)other >= (uint64_t)nr) { bad = true; parent[x] = (int32_t)x; break; }
         if (best[other] == (SIDE ? b ^ 1u : b) && (int32_t)x < other) {
             parent[x] = (int32_t)x;
+            root = true;
         } else {
             parent[x] = other;
             mask[edge_id<MODE>(g, pos)] = 1;
             wsum += b >> 32;
             ++nfound;
+        }
+        } while (false);
+        const uint64_t rb = __ballot(root), lb = __ballot(live);
+        if (lane_id() == 0) {
+            rootbits[x >> 6] = rb;
+            livebits[x >> 6] = lb;
         }
     }
     // one set of counter atomics per workgroup (same-address atomics from
@@ -427,10 +444,10 @@ __global__ __launch_bounds__(kBlock) void k_jump(int32_t* __restrict__ parent, i
     if (__ballot(more) && lane_id() == 0) ctrl->jump_more = 1;
 }
 
-// Dense ids for the roots that still have edges: stable scan over the flags
-// (parent[x] == x && best[x] != MAX); root x gets label[x] = its rank.
+// Dense ids for the roots that still have edges: stable scan over the hook's
+// root bits; root x gets label[x] = its rank.
 __global__ __launch_bounds__(kBlock) void k_scan_roots(
-    const int32_t* __restrict__ parent, const uint64_t* __restrict__ best, int64_t nr,
+    const uint64_t* __restrict__ rootbits, int64_t nr,
     int32_t* __restrict__ label, uint64_t* status, Ctrl* ctrl, uint32_t ntiles) {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wave[kBlock / kWave];
@@ -442,10 +459,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_roots(
     uint32_t cnt = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        const int64_t x = wbase + k * kWave + lane;
-        bool f = false;
-        if (x < nr) f = parent[x] == (int32_t)x && best[x] != kKeyMax;
-        mk[k] = __ballot(f);
+        const int64_t x0 = wbase + k * kWave;          // a multiple of 64
+        mk[k] = x0 < nr ? rootbits[x0 >> 6] : 0;
         cnt += __popcll(mk[k]);
     }
     if (lane == 0) s_wave[wave] = cnt;
@@ -470,13 +485,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_roots(
 // label[x] for non-roots from their root; -1 for vertices without edges.
 // Also resets best_next[0, n_next) for the fused next-round minedge.
 __global__ __launch_bounds__(kBlock) void k_label(
-    const int32_t* __restrict__ parent, const uint64_t* __restrict__ best, int64_t nr,
+    const int32_t* __restrict__ parent, const uint64_t* __restrict__ livebits, int64_t nr,
     int32_t* __restrict__ label, uint64_t* __restrict__ best_next, const Ctrl* ctrl) {
     const int64_t nn = (int64_t)ctrl->n_next;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nr;
          x += (int64_t)gridDim.x * blockDim.x) {
         const int32_t p = parent[x];
-        if (best[x] == kKeyMax) label[x] = -1;
+        if (!((livebits[x >> 6] >> (x & 63)) & 1)) label[x] = -1;
         else if (p != (int32_t)x) label[x] = label[p];
         if (x < nn) best_next[x] = kKeyMax;
     }
@@ -1295,38 +1310,39 @@ void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, in
                            n, best, ctrl, hot, sh);
 }
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
-                 int32_t* parent, uint8_t* mask, Ctrl* ctrl, bool side_keys, hipStream_t s) {
+                 int32_t* parent, uint8_t* mask, uint64_t* rootbits, uint64_t* livebits,
+                 Ctrl* ctrl, bool side_keys, hipStream_t s) {
     int64_t hb = (nr + kHookBlock - 1) / kHookBlock;
     hb = hb < 1 ? 1 : (hb > 256 ? 256 : hb);
     const dim3 gr((unsigned)hb), bl(kHookBlock);
     if (side_keys) {
         switch (mode) {
-            case kOrig: hipLaunchKernelGGL((k_hook<kOrig, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
-            case kFull32: hipLaunchKernelGGL((k_hook<kFull32, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
-            case kFull16: hipLaunchKernelGGL((k_hook<kFull16, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
-            default: hipLaunchKernelGGL((k_hook<kCompact, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+            case kOrig: hipLaunchKernelGGL((k_hook<kOrig, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, rootbits, livebits, ctrl); break;
+            case kFull32: hipLaunchKernelGGL((k_hook<kFull32, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, rootbits, livebits, ctrl); break;
+            case kFull16: hipLaunchKernelGGL((k_hook<kFull16, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, rootbits, livebits, ctrl); break;
+            default: hipLaunchKernelGGL((k_hook<kCompact, true>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, rootbits, livebits, ctrl); break;
         }
         return;
     }
     switch (mode) {
-        case kOrig: hipLaunchKernelGGL((k_hook<kOrig, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
-        case kFull32: hipLaunchKernelGGL((k_hook<kFull32, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
-        case kFull16: hipLaunchKernelGGL((k_hook<kFull16, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
-        default: hipLaunchKernelGGL((k_hook<kCompact, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, ctrl); break;
+        case kOrig: hipLaunchKernelGGL((k_hook<kOrig, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, rootbits, livebits, ctrl); break;
+        case kFull32: hipLaunchKernelGGL((k_hook<kFull32, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, rootbits, livebits, ctrl); break;
+        case kFull16: hipLaunchKernelGGL((k_hook<kFull16, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, rootbits, livebits, ctrl); break;
+        default: hipLaunchKernelGGL((k_hook<kCompact, false>), gr, bl, 0, s, best, nr, g, cmap, parent, mask, rootbits, livebits, ctrl); break;
     }
 }
 void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s) {
     hipLaunchKernelGGL(k_jump, dim3(grid_for(nr)), dim3(kBlock), 0, s, parent, nr, iters, ctrl);
 }
-void launch_scan_roots(const int32_t* parent, const uint64_t* best, int64_t nr, int32_t* label,
+void launch_scan_roots(const uint64_t* rootbits, int64_t nr, int32_t* label,
                        uint64_t* status, Ctrl* ctrl, hipStream_t s) {
     const uint32_t nt = (uint32_t)((nr + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_scan_roots, dim3(nt), dim3(kBlock), 0, s, parent, best, nr, label,
+    hipLaunchKernelGGL(k_scan_roots, dim3(nt), dim3(kBlock), 0, s, rootbits, nr, label,
                        status, ctrl, nt);
 }
-void launch_label(const int32_t* parent, const uint64_t* best, int64_t nr, int32_t* label,
+void launch_label(const int32_t* parent, const uint64_t* livebits, int64_t nr, int32_t* label,
                   uint64_t* best_next, const Ctrl* ctrl, hipStream_t s) {
-    hipLaunchKernelGGL(k_label, dim3(grid_for(nr)), dim3(kBlock), 0, s, parent, best, nr, label,
+    hipLaunchKernelGGL(k_label, dim3(grid_for(nr)), dim3(kBlock), 0, s, parent, livebits, nr, label,
                        best_next, ctrl);
 }
 void launch_compose(const int32_t* cmap, int64_t nc, const int32_t* label, int32_t* out,

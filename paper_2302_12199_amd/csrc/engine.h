@@ -14,6 +14,8 @@ struct EngineBuffers {
     uint64_t* cbsum;      // compaction scan chunk sums
     uint64_t* best[2];    // lightest-edge keys, this round / next round
     int32_t* parent;
+    uint64_t* rootbits;   // the hook's root and live bits, one word per 64 vertices
+    uint64_t* livebits;
     int32_t* lab[2];      // per-round label arrays (alternating)
     int32_t* map[2];      // composed label maps (alternating)
     int32_t* orig[2];     // representative-tracking: input vertex of each round vertex

@@ -52,6 +52,8 @@ size_t engine_carve(char* ws, int64_t m, int64_t n, EngineBuffers* B, bool bucke
     b.cbsum = (uint64_t*)take(1024 * 8);
     for (int i = 0; i < 2; ++i) b.best[i] = (uint64_t*)take(nn * 8);
     b.parent = (int32_t*)take(nn * 4);
+    b.rootbits = (uint64_t*)take((nn / 64 + 1) * 8);
+    b.livebits = (uint64_t*)take((nn / 64 + 1) * 8);
     for (int i = 0; i < 2; ++i) b.lab[i] = (int32_t*)take(nn * 4);
     for (int i = 0; i < 2; ++i) b.map[i] = (int32_t*)take(nn * 4);
     for (int i = 0; i < 2; ++i) b.orig[i] = (int32_t*)take(nn * 4);
@@ -169,7 +171,8 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
     while (m_live > 0 || m_pending) {
         launch_scan_prep(B.status, 0, dc, 1, s);
         const int hh = prof_begin(K_HOOK, s);
-        launch_hook(mode, B.best[cur], nr, view, cmap, B.parent, mask, dc, side_keys, s);
+        launch_hook(mode, B.best[cur], nr, view, cmap, B.parent, mask, B.rootbits, B.livebits,
+                    dc, side_keys, s);
         prof_end(hh, s, 12.0 * nr);
         int32_t* lab = B.lab[labsel];
         for (int attempt = 0;; ++attempt) {
@@ -179,10 +182,10 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             const int64_t ntv = (nr + kTile - 1) / kTile;
             launch_scan_prep(B.status, ntv, dc, 0, s);
             h = prof_begin(K_SCAN_ROOTS, s);
-            launch_scan_roots(B.parent, B.best[cur], nr, lab, B.status, dc, s);
+            launch_scan_roots(B.rootbits, nr, lab, B.status, dc, s);
             prof_end(h, s, 12.0 * nr);
             h = prof_begin(K_LABEL, s);
-            launch_label(B.parent, B.best[cur], nr, lab, B.best[cur ^ 1], dc, s);
+            launch_label(B.parent, B.livebits, nr, lab, B.best[cur ^ 1], dc, s);
             prof_end(h, s, 16.0 * nr);
             HIP_TRY(hipGetLastError());
             if ((st = read_ctrl(dc, hc, s))) return st;

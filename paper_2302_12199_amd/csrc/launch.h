@@ -21,12 +21,15 @@ void launch_minedge_r0(const int32_t* u, const int32_t* v, const uint32_t* w, in
                        bool side_keys, hipStream_t s);
 // side_keys: best[] holds w << 32 | position << 1 | side, else w << 32 |
 // position (the form every kernel that fills best[] was given).
+// rootbits / livebits ((nr + 63) / 64 words each): bit x says whether x is a
+// root that found an edge / found an edge at all.
 void launch_hook(int mode, const uint64_t* best, int64_t nr, const View& g, const int32_t* cmap,
-                 int32_t* parent, uint8_t* mask, Ctrl* ctrl, bool side_keys, hipStream_t s);
+                 int32_t* parent, uint8_t* mask, uint64_t* rootbits, uint64_t* livebits,
+                 Ctrl* ctrl, bool side_keys, hipStream_t s);
 void launch_jump(int32_t* parent, int64_t nr, int iters, Ctrl* ctrl, hipStream_t s);
-void launch_scan_roots(const int32_t* parent, const uint64_t* best, int64_t nr, int32_t* label,
+void launch_scan_roots(const uint64_t* rootbits, int64_t nr, int32_t* label,
                        uint64_t* status, Ctrl* ctrl, hipStream_t s);
-void launch_label(const int32_t* parent, const uint64_t* best, int64_t nr, int32_t* label,
+void launch_label(const int32_t* parent, const uint64_t* livebits, int64_t nr, int32_t* label,
                   uint64_t* best_next, const Ctrl* ctrl, hipStream_t s);
 void launch_compose(const int32_t* cmap, int64_t nc, const int32_t* label, int32_t* out,
                     hipStream_t s);
