@@ -177,7 +177,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         int32_t* lab = B.lab[labsel];
         for (int attempt = 0;; ++attempt) {
             h = prof_begin(K_JUMP, s);
-            launch_jump(B.parent, nr, 32, dc, s);
+            launch_jump(B.parent, nr, 16, dc, s);
             prof_end(h, s, 12.0 * nr);
             const int64_t ntv = (nr + kTile - 1) / kTile;
             launch_scan_prep(B.status, ntv, dc, 0, s);

@@ -59,6 +59,12 @@ def test_closed_forms():
     v = ((u + 1) % k).astype(np.int32)
     mask, total, _ = gpu_msf(u, v, np.full(k, 9, np.uint32), k)     # cycle, equal weights
     assert mask[:-1].all() and mask[-1] == 0 and total == 9 * (k - 1)
+    # a path of 2^20 equal-weight edges, listed in order: every vertex but 0 picks
+    # its lower edge, so round 0 leaves one chain 2^20 deep for pointer jumping
+    k = 1 << 20
+    u = np.arange(k - 1, dtype=np.int32)
+    mask, total, st = gpu_msf(u, u + 1, np.full(k - 1, 3, np.uint32), k)
+    assert mask.all() and total == 3 * (k - 1) and st["rounds"] >= 1
     n = 60                                                           # K_n, equal weights
     pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
     u = np.array([p[0] for p in pairs], np.int32)
