@@ -514,12 +514,12 @@ __global__ __launch_bounds__(kBlock) void k_compose(const int32_t* __restrict__ 
 // compressed by pointer doubling at the end).  orig_cur[x] is the input
 // vertex that round vertex x stands for (null: identity).
 __global__ __launch_bounds__(kBlock) void k_rep_update(
-    const int32_t* __restrict__ parent, const uint64_t* __restrict__ best,
+    const int32_t* __restrict__ parent, const uint64_t* __restrict__ livebits,
     const int32_t* __restrict__ label, int64_t nr, const int32_t* __restrict__ orig_cur,
     int32_t* __restrict__ orig_next, int32_t* __restrict__ rep) {
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nr;
          x += (int64_t)gridDim.x * blockDim.x) {
-        if (best[x] == kKeyMax) continue;
+        if (!((livebits[x >> 6] >> (x & 63)) & 1)) continue;   // no edge
         const int32_t p = parent[x];
         const int32_t ox = orig_cur ? orig_cur[x] : (int32_t)x;
         if (p != (int32_t)x) rep[ox] = orig_cur ? orig_cur[p] : p;
@@ -1436,10 +1436,10 @@ void launch_hot_first_small(int mode, const View& g, const int32_t* cmap, int32_
     hipLaunchKernelGGL(k_apply_perm, dim3(grid_for(nr)), dim3(kBlock), 0, s, lab, nr, perm, nn);
 }
 
-void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_t* label,
+void launch_rep_update(const int32_t* parent, const uint64_t* livebits, const int32_t* label,
                        int64_t nr, const int32_t* orig_cur, int32_t* orig_next, int32_t* rep,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_rep_update, dim3(grid_for(nr)), dim3(kBlock), 0, s, parent, best, label,
+    hipLaunchKernelGGL(k_rep_update, dim3(grid_for(nr)), dim3(kBlock), 0, s, parent, livebits, label,
                        nr, orig_cur, orig_next, rep);
 }
 

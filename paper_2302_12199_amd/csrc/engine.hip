@@ -173,7 +173,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         const int hh = prof_begin(K_HOOK, s);
         launch_hook(mode, B.best[cur], nr, view, cmap, B.parent, mask, B.rootbits, B.livebits,
                     dc, side_keys, s);
-        prof_end(hh, s, 12.0 * nr);
+        prof_end(hh, s, 12.25 * nr);   // best[] in; parent[], root and live bits out
         int32_t* lab = B.lab[labsel];
         for (int attempt = 0;; ++attempt) {
             h = prof_begin(K_JUMP, s);
@@ -183,10 +183,10 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             launch_scan_prep(B.status, ntv, dc, 0, s);
             h = prof_begin(K_SCAN_ROOTS, s);
             launch_scan_roots(B.rootbits, nr, lab, B.status, dc, s);
-            prof_end(h, s, 12.0 * nr);
+            prof_end(h, s, 0.125 * nr);   // root bits in (+ a label per root)
             h = prof_begin(K_LABEL, s);
             launch_label(B.parent, B.livebits, nr, lab, B.best[cur ^ 1], dc, s);
-            prof_end(h, s, 16.0 * nr);
+            prof_end(h, s, 8.125 * nr);   // parent[] and live bits in, label[] out (+ best_next)
             HIP_TRY(hipGetLastError());
             if ((st = read_ctrl(dc, hc, s))) return st;
             if (!hc->jump_more) break;
@@ -233,7 +233,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
             launch_hot_first_small(mode, view, cmap, lab, nr, nn, B.perm, &dc->aux[2], s);
         else if (pre_tail_hot)   // every pair fits the LDS table
             launch_fill_u64(&dc->aux[2], 1, (uint64_t)nn, s);
-        prof_add(K_HOOK, 17.0 * live);
+        prof_add(K_HOOK, (side_keys ? 13.0 : 17.0) * live);   // other end(s), best[other], mask
         prof_add(K_SCAN_ROOTS, 4.0 * nn);
         prof_add(K_LABEL, 8.0 * nn);
         if (stats && rounds < MSF_MAX_TRACE) {
@@ -245,7 +245,7 @@ int engine_solve(EngineBuffers& B, int mode, const View& view0, int64_t nv, uint
         ++rounds;
 
         if (rep) {
-            launch_rep_update(B.parent, B.best[cur], lab, nr, rounds - 1 == first_round ? nullptr : B.orig[origsel],
+            launch_rep_update(B.parent, B.livebits, lab, nr, rounds - 1 == first_round ? nullptr : B.orig[origsel],
                               B.orig[origsel ^ 1], rep, s);
             origsel ^= 1;
         }

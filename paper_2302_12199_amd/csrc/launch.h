@@ -46,7 +46,7 @@ void launch_hot_first_small(int mode, const View& g, const int32_t* cmap, int32_
 void launch_tail(const uint64_t* pairs, int64_t nn, uint32_t* const list_xy[2],
                  uint64_t* const list_key[2], const uint32_t* view_id, uint8_t* mask,
                  const int32_t* orig_in, int32_t* rep, Ctrl* ctrl, hipStream_t s);
-void launch_rep_update(const int32_t* parent, const uint64_t* best, const int32_t* label,
+void launch_rep_update(const int32_t* parent, const uint64_t* livebits, const int32_t* label,
                        int64_t nr, const int32_t* orig_cur, int32_t* orig_next, int32_t* rep,
                        hipStream_t s);
 // dedup (DedupKind): kDedupLocal keeps only the lightest edge per vertex pair
