@@ -271,8 +271,8 @@ int msf_batched_graph_destroy(msf_batch_graph* graph);
 /*
  * Autotuner for the batched solver: a coordinate search from the defaults,
  * one option at a time in this order, keeping the fastest value of each:
- * block {512, 1024}, lds_vertices {1024, 2048, 4096, 8000}, coop_edges {2^19,
- * 2^20, never}, hot_min {4, 8, 16, off}, wave_min {2, 4, off}.  Each candidate runs the batch once on `stream`, timed
+ * block {512, 1024}, lds_vertices {1024, 2048, 4096, 8000}, coop_edges {2^18,
+ * 2^19, 2^20, 2^21, never}, hot_min {4, 8, 16, off}, wave_min {2, 4, off}.  Each candidate runs the batch once on `stream`, timed
  * with HIP events (after one warm-up run); the fastest options go to
  * *best_out (HOST) and its time to *best_ms_out (HOST, nullable).  Blocking.
  * Same array arguments as msf_compute_batched; the workspace must fit every

@@ -240,13 +240,13 @@ int msf_batched_autotune(const int32_t* u, const int32_t* v, const uint32_t* w,
     // 8000 vertices (160,000 B) still fit beside the kernel's static LDS in
     // one CU's 160 KiB; a 512-thread workgroup is alone on its CU anyway
     const int ldss[] = {1024, 2048, 4096, 8000};
-    const int coops[] = {1 << 19, 1 << 20, -1};
+    const int coops[] = {1 << 18, 1 << 19, 1 << 20, 1 << 21, -1};
     const int hots[] = {4, 8, 16, -1};
     const int wmins[] = {2, 4, -1};
     struct Axis { int32_t msf_batch_options::*field; const int* vals; int n; };
     const Axis axes[] = {{&msf_batch_options::block, blocks, 2},
                          {&msf_batch_options::lds_vertices, ldss, 4},
-                         {&msf_batch_options::coop_edges, coops, 3},
+                         {&msf_batch_options::coop_edges, coops, 5},
                          {&msf_batch_options::hot_min, hots, 4},
                          {&msf_batch_options::wave_min, wmins, 3}};
     for (const Axis& ax : axes) {
