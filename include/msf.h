@@ -232,7 +232,7 @@ int msf_compute_noalloc(const int32_t* u, const int32_t* v, const uint32_t* w, i
 typedef struct msf_batch_options {
     int32_t block;           /* threads per workgroup: 256, 512 or 1024; 0 = 512 */
     int32_t lds_vertices;    /* graphs with at most this many vertices keep their
-                                state in LDS (20 B per vertex); 0 = 4096, -1 = never */
+                                state in LDS (20 B per vertex); 0 = 8000, -1 = never */
     int32_t workgroups;      /* persistent workgroups; 0 = as many as can be resident */
     int32_t coop_edges;      /* graphs with at least this many edges are solved
                                 cooperatively per XCD; 0 = 2^20, -1 = never */
@@ -272,7 +272,7 @@ int msf_batched_graph_destroy(msf_batch_graph* graph);
  * Autotuner for the batched solver: a coordinate search from the defaults,
  * one option at a time in this order, keeping the fastest value of each:
  * block {512, 1024}, lds_vertices {1024, 2048, 4096, 8000}, coop_edges {2^18,
- * 2^19, 2^20, 2^21, never}, hot_min {4, 8, 16, off}, wave_min {2, 4, off}.  Each candidate runs the batch once on `stream`, timed
+ * 2^19, 2^20, never}, hot_min {4, 8, 16, off}, wave_min {2, 4, off}.  Each candidate runs the batch once on `stream`, timed
  * with HIP events (after one warm-up run); the fastest options go to
  * *best_out (HOST) and its time to *best_ms_out (HOST, nullable).  Blocking.
  * Same array arguments as msf_compute_batched; the workspace must fit every
