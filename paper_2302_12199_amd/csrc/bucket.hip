@@ -50,7 +50,7 @@ constexpr int kInFlight = 16;                                       // gathers p
 constexpr int kHotSample = 65535;                                   // edge ends sampled for hot labels
 constexpr uint32_t kHotIds = 10240;                                 // labels whose minima stay in LDS
 constexpr uint32_t kPassGrid = 256;   // workgroups of the pass: one per CU, tiles taken grid-stride
-constexpr uint32_t kScatterGrid = 512;                              // workgroups of the scatter
+constexpr uint32_t kScatterGrid = 1024;                             // workgroups of the scatter
 constexpr int kPassThreads = 1024;    // one pass workgroup per CU (LDS)
 constexpr int kPassParts = (int)(kBucketTile / 4 / kPassThreads / kGroups);   // edge parts per tile
 
